@@ -1,0 +1,183 @@
+/*
+ * rbm.h - C ABI of the MI355X (gfx950) rigid-body Stokes mobility library.
+ *
+ * The library solves the mobility problem of Corona, Greengard, Rachh and
+ * Veerapaneni, "An integral equation formulation for rigid bodies in Stokes flow
+ * in three dimensions" (arXiv 1606.07428): given body shapes, centroids,
+ * orientations, forces F_i and torques T_i (§1, mobility relation V = M F), it
+ * returns the translational and rotational velocities (v_i, omega_i), using the
+ * single-layer second-kind formulation of §2.3 (augmented operator 1/2 I + K + L)
+ * discretized with spherical harmonics (§3), the rotated-grid singular self
+ * quadrature (§3, §3.1) and right block-diagonal preconditioned GMRES (§3.2).
+ * Interactions between bodies are a direct all-pairs sum on the GPU.
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ *  - All real arrays are float64 and C-contiguous.  Host arrays are owned by the
+ *    caller; the library copies what it needs and writes outputs only into
+ *    caller buffers.
+ *  - The library allocates no device memory.  The caller queries the size with
+ *    rbm_workspace_size() and binds one device buffer (e.g. a PyTorch tensor) with
+ *    rbm_bind_workspace(); all device state lives there.  Work is issued on the
+ *    stream given in rbm_options (NULL = the default stream).
+ *  - Spherical harmonics: real orthonormal basis, index l*l + l + m,
+ *      Y_l0 = N_l0 P_l(cos t), Y_lm = sqrt2 N_lm P_l^m(cos t) cos(m f) (m > 0),
+ *      Y_l,-m = sqrt2 N_lm P_l^m(cos t) sin(m f), no Condon-Shortley phase
+ *    (the paper's Y_n^m with P_n^|m| of §3, made real).
+ *  - Grid (§3): p+1 Gauss-Legendre nodes in cos(theta) (ascending) times 2p
+ *    azimuths phi_k = pi k / p; node a = j*2p + k, M = 2p(p+1) nodes per body.
+ *    Density arrays are component-major [3][N], N = n*M, body i's node a at
+ *    column i*M + a, in the lab frame.
+ *  - Poses: the body frame is the shape's frame recentred at its area centroid;
+ *    quat = (w, x, y, z) rotates body to lab; centre = lab position of the area
+ *    centroid.  Torques are about that centroid.  F_i is the force the body exerts
+ *    on the fluid (traction integrates to -F_i), so an isolated sphere of radius a
+ *    moves with v = F/(6 pi eta a), omega = T/(8 pi eta a^3).
+ *  - Errors: every call returns an rbm_status; rbm_last_error() gives a
+ *    thread-local message.  No call throws across the ABI.  Calls on one context
+ *    are not thread safe; different contexts are independent.
+ */
+#ifndef RBM_H
+#define RBM_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct rbm_ctx rbm_ctx;
+
+typedef enum {
+  RBM_OK = 0,
+  RBM_E_INVAL = -1,   /* bad argument (sizes, NaN/Inf input, unknown shape id, ...) */
+  RBM_E_NOMEM = -2,   /* no workspace bound, or the bound one is too small */
+  RBM_E_DEVICE = -3,  /* a HIP runtime call failed */
+  RBM_E_NOCONV = -4,  /* GMRES hit max_iter before tol; outputs are still written */
+  RBM_E_STATE = -6    /* call out of order (e.g. solve before setup) */
+} rbm_status;
+
+typedef enum {
+  RBM_FP64 = 0,        /* everything in float64 */
+  RBM_MIXED_FP32 = 1,  /* GMRES-IR: fp32 far sum + fp32 preconditioner, fp64 residuals */
+  RBM_MIXED_BF16 = 2   /* GMRES-IR: fp32 far sum + bf16 preconditioner (fp32 accumulate) */
+} rbm_precision;
+
+typedef enum {
+  RBM_GUESS_ZERO = 0,       /* mu_0 = 0 */
+  RBM_GUESS_BLOCKDIAG = 1,  /* mu_0 = P^{-1} b, P = block-diagonal self operator (§3.2) */
+  RBM_GUESS_USER = 2        /* mu_0 taken from rbm_set_guess_dev() (e.g. a learned guess) */
+} rbm_guess;
+
+typedef struct {
+  int p;            /* SH order, 2 <= p <= 32; M = 2p(p+1) nodes per body */
+  int p_sing;       /* order of the rotated grid of the singular rule; 0 -> 2p; >= p+1 */
+  double eta;       /* viscosity (> 0) */
+  double tol;       /* stop when ||b - A mu||_2 <= tol ||b||_2 */
+  int max_iter;     /* Krylov dimension (iterations per GMRES cycle), 1..400 */
+  int max_restart;  /* extra GMRES cycles allowed after the first (>= 0) */
+  int precision;    /* rbm_precision */
+  int guess;        /* rbm_guess */
+  double inner_tol; /* GMRES-IR inner relative tolerance (0 -> 1e-4) */
+  void* stream;     /* hipStream_t or NULL */
+} rbm_options;
+
+typedef struct {
+  int iters;          /* total inner GMRES iterations */
+  int matvecs;        /* applications of the full operator (all precisions) */
+  int refinements;    /* GMRES-IR outer steps (0 for RBM_FP64) */
+  int cycles;         /* GMRES cycles (restarts + 1) */
+  double rel_residual;/* final ||b - A mu|| / ||b|| in float64 */
+  double bnorm;       /* ||b|| */
+  double ms_total;    /* wall time of the solve on the stream (ms) */
+  double ms_far;      /* time in the all-pairs sums (ms, event-timed) */
+  double ms_self;     /* time in the per-body operator applies (ms) */
+  double far_pairs;   /* off-body pair interactions evaluated */
+} rbm_solve_info;
+
+/* Default options: p = 8, p_sing = 0, eta = 1, tol = 1e-12, max_iter = 100,
+ * max_restart = 4, RBM_FP64, RBM_GUESS_BLOCKDIAG, inner_tol = 1e-4, stream NULL. */
+void rbm_default_options(rbm_options* opt);
+
+/* Create a context.  Validates opt; no device work. */
+rbm_status rbm_create(const rbm_options* opt, rbm_ctx** out);
+void rbm_destroy(rbm_ctx* ctx);
+
+/* Shapes as coordinate-function coefficients (§3, truncated SH expansion of x):
+ * coef[n_shapes][3][(lmax+1)^2] in the body frame, lmax <= p-1. */
+rbm_status rbm_set_shapes(rbm_ctx* ctx, int n_shapes, int lmax, const double* coef);
+
+/* Shapes as radial functions r(s) = sum rc_lm Y_lm(s), x = r(s) s:
+ * rc[n_shapes][(lmax+1)^2], lmax <= p-2 (x then has degree lmax+1 <= p-1 and is
+ * converted exactly to coordinate coefficients on the device). */
+rbm_status rbm_set_shapes_radial(rbm_ctx* ctx, int n_shapes, int lmax, const double* rc);
+
+/* Bodies: shape_id[n] in [0, n_shapes), centre[n][3] (lab area centroids),
+ * quat[n][4] (w,x,y,z; renormalised if | |q| - 1 | < 1e-6, else RBM_E_INVAL).
+ * n may change between calls as long as it stays <= the n the workspace was
+ * sized for. */
+rbm_status rbm_set_bodies(rbm_ctx* ctx, int n, const int* shape_id,
+                          const double* centre, const double* quat);
+
+/* Device bytes needed for n_bodies_max bodies and the shapes already set. */
+rbm_status rbm_workspace_size(rbm_ctx* ctx, int n_bodies_max, size_t* bytes);
+
+/* Bind a caller-owned device buffer of at least rbm_workspace_size() bytes
+ * (256-byte aligned).  Must precede rbm_setup(). */
+rbm_status rbm_bind_workspace(rbm_ctx* ctx, void* dptr, size_t bytes);
+
+/* Setup (Algorithm 1, first line; §3, §3.1): on the device, in float64, build per
+ * shape the grid geometry, area, centroid, tau (§2.2), the singular self
+ * operators, A0 = 1/2 I + K0 + L0, its inverse (the block preconditioner of §3.2)
+ * and the velocity functional.  Call once per shape set. */
+rbm_status rbm_setup(rbm_ctx* ctx);
+
+/* Solve the mobility problem for loads FT[n][6] = (F_i, T_i) (lab frame) and
+ * write VW[n][6] = (v_i, omega_i).  Host pointers.  info may be NULL. */
+rbm_status rbm_solve(rbm_ctx* ctx, const double* FT, double* VW, rbm_solve_info* info);
+
+/* Same with device pointers d_FT[n][6], d_VW[n][6] (no host copies of data; one
+ * scalar is read back per GMRES iteration for the stopping test). */
+rbm_status rbm_solve_dev(rbm_ctx* ctx, const double* d_FT, double* d_VW, rbm_solve_info* info);
+
+/* Initial density for RBM_GUESS_USER: d_mu0[3][N] device array, copied. */
+rbm_status rbm_set_guess_dev(rbm_ctx* ctx, const double* d_mu0);
+
+/* Copy out the last solve's densities ([3][N] host arrays; either may be NULL). */
+rbm_status rbm_get_density(rbm_ctx* ctx, double* mu, double* rho);
+
+/* Device pointers of internal arrays for inspection (valid until the workspace is
+ * rebound).  name: "X","N","W" ([3][N]/[N] lab nodes, normals, weights), "mu",
+ * "rho", "b" ([3][N]), "A0","P0" ([n_shapes][3M][3M] column-major body-frame
+ * operators), "V0" ([n_shapes][6][3M]), "geom" (per-shape r[3][M], n[3][M], w[M]),
+ * "shape" (per-shape area, xc[3], tau[9], tauinv[9]).  Returns NULL if unknown. */
+const void* rbm_debug_ptr(rbm_ctx* ctx, const char* name);
+
+/* Copy `bytes` bytes starting `offset` bytes into the internal array `name` (as for
+ * rbm_debug_ptr) to the host buffer dst (synchronous). */
+rbm_status rbm_debug_read(rbm_ctx* ctx, const char* name, size_t offset, size_t bytes, void* dst);
+
+/* Low-level kernels behind the solve, exposed for parity tests and benchmarks
+ * (all device pointers, on the context stream):
+ *
+ * rbm_far_traction: y[3][n_t] = add[3][n_t] (may be NULL) + sum over sources b
+ *   not on the target's body of -(3/4pi) d (d.N_a)(d.q_b)/|d|^5, d = X_a - X_b
+ *   (traction of the Stokeslet sum, §2.1, §3.1).  Targets X[3][n_t], N[3][n_t];
+ *   sources X[3][n_s] with strengths q[3][n_s]; body of point k is k / M.
+ *   precision 0 = float64, 1 = float32 arithmetic (inputs/outputs float64). */
+rbm_status rbm_far_traction(rbm_ctx* ctx, int n_points, int M, const double* X,
+                            const double* Nrm, const double* q, const double* add,
+                            double* y, int precision);
+
+/* rbm_far_stokeslet: u[3][n] = sum over sources b not on the target's body of
+ * (1/(8 pi eta)) [q_b/|d| + d (d.q_b)/|d|^3]  (Stokeslet of §2.1). */
+rbm_status rbm_far_stokeslet(rbm_ctx* ctx, int n_points, int M, const double* X,
+                             const double* q, double* u, int precision);
+
+const char* rbm_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RBM_H */

@@ -1,0 +1,102 @@
+// Launchers of the gfx950 kernels (host side).  Every launcher enqueues on `st`
+// and returns the hipError_t of the launch.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+namespace rbm {
+
+// ---- setup (k_setup.hip) ------------------------------------------------------
+hipError_t launch_gauss_legendre(int n, double* t, double* w, hipStream_t st);
+// grid tables: Y, dY/dtheta, (dY/dphi)/sin(theta) [(p+1)^2][M]; forward matrix F [nB][M];
+// transposed forward matrix Ft [M][nB]; node theta/phi/lambda [M].
+hipError_t launch_grid_tables(int p, const double* gl_t, const double* gl_w, double* Ytab,
+                              double* Yttab, double* Ypstab, double* Ftab, double* Fttab,
+                              double* node_th, double* node_ph, double* node_lam, hipStream_t st);
+// rotated grid of order ps: nodes [3][Ms] and singular weights [Ms]
+hipError_t launch_rotated_rule(int ps, const double* glt, const double* glw, double* nodes,
+                               double* W, hipStream_t st);
+hipError_t launch_radial_to_coef(int ns, int p, int nrc, const double* rc, const double* Ytab,
+                                 const double* Ftab, const double* node_th, const double* node_ph,
+                                 double* coef, hipStream_t st);
+hipError_t launch_shape_geometry(int ns, int p, const double* coef, const double* Ytab,
+                                 const double* Yttab, const double* Ypstab, const double* node_lam,
+                                 double* gx, double* gn, double* gw, double* gr, double* shp,
+                                 hipStream_t st);
+hipError_t launch_singular_assemble(int ns, int p, int ps, double eta, const double* coef,
+                                    const double* gx, const double* gn, const double* node_th,
+                                    const double* node_ph, const double* rnodes, const double* rW,
+                                    const double* Fttab, double* Sop, double* Kop, hipStream_t st);
+hipError_t launch_finish_A0(int ns, int M, const double* gr, const double* gw, double* A0,
+                            hipStream_t st);
+hipError_t launch_velocity_functional(int ns, int M, const double* Sop, const double* gr,
+                                      const double* gw, const double* shp, double* V0,
+                                      hipStream_t st);
+hipError_t launch_gauss_jordan(int ns, int n, double* A, int* piv, hipStream_t st);
+hipError_t launch_cast_f32(size_t n, const double* x, float* y, hipStream_t st);
+// bf16 stored as raw uint16 (upper half of the fp32 pattern, round to nearest even)
+hipError_t launch_cast_bf16(size_t n, const double* x, uint16_t* y, hipStream_t st);
+
+// ---- per-solve geometry and densities (k_solve.hip) ------------------------------
+hipError_t launch_body_prep(int n, const double* quat, const int* sid, const double* shp,
+                            double* Rm, double* tauinv_lab, double* area_b, hipStream_t st);
+hipError_t launch_nodes(int n, int M, const int* sid, const double* cen, const double* Rm,
+                        const double* gr, const double* gn, const double* gw, double* X,
+                        double* Nn, double* W, float* Xf, float* Nf, hipStream_t st);
+hipError_t launch_rho(int n, int M, const double* FT, const double* cen, const double* X,
+                      const double* tauinv_lab, const double* area_b, double* rho, hipStream_t st);
+// per-body moments of a lab field u[3][N]: out[i] = (sum w u, sum w (X-c) x u)
+hipError_t launch_moments(int n, int M, const double* u, const double* X, const double* W,
+                          const double* cen, double* mom, hipStream_t st);
+// out = a*x + b*y + L-like term: out_g += sign * (F_i + T_i x (X_g - c_i)) from mom
+hipError_t launch_add_rigid(int n, int M, const double* mom, const double* X, const double* cen,
+                            double sign, double* out, hipStream_t st);
+hipError_t launch_velocity_self(int n, int M, const int* sid, const double* V0, const double* Rm,
+                                const double* sig, double* vw_self, hipStream_t st);
+hipError_t launch_velocity_final(int n, const double* mom_far, const double* vw_self,
+                                 const double* tauinv_lab, const double* area_b, double* VW,
+                                 hipStream_t st);
+
+// ---- per-body operator apply (k_self.hip) ----------------------------------------
+// y_body[3][N] = A_{s(i)} (R_i^T x_lab) per body; A column-major [ns][3M][3M].
+template <typename TM>
+hipError_t launch_self_apply(int n, int M, const int* sid, const TM* A, const double* Rm,
+                             const double* x_lab, double* y_body, hipStream_t st);
+
+// ---- far field (k_far.hip) -------------------------------------------------------
+// Pack sources: (X_g, q_g) with q_g = W_g * (R_i z_body or z_lab)[g] into AoS of T.
+// If z_lab_out != nullptr the rotated z is also written (lab frame, float64).
+template <typename T>
+hipError_t launch_pack_sources(int N, int M, const double* X, const double* W, const double* Rm,
+                               const double* z, int z_is_body, double* z_lab_out, void* src,
+                               hipStream_t st);
+// kind 0 = traction (targets need normals), 1 = Stokeslet.  Writes nsplit partial sums
+// part[nsplit][3][N] (float64).  Returns the split used through *nsplit_out.
+template <typename T>
+hipError_t launch_far(int kind, int N, int M, const T* tx, const T* nrm, const void* src,
+                      double* part, int nsplit, hipStream_t st);
+// out[3][N] = ca * a[3][N] (optional) + cb * R_i b_body (optional) + cp * sum_s part[s]
+hipError_t launch_combine(int N, int M, int nsplit, const double* part, double cp,
+                          const double* a, double ca, const double* b_body, const double* Rm,
+                          double cb, double* out, hipStream_t st);
+
+// ---- Krylov (k_krylov.hip) --------------------------------------------------------
+hipError_t launch_dots(int kk, size_t len, const double* V, size_t ldv, const double* w,
+                       double* partial, int nblk, hipStream_t st);
+hipError_t launch_dots_final(int kk, int nblk, const double* partial, double* h, double* hacc,
+                             hipStream_t st);
+// w -= sum_j V[j] h[j]  (or w = sum_j V[j] h[j] if overwrite)
+hipError_t launch_vupdate(int kk, size_t len, const double* V, size_t ldv, const double* h,
+                          double* w, int overwrite, hipStream_t st);
+hipError_t launch_scale_copy(size_t len, const double* x, const double* s, int invert, double* y,
+                             hipStream_t st);
+hipError_t launch_axpby(size_t len, double a, const double* x, double b, const double* y,
+                        double* out, hipStream_t st);
+hipError_t launch_givens(int k, int ldh, double* H, double* cs, double* sn, double* g,
+                         const double* hcol, const double* hnext, double* resid, hipStream_t st);
+hipError_t launch_backsolve(int m, int ldh, const double* H, const double* g, double* y,
+                            hipStream_t st);
+hipError_t launch_dots_final_sqrt(int nblk, const double* partial, double* h, hipStream_t st);
+
+}  // namespace rbm

@@ -1,0 +1,713 @@
+// Host side of the C ABI declared in include/rbm.h: context, workspace layout,
+// setup, and the GMRES / GMRES-IR drivers that sequence the gfx950 kernels.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <type_traits>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/rbm.h"
+#include "kernels.h"
+
+using namespace rbm;
+
+static thread_local std::string g_err;
+
+static rbm_status fail(rbm_status s, const std::string& msg) {
+  g_err = msg;
+  return s;
+}
+
+#define HIPCHECK(expr)                                                              \
+  do {                                                                              \
+    hipError_t e_ = (expr);                                                         \
+    if (e_ != hipSuccess)                                                           \
+      return fail(RBM_E_DEVICE, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+struct rbm_ctx {
+  rbm_options opt;
+  int p = 0, ps = 0, M = 0, M3 = 0, nc = 0, nB = 0, Ms = 0;
+  hipStream_t st = nullptr;
+  // shapes (host copy until setup)
+  int ns = 0, shape_kind = -1, shape_lmax = 0, nsrc = 0;
+  std::vector<double> shape_data;
+  // bodies
+  int n = 0, nmax = 0;
+  std::vector<int> sid_h;
+  std::vector<double> cen_h, quat_h;
+  bool bodies_dirty = true;
+  // workspace
+  char* ws = nullptr;
+  size_t ws_bytes = 0;
+  bool setup_done = false, have_solution = false, guess_set = false;
+  int nsplit = 1, nblk = 256;
+  // tables
+  double *gl_t, *gl_w, *glr_t, *glr_w, *Ytab, *Yttab, *Ypstab, *Ftab, *Fttab, *nth, *nph, *nlam,
+      *rnodes, *rW;
+  // shapes
+  double *coef, *rcbuf, *gx, *gn, *gw, *gr, *shp, *A0, *P0, *V0;
+  float* P0f;
+  uint16_t* P0h;
+  int* piv;
+  // bodies and nodes
+  int* sid;
+  double *cen, *quat, *FT, *VW, *Rm, *tauinv, *area_b, *mom, *vws;
+  double *X, *Nn, *W;
+  float *Xf, *Nf;
+  // vectors
+  double *rho, *b, *mu, *r, *t1, *t2, *yb, *guess;
+  // Krylov
+  double *V, *H, *cs, *sn, *g, *y, *htmp, *scal, *partial;
+  // far field
+  void* src;
+  double* part;
+  double* pinned = nullptr;
+  // events for timing
+  std::vector<hipEvent_t> ev;
+  int ev_used = 0;
+  bool timing = true;
+};
+
+extern "C" void rbm_default_options(rbm_options* o) {
+  std::memset(o, 0, sizeof(*o));
+  o->p = 8;
+  o->p_sing = 0;
+  o->eta = 1.0;
+  o->tol = 1e-12;
+  o->max_iter = 100;
+  o->max_restart = 4;
+  o->precision = RBM_FP64;
+  o->guess = RBM_GUESS_BLOCKDIAG;
+  o->inner_tol = 1e-4;
+  o->stream = nullptr;
+}
+
+extern "C" const char* rbm_last_error(void) { return g_err.c_str(); }
+
+extern "C" rbm_status rbm_create(const rbm_options* opt, rbm_ctx** out) {
+  if (!opt || !out) return fail(RBM_E_INVAL, "null argument");
+  if (opt->p < 2 || opt->p > 20) return fail(RBM_E_INVAL, "p must be in [2, 20]");
+  const int ps = opt->p_sing ? opt->p_sing : 2 * opt->p;
+  if (ps < opt->p + 1 || ps > 64) return fail(RBM_E_INVAL, "p_sing must be in [p+1, 64]");
+  if (!(opt->eta > 0.0) || !std::isfinite(opt->eta)) return fail(RBM_E_INVAL, "eta must be > 0");
+  if (!(opt->tol > 0.0) || !std::isfinite(opt->tol)) return fail(RBM_E_INVAL, "tol must be > 0");
+  if (opt->max_iter < 1 || opt->max_iter > 400) return fail(RBM_E_INVAL, "max_iter in [1, 400]");
+  if (opt->max_restart < 0) return fail(RBM_E_INVAL, "max_restart >= 0");
+  if (opt->precision < 0 || opt->precision > 2) return fail(RBM_E_INVAL, "bad precision");
+  if (opt->guess < 0 || opt->guess > 2) return fail(RBM_E_INVAL, "bad guess");
+  rbm_ctx* c = new rbm_ctx();
+  c->opt = *opt;
+  if (!(c->opt.inner_tol > 0.0)) c->opt.inner_tol = 1e-4;
+  c->p = opt->p;
+  c->ps = ps;
+  c->M = (c->p + 1) * 2 * c->p;
+  c->M3 = 3 * c->M;
+  c->nc = (c->p + 1) * (c->p + 1);
+  c->nB = c->p * c->p + 2 * c->p;
+  c->Ms = (ps + 1) * 2 * ps;
+  c->st = (hipStream_t)opt->stream;
+  *out = c;
+  return RBM_OK;
+}
+
+extern "C" void rbm_destroy(rbm_ctx* c) {
+  if (!c) return;
+  for (auto e : c->ev) (void)hipEventDestroy(e);
+  if (c->pinned) (void)hipHostFree(c->pinned);
+  delete c;
+}
+
+static bool all_finite(const double* x, size_t n) {
+  for (size_t i = 0; i < n; ++i)
+    if (!std::isfinite(x[i])) return false;
+  return true;
+}
+
+extern "C" rbm_status rbm_set_shapes(rbm_ctx* c, int n_shapes, int lmax, const double* coef) {
+  if (!c || !coef) return fail(RBM_E_INVAL, "null argument");
+  if (n_shapes < 1) return fail(RBM_E_INVAL, "n_shapes must be >= 1");
+  if (lmax < 1 || lmax > c->p - 1) return fail(RBM_E_INVAL, "coordinate lmax must be in [1, p-1]");
+  const size_t k = (size_t)(lmax + 1) * (lmax + 1);
+  if (!all_finite(coef, (size_t)n_shapes * 3 * k)) return fail(RBM_E_INVAL, "non-finite coefficient");
+  c->shape_data.assign(coef, coef + (size_t)n_shapes * 3 * k);
+  c->ns = n_shapes;
+  c->shape_kind = 0;
+  c->shape_lmax = lmax;
+  c->setup_done = false;
+  return RBM_OK;
+}
+
+extern "C" rbm_status rbm_set_shapes_radial(rbm_ctx* c, int n_shapes, int lmax, const double* rc) {
+  if (!c || !rc) return fail(RBM_E_INVAL, "null argument");
+  if (n_shapes < 1) return fail(RBM_E_INVAL, "n_shapes must be >= 1");
+  if (lmax < 0 || lmax > c->p - 2) return fail(RBM_E_INVAL, "radial lmax must be in [0, p-2]");
+  const size_t k = (size_t)(lmax + 1) * (lmax + 1);
+  if (!all_finite(rc, (size_t)n_shapes * k)) return fail(RBM_E_INVAL, "non-finite coefficient");
+  c->shape_data.assign(rc, rc + (size_t)n_shapes * k);
+  c->ns = n_shapes;
+  c->shape_kind = 1;
+  c->shape_lmax = lmax;
+  c->setup_done = false;
+  return RBM_OK;
+}
+
+extern "C" rbm_status rbm_set_bodies(rbm_ctx* c, int n, const int* shape_id, const double* centre,
+                                     const double* quat) {
+  if (!c || !shape_id || !centre || !quat) return fail(RBM_E_INVAL, "null argument");
+  if (n < 1) return fail(RBM_E_INVAL, "n must be >= 1");
+  if (c->ns < 1) return fail(RBM_E_STATE, "set shapes first");
+  if (c->ws && n > c->nmax) return fail(RBM_E_NOMEM, "more bodies than the workspace holds");
+  if (!all_finite(centre, 3 * (size_t)n) || !all_finite(quat, 4 * (size_t)n))
+    return fail(RBM_E_INVAL, "non-finite centre or quaternion");
+  for (int i = 0; i < n; ++i) {
+    if (shape_id[i] < 0 || shape_id[i] >= c->ns) return fail(RBM_E_INVAL, "unknown shape id");
+    const double* q = quat + 4 * i;
+    const double nq = std::sqrt(q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3]);
+    if (std::fabs(nq - 1.0) > 1e-6) return fail(RBM_E_INVAL, "quaternion is not unit");
+  }
+  c->n = n;
+  c->sid_h.assign(shape_id, shape_id + n);
+  c->cen_h.assign(centre, centre + 3 * (size_t)n);
+  c->quat_h.assign(quat, quat + 4 * (size_t)n);
+  c->bodies_dirty = true;
+  c->have_solution = false;
+  return RBM_OK;
+}
+
+static int far_split(int N) {
+  const int nbx = (N + 511) / 512;
+  int s = (2048 + nbx - 1) / nbx;
+  if (s < 1) s = 1;
+  if (s > 64) s = 64;
+  if (s > (N + 255) / 256) s = (N + 255) / 256;
+  return s < 1 ? 1 : s;
+}
+
+// Split of the source range for N points, bounded by the partial-sum buffer.
+static int split_for(const rbm_ctx* c, int N) {
+  const size_t cap = (size_t)c->nsplit * c->nmax * c->M;
+  int s = far_split(N);
+  while (s > 1 && (size_t)s * N > cap) --s;
+  return s;
+}
+
+// Bump allocation over the bound workspace; with assign == false only sizes.
+static size_t layout(rbm_ctx* c, int nmax, bool assign) {
+  size_t off = 0;
+  auto take = [&](auto*& ptr, size_t count) {
+    using T = std::remove_reference_t<decltype(*ptr)>;
+    off = (off + 255) & ~(size_t)255;
+    if (assign) ptr = reinterpret_cast<T*>(c->ws + off);
+    off += count * sizeof(T);
+  };
+  const int p = c->p, ps = c->ps, M = c->M, M3 = c->M3, nc = c->nc, nB = c->nB, Ms = c->Ms;
+  const size_t ns = c->ns;
+  take(c->gl_t, p + 1); take(c->gl_w, p + 1); take(c->glr_t, ps + 1); take(c->glr_w, ps + 1);
+  take(c->Ytab, (size_t)nc * M); take(c->Yttab, (size_t)nc * M); take(c->Ypstab, (size_t)nc * M);
+  take(c->Ftab, (size_t)nB * M); take(c->Fttab, (size_t)nB * M);
+  take(c->nth, M); take(c->nph, M); take(c->nlam, M);
+  take(c->rnodes, 3 * (size_t)Ms); take(c->rW, Ms);
+  take(c->coef, ns * 3 * nc);
+  take(c->rcbuf, c->shape_data.size() + 1);
+  take(c->gx, ns * 3 * M); take(c->gn, ns * 3 * M); take(c->gr, ns * 3 * M); take(c->gw, ns * M);
+  take(c->shp, ns * 32);
+  take(c->A0, ns * M3 * M3); take(c->P0, ns * M3 * M3); take(c->V0, ns * 6 * M3);
+  take(c->piv, ns * M3);
+  if (c->opt.precision == RBM_MIXED_FP32) take(c->P0f, ns * M3 * M3); else if (assign) c->P0f = nullptr;
+  if (c->opt.precision == RBM_MIXED_BF16) take(c->P0h, ns * M3 * M3); else if (assign) c->P0h = nullptr;
+  const size_t nm = nmax, N = nm * M, N3 = 3 * N;
+  take(c->sid, nm); take(c->cen, 3 * nm); take(c->quat, 4 * nm); take(c->FT, 6 * nm);
+  take(c->VW, 6 * nm); take(c->Rm, 9 * nm); take(c->tauinv, 9 * nm); take(c->area_b, nm);
+  take(c->mom, 6 * nm); take(c->vws, 6 * nm);
+  take(c->X, N3); take(c->Nn, N3); take(c->W, N); take(c->Xf, N3); take(c->Nf, N3);
+  take(c->rho, N3); take(c->b, N3); take(c->mu, N3); take(c->r, N3); take(c->t1, N3);
+  take(c->t2, N3); take(c->yb, N3); take(c->guess, N3);
+  const int m = c->opt.max_iter;
+  take(c->V, (size_t)(m + 1) * N3); take(c->H, (size_t)(m + 1) * (m + 1)); take(c->cs, m + 1);
+  take(c->sn, m + 1); take(c->g, m + 2); take(c->y, m + 2); take(c->htmp, m + 2);
+  take(c->scal, 64);
+  take(c->partial, (size_t)(m + 2) * c->nblk);
+  double* srcd = nullptr;
+  take(srcd, 8 * N);
+  if (assign) c->src = srcd;
+  take(c->part, (size_t)far_split((int)N) * N3);
+  return off + 256;
+}
+
+extern "C" rbm_status rbm_workspace_size(rbm_ctx* c, int n_bodies_max, size_t* bytes) {
+  if (!c || !bytes) return fail(RBM_E_INVAL, "null argument");
+  if (c->ns < 1) return fail(RBM_E_STATE, "set shapes first");
+  if (n_bodies_max < 1) return fail(RBM_E_INVAL, "n_bodies_max >= 1");
+  if ((double)n_bodies_max * c->M > 2.0e9) return fail(RBM_E_INVAL, "too many points");
+  *bytes = layout(c, n_bodies_max, false);
+  return RBM_OK;
+}
+
+extern "C" rbm_status rbm_bind_workspace(rbm_ctx* c, void* dptr, size_t bytes) {
+  if (!c || !dptr) return fail(RBM_E_INVAL, "null argument");
+  if (c->ns < 1) return fail(RBM_E_STATE, "set shapes first");
+  if (((uintptr_t)dptr & 255) != 0) return fail(RBM_E_INVAL, "workspace must be 256-byte aligned");
+  // largest body count that fits
+  int lo = 0, hi = 1;
+  while (hi < (1 << 26) && layout(c, hi, false) <= bytes) { lo = hi; hi *= 2; }
+  while (hi - lo > 1) {
+    const int mid = lo + (hi - lo) / 2;
+    if (layout(c, mid, false) <= bytes) lo = mid; else hi = mid;
+  }
+  if (lo < 1) return fail(RBM_E_NOMEM, "workspace too small for one body");
+  if (c->n > lo) return fail(RBM_E_NOMEM, "workspace too small for the bodies already set");
+  c->ws = reinterpret_cast<char*>(dptr);
+  c->ws_bytes = bytes;
+  c->nmax = lo;
+  layout(c, lo, true);
+  c->nsplit = far_split(lo * c->M);
+  if (!c->pinned) HIPCHECK(hipHostMalloc((void**)&c->pinned, 64 * sizeof(double), 0));
+  c->setup_done = false;
+  c->bodies_dirty = true;
+  return RBM_OK;
+}
+
+extern "C" rbm_status rbm_setup(rbm_ctx* c) {
+  if (!c) return fail(RBM_E_INVAL, "null argument");
+  if (!c->ws) return fail(RBM_E_NOMEM, "bind a workspace first");
+  if (c->ns < 1) return fail(RBM_E_STATE, "set shapes first");
+  hipStream_t st = c->st;
+  const int p = c->p, M = c->M, M3 = c->M3;
+  HIPCHECK(launch_gauss_legendre(p + 1, c->gl_t, c->gl_w, st));
+  HIPCHECK(launch_gauss_legendre(c->ps + 1, c->glr_t, c->glr_w, st));
+  HIPCHECK(launch_grid_tables(p, c->gl_t, c->gl_w, c->Ytab, c->Yttab, c->Ypstab, c->Ftab, c->Fttab,
+                              c->nth, c->nph, c->nlam, st));
+  HIPCHECK(launch_rotated_rule(c->ps, c->glr_t, c->glr_w, c->rnodes, c->rW, st));
+  if (c->shape_kind == 1) {
+    const int nrc = (c->shape_lmax + 1) * (c->shape_lmax + 1);
+    HIPCHECK(hipMemcpyAsync(c->rcbuf, c->shape_data.data(), c->shape_data.size() * sizeof(double),
+                            hipMemcpyHostToDevice, st));
+    HIPCHECK(launch_radial_to_coef(c->ns, p, nrc, c->rcbuf, c->Ytab, c->Ftab, c->nth, c->nph,
+                                   c->coef, st));
+  } else {
+    std::vector<double> full((size_t)c->ns * 3 * c->nc, 0.0);
+    const int k = (c->shape_lmax + 1) * (c->shape_lmax + 1);
+    for (int s = 0; s < c->ns; ++s)
+      for (int d = 0; d < 3; ++d)
+        for (int i = 0; i < k; ++i)
+          full[((size_t)s * 3 + d) * c->nc + i] = c->shape_data[((size_t)s * 3 + d) * k + i];
+    HIPCHECK(hipMemcpyAsync(c->coef, full.data(), full.size() * sizeof(double),
+                            hipMemcpyHostToDevice, st));
+    HIPCHECK(hipStreamSynchronize(st));
+  }
+  HIPCHECK(launch_shape_geometry(c->ns, p, c->coef, c->Ytab, c->Yttab, c->Ypstab, c->nlam, c->gx,
+                                 c->gn, c->gw, c->gr, c->shp, st));
+  // S0 into the P0 buffer (temporary), K0 into A0
+  HIPCHECK(launch_singular_assemble(c->ns, p, c->ps, c->opt.eta, c->coef, c->gx, c->gn, c->nth,
+                                    c->nph, c->rnodes, c->rW, c->Fttab, c->P0, c->A0, st));
+  HIPCHECK(launch_finish_A0(c->ns, M, c->gr, c->gw, c->A0, st));
+  HIPCHECK(launch_velocity_functional(c->ns, M, c->P0, c->gr, c->gw, c->shp, c->V0, st));
+  HIPCHECK(hipMemcpyAsync(c->P0, c->A0, (size_t)c->ns * M3 * M3 * sizeof(double),
+                          hipMemcpyDeviceToDevice, st));
+  HIPCHECK(launch_gauss_jordan(c->ns, M3, c->P0, c->piv, st));
+  if (c->P0f) HIPCHECK(launch_cast_f32((size_t)c->ns * M3 * M3, c->P0, c->P0f, st));
+  if (c->P0h) HIPCHECK(launch_cast_bf16((size_t)c->ns * M3 * M3, c->P0, c->P0h, st));
+  HIPCHECK(hipStreamSynchronize(st));
+  c->setup_done = true;
+  c->bodies_dirty = true;
+  return RBM_OK;
+}
+
+// ---------------------------------------------------------------------------------
+// Solve
+
+static rbm_status upload_bodies(rbm_ctx* c) {
+  if (!c->bodies_dirty) return RBM_OK;
+  hipStream_t st = c->st;
+  const int n = c->n;
+  HIPCHECK(hipMemcpyAsync(c->sid, c->sid_h.data(), n * sizeof(int), hipMemcpyHostToDevice, st));
+  HIPCHECK(hipMemcpyAsync(c->cen, c->cen_h.data(), 3 * n * sizeof(double), hipMemcpyHostToDevice, st));
+  HIPCHECK(hipMemcpyAsync(c->quat, c->quat_h.data(), 4 * n * sizeof(double), hipMemcpyHostToDevice, st));
+  HIPCHECK(launch_body_prep(n, c->quat, c->sid, c->shp, c->Rm, c->tauinv, c->area_b, st));
+  HIPCHECK(launch_nodes(n, c->M, c->sid, c->cen, c->Rm, c->gr, c->gn, c->gw, c->X, c->Nn, c->W,
+                        c->Xf, c->Nf, st));
+  HIPCHECK(hipStreamSynchronize(st));
+  c->bodies_dirty = false;
+  return RBM_OK;
+}
+
+struct Timer {
+  rbm_ctx* c;
+  hipEvent_t a, b;
+  bool on;
+  Timer(rbm_ctx* cc) : c(cc), on(cc->timing) {
+    if (!on) return;
+    while ((int)c->ev.size() < c->ev_used + 2) {
+      hipEvent_t e;
+      if (hipEventCreate(&e) != hipSuccess) { on = false; return; }
+      c->ev.push_back(e);
+    }
+    a = c->ev[c->ev_used];
+    b = c->ev[c->ev_used + 1];
+    c->ev_used += 2;
+    (void)hipEventRecord(a, c->st);
+  }
+  void stop() { if (on) (void)hipEventRecord(b, c->st); }
+};
+
+struct SolveState {
+  std::vector<std::pair<int, int>> far_ev, self_ev;  // event index pairs
+  double far_pairs = 0.0;
+  int matvecs = 0;
+};
+
+// Far traction of x (lab [3][N] or body frame), precision prec: part sums in c->part.
+static rbm_status far_traction(rbm_ctx* c, SolveState& S, const double* x, int x_is_body,
+                               int prec) {
+  const int N = c->n * c->M;
+  const int nsp = split_for(c, N);
+  Timer t(c);
+  if (prec == 0) {
+    HIPCHECK(launch_pack_sources<double>(N, c->M, c->X, c->W, c->Rm, x, x_is_body, nullptr, c->src, c->st));
+    HIPCHECK(launch_far<double>(0, N, c->M, c->X, c->Nn, c->src, c->part, nsp, c->st));
+  } else {
+    HIPCHECK(launch_pack_sources<float>(N, c->M, c->X, c->W, c->Rm, x, x_is_body, nullptr, c->src, c->st));
+    HIPCHECK(launch_far<float>(0, N, c->M, c->Xf, c->Nf, c->src, c->part, nsp, c->st));
+  }
+  t.stop();
+  if (t.on) S.far_ev.push_back({c->ev_used - 2, c->ev_used - 1});
+  S.far_pairs += (double)N * N - (double)c->n * c->M * c->M;
+  return RBM_OK;
+}
+
+// y_body = A (R^T x) with A = A0 (which 0), P0 (which 1) in the given precision.
+static rbm_status self_apply(rbm_ctx* c, SolveState& S, int which, int prec, const double* x,
+                             double* ybody) {
+  Timer t(c);
+  if (which == 0 || prec == 0) {
+    HIPCHECK(launch_self_apply<double>(c->n, c->M, c->sid, which == 0 ? c->A0 : c->P0, c->Rm, x,
+                                       ybody, c->st));
+  } else if (prec == 1) {
+    HIPCHECK(launch_self_apply<float>(c->n, c->M, c->sid, c->P0f, c->Rm, x, ybody, c->st));
+  } else {
+    HIPCHECK(launch_self_apply<uint16_t>(c->n, c->M, c->sid, c->P0h, c->Rm, x, ybody, c->st));
+  }
+  t.stop();
+  if (t.on) S.self_ev.push_back({c->ev_used - 2, c->ev_used - 1});
+  return RBM_OK;
+}
+
+// out = A x = A_self x + K_far(w x)   (float64; A_self includes 1/2 I and L)
+static rbm_status apply_A(rbm_ctx* c, SolveState& S, const double* x, double* out) {
+  const int N = c->n * c->M;
+  rbm_status s;
+  if ((s = self_apply(c, S, 0, 0, x, c->yb)) != RBM_OK) return s;
+  if ((s = far_traction(c, S, x, 0, 0)) != RBM_OK) return s;
+  HIPCHECK(launch_combine(N, c->M, split_for(c, N), c->part, 1.0, nullptr, 0.0, c->yb, c->Rm, 1.0, out, c->st));
+  S.matvecs++;
+  return RBM_OK;
+}
+
+// out = v + K_far(w R P~^{-1} R^T v): the right-preconditioned operator A P^{-1}
+static rbm_status apply_AP(rbm_ctx* c, SolveState& S, int prec, const double* v, double* out) {
+  const int N = c->n * c->M;
+  rbm_status s;
+  if ((s = self_apply(c, S, 1, prec, v, c->yb)) != RBM_OK) return s;
+  if ((s = far_traction(c, S, c->yb, 1, prec == 0 ? 0 : 1)) != RBM_OK) return s;
+  HIPCHECK(launch_combine(N, c->M, split_for(c, N), c->part, 1.0, v, 1.0, nullptr, nullptr, 0.0, out, c->st));
+  S.matvecs++;
+  return RBM_OK;
+}
+
+static rbm_status dot_into(rbm_ctx* c, int kk, const double* Vb, size_t ldv, const double* w,
+                           double* h, double* hacc) {
+  const size_t len = 3 * (size_t)c->n * c->M;
+  HIPCHECK(launch_dots(kk, len, Vb, ldv, w, c->partial, c->nblk, c->st));
+  HIPCHECK(launch_dots_final(kk, c->nblk, c->partial, h, hacc, c->st));
+  return RBM_OK;
+}
+
+static rbm_status norm_into(rbm_ctx* c, const double* w, double* out) {
+  const size_t len = 3 * (size_t)c->n * c->M;
+  HIPCHECK(launch_dots(1, len, w, len, w, c->partial, c->nblk, c->st));
+  HIPCHECK(launch_dots_final_sqrt(c->nblk, c->partial, out, c->st));
+  return RBM_OK;
+}
+
+static rbm_status read_scalar(rbm_ctx* c, const double* d, double* h) {
+  HIPCHECK(hipMemcpyAsync(c->pinned, d, sizeof(double), hipMemcpyDeviceToHost, c->st));
+  HIPCHECK(hipStreamSynchronize(c->st));
+  *h = c->pinned[0];
+  return RBM_OK;
+}
+
+// One GMRES cycle on A delta = r (right preconditioned, CGS2), starting from 0, with
+// V_0 = r/||r||; stops when the residual estimate <= abs_tol or after max_iter.
+// On exit mu += P~^{-1} V y (lab frame).  prec: 0 fp64, 1 fp32, 2 bf16 operators.
+static rbm_status gmres_cycle(rbm_ctx* c, SolveState& S, int prec, const double* r, double rnorm,
+                              double abs_tol, int* iters) {
+  const size_t len = 3 * (size_t)c->n * c->M;
+  const int m = c->opt.max_iter;
+  const int ldh = m + 1;
+  const int N = c->n * c->M;
+  rbm_status s;
+  // g = (rnorm, 0, ...), V0 = r / rnorm
+  HIPCHECK(hipMemsetAsync(c->g, 0, (m + 2) * sizeof(double), c->st));
+  HIPCHECK(hipMemsetAsync(c->H, 0, (size_t)(m + 1) * (m + 1) * sizeof(double), c->st));
+  c->pinned[1] = rnorm;
+  HIPCHECK(hipMemcpyAsync(c->g, c->pinned + 1, sizeof(double), hipMemcpyHostToDevice, c->st));
+  HIPCHECK(launch_scale_copy(len, r, c->g, 1, c->V, c->st));
+  int k = 0;
+  for (k = 0; k < m; ++k) {
+    double* vk = c->V + (size_t)k * len;
+    double* w = c->V + (size_t)(k + 1) * len;
+    if ((s = apply_AP(c, S, prec, vk, w)) != RBM_OK) return s;
+    double* hcol = c->H + (size_t)k * ldh;
+    if ((s = dot_into(c, k + 1, c->V, len, w, hcol, nullptr)) != RBM_OK) return s;
+    HIPCHECK(launch_vupdate(k + 1, len, c->V, len, hcol, w, 0, c->st));
+    if ((s = dot_into(c, k + 1, c->V, len, w, c->htmp, hcol)) != RBM_OK) return s;
+    HIPCHECK(launch_vupdate(k + 1, len, c->V, len, c->htmp, w, 0, c->st));
+    if ((s = norm_into(c, w, hcol + k + 1)) != RBM_OK) return s;
+    HIPCHECK(launch_scale_copy(len, w, hcol + k + 1, 1, w, c->st));
+    HIPCHECK(launch_givens(k, ldh, c->H, c->cs, c->sn, c->g, nullptr, nullptr, c->scal, c->st));
+    double res;
+    if ((s = read_scalar(c, c->scal, &res)) != RBM_OK) return s;
+    if (!std::isfinite(res)) return fail(RBM_E_DEVICE, "non-finite GMRES residual");
+    if (res <= abs_tol) { ++k; break; }
+  }
+  if (k > m) k = m;
+  *iters = k;
+  HIPCHECK(launch_backsolve(k, ldh, c->H, c->g, c->y, c->st));
+  HIPCHECK(launch_vupdate(k, len, c->V, len, c->y, c->t2, 1, c->st));
+  if ((s = self_apply(c, S, 1, prec, c->t2, c->yb)) != RBM_OK) return s;
+  HIPCHECK(launch_combine(N, c->M, 0, nullptr, 0.0, c->mu, 1.0, c->yb, c->Rm, 1.0, c->mu, c->st));
+  return RBM_OK;
+}
+
+static rbm_status solve_impl(rbm_ctx* c, const double* dFT, double* dVW, rbm_solve_info* info) {
+  if (!c->ws) return fail(RBM_E_NOMEM, "bind a workspace first");
+  if (!c->setup_done) return fail(RBM_E_STATE, "call rbm_setup first");
+  if (c->n < 1) return fail(RBM_E_STATE, "set bodies first");
+  rbm_status s;
+  if ((s = upload_bodies(c)) != RBM_OK) return s;
+  hipStream_t st = c->st;
+  const int n = c->n, M = c->M, N = n * M;
+  const size_t len = 3 * (size_t)N;
+  SolveState S;
+  c->ev_used = 0;
+  Timer total(c);
+  // incident density and right-hand side b = -(A_self rho - L rho + K_far rho)
+  HIPCHECK(launch_rho(n, M, dFT, c->cen, c->X, c->tauinv, c->area_b, c->rho, st));
+  if ((s = self_apply(c, S, 0, 0, c->rho, c->yb)) != RBM_OK) return s;
+  if ((s = far_traction(c, S, c->rho, 0, 0)) != RBM_OK) return s;
+  HIPCHECK(launch_combine(N, M, split_for(c, N), c->part, -1.0, nullptr, 0.0, c->yb, c->Rm, -1.0, c->b, st));
+  HIPCHECK(launch_moments(n, M, c->rho, c->X, c->W, c->cen, c->mom, st));
+  HIPCHECK(launch_add_rigid(n, M, c->mom, c->X, c->cen, 1.0, c->b, st));
+  S.matvecs++;
+  double bnorm;
+  if ((s = norm_into(c, c->b, c->scal + 1)) != RBM_OK) return s;
+  if ((s = read_scalar(c, c->scal + 1, &bnorm)) != RBM_OK) return s;
+  if (!std::isfinite(bnorm)) return fail(RBM_E_INVAL, "non-finite right-hand side");
+  const double abs_tol = c->opt.tol * bnorm;
+  const int prec = c->opt.precision;
+  // initial guess
+  bool mu_zero = false;
+  if (bnorm == 0.0 || c->opt.guess == RBM_GUESS_ZERO) {
+    HIPCHECK(hipMemsetAsync(c->mu, 0, len * sizeof(double), st));
+    mu_zero = true;
+  } else if (c->opt.guess == RBM_GUESS_BLOCKDIAG) {
+    if ((s = self_apply(c, S, 1, prec, c->b, c->yb)) != RBM_OK) return s;
+    HIPCHECK(launch_combine(N, M, 0, nullptr, 0.0, nullptr, 0.0, c->yb, c->Rm, 1.0, c->mu, st));
+  } else {
+    if (!c->guess_set) return fail(RBM_E_STATE, "RBM_GUESS_USER needs rbm_set_guess_dev");
+    HIPCHECK(hipMemcpyAsync(c->mu, c->guess, len * sizeof(double), hipMemcpyDeviceToDevice, st));
+  }
+  int total_iters = 0, cycles = 0, refinements = 0;
+  double rel = 0.0;
+  bool converged = false;
+  const int max_outer = prec == 0 ? c->opt.max_restart + 1 : 50;
+  for (int outer = 0; outer <= max_outer; ++outer) {
+    // float64 residual r = b - A mu
+    double rn;
+    if (mu_zero) {
+      HIPCHECK(hipMemcpyAsync(c->r, c->b, len * sizeof(double), hipMemcpyDeviceToDevice, st));
+      rn = bnorm;
+      mu_zero = false;
+    } else {
+      if ((s = apply_A(c, S, c->mu, c->t1)) != RBM_OK) return s;
+      HIPCHECK(launch_axpby(len, 1.0, c->b, -1.0, c->t1, c->r, st));
+      if ((s = norm_into(c, c->r, c->scal + 2)) != RBM_OK) return s;
+      if ((s = read_scalar(c, c->scal + 2, &rn)) != RBM_OK) return s;
+    }
+    rel = bnorm > 0.0 ? rn / bnorm : 0.0;
+    if (rn <= abs_tol || bnorm == 0.0) { converged = true; break; }
+    if (outer == max_outer) break;
+    const double inner_abs = prec == 0 ? abs_tol : std::max(c->opt.inner_tol * rn, 0.5 * abs_tol);
+    int it = 0;
+    if ((s = gmres_cycle(c, S, prec, c->r, rn, inner_abs, &it)) != RBM_OK) return s;
+    total_iters += it;
+    cycles++;
+    if (prec != 0) refinements++;
+  }
+  // velocities u = S[rho + mu]: far Stokeslet sum + self functional, float64
+  HIPCHECK(launch_axpby(len, 1.0, c->rho, 1.0, c->mu, c->t2, st));
+  {
+    Timer t(c);
+    HIPCHECK(launch_pack_sources<double>(N, M, c->X, c->W, c->Rm, c->t2, 0, nullptr, c->src, st));
+    HIPCHECK(launch_far<double>(1, N, M, c->X, nullptr, c->src, c->part, split_for(c, N), st));
+    t.stop();
+    if (t.on) S.far_ev.push_back({c->ev_used - 2, c->ev_used - 1});
+    S.far_pairs += (double)N * N - (double)n * M * M;
+  }
+  HIPCHECK(launch_combine(N, M, split_for(c, N), c->part, 1.0 / c->opt.eta, nullptr, 0.0, nullptr, nullptr,
+                          0.0, c->t1, st));
+  HIPCHECK(launch_moments(n, M, c->t1, c->X, c->W, c->cen, c->mom, st));
+  HIPCHECK(launch_velocity_self(n, M, c->sid, c->V0, c->Rm, c->t2, c->vws, st));
+  HIPCHECK(launch_velocity_final(n, c->mom, c->vws, c->tauinv, c->area_b, dVW, st));
+  total.stop();
+  HIPCHECK(hipStreamSynchronize(st));
+  c->have_solution = true;
+  if (info) {
+    std::memset(info, 0, sizeof(*info));
+    info->iters = total_iters;
+    info->matvecs = S.matvecs;
+    info->refinements = refinements;
+    info->cycles = cycles;
+    info->rel_residual = rel;
+    info->bnorm = bnorm;
+    info->far_pairs = S.far_pairs;
+    if (total.on) {
+      float ms = 0;
+      (void)hipEventElapsedTime(&ms, total.a, total.b);
+      info->ms_total = ms;
+      for (auto& e : S.far_ev) {
+        (void)hipEventElapsedTime(&ms, c->ev[e.first], c->ev[e.second]);
+        info->ms_far += ms;
+      }
+      for (auto& e : S.self_ev) {
+        (void)hipEventElapsedTime(&ms, c->ev[e.first], c->ev[e.second]);
+        info->ms_self += ms;
+      }
+    }
+  }
+  if (!converged) return fail(RBM_E_NOCONV, "GMRES did not reach tol");
+  return RBM_OK;
+}
+
+extern "C" rbm_status rbm_solve_dev(rbm_ctx* c, const double* d_FT, double* d_VW,
+                                    rbm_solve_info* info) {
+  if (!c || !d_FT || !d_VW) return fail(RBM_E_INVAL, "null argument");
+  return solve_impl(c, d_FT, d_VW, info);
+}
+
+extern "C" rbm_status rbm_solve(rbm_ctx* c, const double* FT, double* VW, rbm_solve_info* info) {
+  if (!c || !FT || !VW) return fail(RBM_E_INVAL, "null argument");
+  if (!c->ws) return fail(RBM_E_NOMEM, "bind a workspace first");
+  if (!all_finite(FT, 6 * (size_t)c->n)) return fail(RBM_E_INVAL, "non-finite load");
+  HIPCHECK(hipMemcpyAsync(c->FT, FT, 6 * c->n * sizeof(double), hipMemcpyHostToDevice, c->st));
+  rbm_status s = solve_impl(c, c->FT, c->VW, info);
+  if (s != RBM_OK && s != RBM_E_NOCONV) return s;
+  HIPCHECK(hipMemcpyAsync(VW, c->VW, 6 * c->n * sizeof(double), hipMemcpyDeviceToHost, c->st));
+  HIPCHECK(hipStreamSynchronize(c->st));
+  return s;
+}
+
+extern "C" rbm_status rbm_set_guess_dev(rbm_ctx* c, const double* d_mu0) {
+  if (!c || !d_mu0) return fail(RBM_E_INVAL, "null argument");
+  if (!c->ws) return fail(RBM_E_NOMEM, "bind a workspace first");
+  const size_t len = 3 * (size_t)c->n * c->M;
+  HIPCHECK(hipMemcpyAsync(c->guess, d_mu0, len * sizeof(double), hipMemcpyDeviceToDevice, c->st));
+  HIPCHECK(hipStreamSynchronize(c->st));
+  c->guess_set = true;
+  return RBM_OK;
+}
+
+extern "C" rbm_status rbm_get_density(rbm_ctx* c, double* mu, double* rho) {
+  if (!c) return fail(RBM_E_INVAL, "null argument");
+  if (!c->have_solution) return fail(RBM_E_STATE, "no solution yet");
+  const size_t len = 3 * (size_t)c->n * c->M;
+  if (mu) HIPCHECK(hipMemcpy(mu, c->mu, len * sizeof(double), hipMemcpyDeviceToHost));
+  if (rho) HIPCHECK(hipMemcpy(rho, c->rho, len * sizeof(double), hipMemcpyDeviceToHost));
+  return RBM_OK;
+}
+
+extern "C" const void* rbm_debug_ptr(rbm_ctx* c, const char* name) {
+  if (!c || !name || !c->ws) return nullptr;
+  const std::string s(name);
+  if (s == "X") return c->X;
+  if (s == "N") return c->Nn;
+  if (s == "W") return c->W;
+  if (s == "mu") return c->mu;
+  if (s == "rho") return c->rho;
+  if (s == "b") return c->b;
+  if (s == "A0") return c->A0;
+  if (s == "P0") return c->P0;
+  if (s == "V0") return c->V0;
+  if (s == "coef") return c->coef;
+  if (s == "gr") return c->gr;
+  if (s == "gn") return c->gn;
+  if (s == "gw") return c->gw;
+  if (s == "gx") return c->gx;
+  if (s == "shape") return c->shp;
+  if (s == "Rm") return c->Rm;
+  if (s == "Ftab") return c->Ftab;
+  if (s == "Ytab") return c->Ytab;
+  return nullptr;
+}
+
+extern "C" rbm_status rbm_far_traction(rbm_ctx* c, int n_points, int M, const double* X,
+                                       const double* Nrm, const double* q, const double* add,
+                                       double* y, int precision) {
+  if (!c || !X || !Nrm || !q || !y) return fail(RBM_E_INVAL, "null argument");
+  if (!c->ws) return fail(RBM_E_NOMEM, "bind a workspace first");
+  if (n_points < 1 || M < 1) return fail(RBM_E_INVAL, "sizes must be >= 1");
+  if (n_points > c->nmax * c->M) return fail(RBM_E_NOMEM, "more points than the workspace holds");
+  const int nsplit = split_for(c, n_points);
+  hipStream_t st = c->st;
+  const size_t N3 = 3 * (size_t)n_points;
+  if (precision == 0) {
+    HIPCHECK(launch_pack_sources<double>(n_points, M, X, nullptr, nullptr, q, 0, nullptr, c->src, st));
+    HIPCHECK(launch_far<double>(0, n_points, M, X, Nrm, c->src, c->part, nsplit, st));
+  } else {
+    HIPCHECK(launch_cast_f32(N3, X, c->Xf, st));
+    HIPCHECK(launch_cast_f32(N3, Nrm, c->Nf, st));
+    HIPCHECK(launch_pack_sources<float>(n_points, M, X, nullptr, nullptr, q, 0, nullptr, c->src, st));
+    HIPCHECK(launch_far<float>(0, n_points, M, c->Xf, c->Nf, c->src, c->part, nsplit, st));
+  }
+  HIPCHECK(launch_combine(n_points, M, nsplit, c->part, 1.0, add, 1.0, nullptr, nullptr, 0.0, y, st));
+  c->bodies_dirty = true;  // Xf/Nf were overwritten
+  return RBM_OK;
+}
+
+extern "C" rbm_status rbm_far_stokeslet(rbm_ctx* c, int n_points, int M, const double* X,
+                                        const double* q, double* u, int precision) {
+  if (!c || !X || !q || !u) return fail(RBM_E_INVAL, "null argument");
+  if (!c->ws) return fail(RBM_E_NOMEM, "bind a workspace first");
+  if (n_points < 1 || M < 1) return fail(RBM_E_INVAL, "sizes must be >= 1");
+  if (n_points > c->nmax * c->M) return fail(RBM_E_NOMEM, "more points than the workspace holds");
+  const int nsplit = split_for(c, n_points);
+  hipStream_t st = c->st;
+  const size_t N3 = 3 * (size_t)n_points;
+  if (precision == 0) {
+    HIPCHECK(launch_pack_sources<double>(n_points, M, X, nullptr, nullptr, q, 0, nullptr, c->src, st));
+    HIPCHECK(launch_far<double>(1, n_points, M, X, nullptr, c->src, c->part, nsplit, st));
+  } else {
+    HIPCHECK(launch_cast_f32(N3, X, c->Xf, st));
+    HIPCHECK(launch_pack_sources<float>(n_points, M, X, nullptr, nullptr, q, 0, nullptr, c->src, st));
+    HIPCHECK(launch_far<float>(1, n_points, M, c->Xf, nullptr, c->src, c->part, nsplit, st));
+  }
+  HIPCHECK(launch_combine(n_points, M, nsplit, c->part, 1.0 / c->opt.eta, nullptr, 0.0, nullptr,
+                          nullptr, 0.0, u, st));
+  c->bodies_dirty = true;
+  return RBM_OK;
+}
+
+extern "C" rbm_status rbm_debug_read(rbm_ctx* c, const char* name, size_t offset, size_t bytes,
+                                     void* dst) {
+  if (!c || !name || !dst) return fail(RBM_E_INVAL, "null argument");
+  const void* p = rbm_debug_ptr(c, name);
+  if (!p) return fail(RBM_E_INVAL, "unknown array name");
+  HIPCHECK(hipStreamSynchronize(c->st));
+  HIPCHECK(hipMemcpy(dst, (const char*)p + offset, bytes, hipMemcpyDeviceToHost));
+  return RBM_OK;
+}

@@ -1,0 +1,243 @@
+"""Thin ctypes binding of librbm.so (C ABI in include/rbm.h).
+
+Argument marshalling only: every step of the method runs in the HIP library.
+PyTorch provides the device workspace and the stream.  ``load()`` raises if the
+library has not been built; nothing here falls back to a CPU path.
+"""
+import ctypes
+import math
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "librbm.so")
+
+RBM_OK, RBM_E_INVAL, RBM_E_NOMEM, RBM_E_DEVICE, RBM_E_NOCONV, RBM_E_STATE = 0, -1, -2, -3, -4, -6
+FP64, MIXED_FP32, MIXED_BF16 = 0, 1, 2
+GUESS_ZERO, GUESS_BLOCKDIAG, GUESS_USER = 0, 1, 2
+
+EXPORTED = [
+    "rbm_default_options", "rbm_create", "rbm_destroy", "rbm_set_shapes", "rbm_set_shapes_radial",
+    "rbm_set_bodies", "rbm_workspace_size", "rbm_bind_workspace", "rbm_setup", "rbm_solve",
+    "rbm_solve_dev", "rbm_set_guess_dev", "rbm_get_density", "rbm_debug_ptr", "rbm_debug_read",
+    "rbm_far_traction", "rbm_far_stokeslet", "rbm_last_error",
+]
+
+
+class Options(ctypes.Structure):
+    _fields_ = [("p", ctypes.c_int), ("p_sing", ctypes.c_int), ("eta", ctypes.c_double),
+                ("tol", ctypes.c_double), ("max_iter", ctypes.c_int), ("max_restart", ctypes.c_int),
+                ("precision", ctypes.c_int), ("guess", ctypes.c_int), ("inner_tol", ctypes.c_double),
+                ("stream", ctypes.c_void_p)]
+
+
+class SolveInfo(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int), ("matvecs", ctypes.c_int), ("refinements", ctypes.c_int),
+                ("cycles", ctypes.c_int), ("rel_residual", ctypes.c_double), ("bnorm", ctypes.c_double),
+                ("ms_total", ctypes.c_double), ("ms_far", ctypes.c_double), ("ms_self", ctypes.c_double),
+                ("far_pairs", ctypes.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+_LIB = None
+
+
+def load():
+    global _LIB
+    if _LIB is not None:
+        return _LIB
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with __graft_entry__.build()")
+    lib = ctypes.CDLL(LIB_PATH)
+    P, I, D, S = ctypes.c_void_p, ctypes.c_int, ctypes.c_double, ctypes.c_size_t
+    sig = {
+        "rbm_default_options": (None, [P]),
+        "rbm_create": (I, [P, P]),
+        "rbm_destroy": (None, [P]),
+        "rbm_set_shapes": (I, [P, I, I, P]),
+        "rbm_set_shapes_radial": (I, [P, I, I, P]),
+        "rbm_set_bodies": (I, [P, I, P, P, P]),
+        "rbm_workspace_size": (I, [P, I, P]),
+        "rbm_bind_workspace": (I, [P, P, S]),
+        "rbm_setup": (I, [P]),
+        "rbm_solve": (I, [P, P, P, P]),
+        "rbm_solve_dev": (I, [P, P, P, P]),
+        "rbm_set_guess_dev": (I, [P, P]),
+        "rbm_get_density": (I, [P, P, P]),
+        "rbm_debug_ptr": (P, [P, ctypes.c_char_p]),
+        "rbm_debug_read": (I, [P, ctypes.c_char_p, S, S, P]),
+        "rbm_far_traction": (I, [P, I, I, P, P, P, P, P, I]),
+        "rbm_far_stokeslet": (I, [P, I, I, P, P, P, I]),
+        "rbm_last_error": (ctypes.c_char_p, []),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    _LIB = lib
+    return lib
+
+
+class RbmError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"rbm status {status}: {msg}")
+        self.status = status
+
+
+def _check(status, allow=()):
+    if status != RBM_OK and status not in allow:
+        raise RbmError(status, load().rbm_last_error().decode())
+    return status
+
+
+def _ptr(a):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _f64(a, shape=None):
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    if shape is not None:
+        a = a.reshape(shape)
+    return a
+
+
+class Solver:
+    """One library context: shapes, bodies, a PyTorch-owned workspace and a stream."""
+
+    def __init__(self, p, shapes, shape_id, centres, quats, eta=1.0, p_sing=0, tol=1e-12,
+                 max_iter=100, max_restart=4, precision=FP64, guess=GUESS_BLOCKDIAG,
+                 inner_tol=1e-4, n_max=None, stream=None, device="cuda"):
+        import torch
+        lib = load()
+        self.torch = torch
+        self.device = torch.device(device)
+        opt = Options()
+        lib.rbm_default_options(ctypes.byref(opt))
+        opt.p, opt.p_sing, opt.eta, opt.tol = p, p_sing, eta, tol
+        opt.max_iter, opt.max_restart, opt.precision, opt.guess = max_iter, max_restart, precision, guess
+        opt.inner_tol = inner_tol
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        opt.stream = ctypes.c_void_p(self.stream.cuda_stream)
+        self.opt = opt
+        ctx = ctypes.c_void_p()
+        _check(lib.rbm_create(ctypes.byref(opt), ctypes.byref(ctx)))
+        self.ctx = ctx
+        self.p = p
+        self.M = 2 * p * (p + 1)
+        self.set_shapes(shapes)
+        self.set_bodies(shape_id, centres, quats)
+        n_max = self.n if n_max is None else n_max
+        nbytes = ctypes.c_size_t()
+        _check(lib.rbm_workspace_size(self.ctx, int(n_max), ctypes.byref(nbytes)))
+        self.ws = torch.empty(nbytes.value, dtype=torch.uint8, device=self.device)
+        _check(lib.rbm_bind_workspace(self.ctx, ctypes.c_void_p(self.ws.data_ptr()), nbytes.value))
+        self.workspace_bytes = nbytes.value
+        _check(lib.rbm_setup(self.ctx))
+
+    # -- inputs -------------------------------------------------------------------
+    def set_shapes(self, shapes):
+        lib = load()
+        kinds = {k for k, _ in shapes}
+        if len(kinds) != 1:
+            raise ValueError("all shapes must use one encoding")
+        kind = kinds.pop()
+        if kind == "radial":
+            L = max(int(round(math.sqrt(len(d)))) - 1 for _, d in shapes)
+            arr = np.zeros((len(shapes), (L + 1) ** 2))
+            for i, (_, d) in enumerate(shapes):
+                arr[i, :len(d)] = d
+            _check(lib.rbm_set_shapes_radial(self.ctx, len(shapes), L, _ptr(arr)))
+        else:
+            L = max(int(round(math.sqrt(np.asarray(d).shape[1]))) - 1 for _, d in shapes)
+            arr = np.zeros((len(shapes), 3, (L + 1) ** 2))
+            for i, (_, d) in enumerate(shapes):
+                d = np.asarray(d)
+                arr[i, :, :d.shape[1]] = d
+            _check(lib.rbm_set_shapes(self.ctx, len(shapes), L, _ptr(arr)))
+        self._shape_arr = arr
+        self.n_shapes = len(shapes)
+
+    def set_bodies(self, shape_id, centres, quats):
+        lib = load()
+        sid = np.ascontiguousarray(shape_id, dtype=np.int32)
+        cen = _f64(centres, (-1, 3))
+        q = _f64(quats, (-1, 4))
+        q = q / np.linalg.norm(q, axis=1)[:, None]
+        _check(lib.rbm_set_bodies(self.ctx, len(sid), _ptr(sid), _ptr(cen), _ptr(q)))
+        self.n = len(sid)
+        self.N = self.n * self.M
+
+    # -- solves -------------------------------------------------------------------
+    def solve(self, FT):
+        lib = load()
+        FT = _f64(FT, (self.n, 6))
+        VW = np.zeros((self.n, 6))
+        info = SolveInfo()
+        st = _check(lib.rbm_solve(self.ctx, _ptr(FT), _ptr(VW), ctypes.byref(info)), allow=(RBM_E_NOCONV,))
+        self.last_status = st
+        return VW, info.as_dict()
+
+    def solve_dev(self, FT_dev, VW_dev):
+        """FT_dev, VW_dev: float64 (n, 6) CUDA tensors."""
+        lib = load()
+        info = SolveInfo()
+        st = _check(lib.rbm_solve_dev(self.ctx, ctypes.c_void_p(FT_dev.data_ptr()),
+                                      ctypes.c_void_p(VW_dev.data_ptr()), ctypes.byref(info)),
+                    allow=(RBM_E_NOCONV,))
+        self.last_status = st
+        return info.as_dict()
+
+    def set_guess_dev(self, mu0_dev):
+        _check(load().rbm_set_guess_dev(self.ctx, ctypes.c_void_p(mu0_dev.data_ptr())))
+
+    def density(self):
+        mu = np.zeros((3, self.N))
+        rho = np.zeros((3, self.N))
+        _check(load().rbm_get_density(self.ctx, _ptr(mu), _ptr(rho)))
+        return mu, rho
+
+    def read(self, name, count, dtype=np.float64, offset=0):
+        out = np.zeros(count, dtype=dtype)
+        _check(load().rbm_debug_read(self.ctx, name.encode(), offset, out.nbytes, _ptr(out)))
+        return out
+
+    # -- low-level sums -------------------------------------------------------------
+    def far_traction(self, X, Nrm, q, M, add=None, precision=0):
+        """X, Nrm, q, add: float64 (3, n) CUDA tensors; returns (3, n) tensor."""
+        torch = self.torch
+        n = X.shape[1]
+        y = torch.empty_like(X)
+        a = ctypes.c_void_p(add.data_ptr()) if add is not None else None
+        _check(load().rbm_far_traction(self.ctx, n, M, ctypes.c_void_p(X.data_ptr()),
+                                       ctypes.c_void_p(Nrm.data_ptr()), ctypes.c_void_p(q.data_ptr()),
+                                       a, ctypes.c_void_p(y.data_ptr()), precision))
+        return y
+
+    def far_stokeslet(self, X, q, M, precision=0):
+        torch = self.torch
+        n = X.shape[1]
+        u = torch.empty_like(X)
+        _check(load().rbm_far_stokeslet(self.ctx, n, M, ctypes.c_void_p(X.data_ptr()),
+                                        ctypes.c_void_p(q.data_ptr()), ctypes.c_void_p(u.data_ptr()),
+                                        precision))
+        return u
+
+    def close(self):
+        if getattr(self, "ctx", None):
+            load().rbm_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def solver_for(workload, **kw):
+    """Build a Solver from a ``paper_1606_07428_amd.inputs`` workload dict."""
+    return Solver(workload["p"], workload["shapes"], workload["shape_id"], workload["centres"],
+                  workload["quats"], eta=workload.get("eta", 1.0), **kw)

@@ -1,0 +1,168 @@
+"""GPU parity of the HIP path (through the C ABI) against the FP64 oracle.
+
+Every test prints the case it runs before touching the GPU."""
+import math
+
+import numpy as np
+import pytest
+
+from paper_1606_07428_amd import inputs, rbm
+from oracle import farfield as ff
+from oracle import geometry as geo
+from oracle import singular as sg
+from tests.helpers import oracle_problem, oracle_shapes, rel_err
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _case(msg):
+    print(f"\n[case] {msg}", flush=True)
+
+
+def _dev(a):
+    return torch.as_tensor(np.ascontiguousarray(a, dtype=np.float64), device="cuda")
+
+
+def _sum_solver(n_points, M):
+    """A context whose workspace holds n_points points (one shared unit sphere)."""
+    p = 2
+    while 2 * p * (p + 1) < M:
+        p += 1
+    nb = -(-n_points // (2 * p * (p + 1)))
+    w = {"p": p, "shapes": [("radial", [math.sqrt(4 * math.pi)])], "shape_id": np.zeros(nb, np.int32),
+         "centres": np.arange(nb)[:, None] * np.array([[3.0, 0, 0]]), "quats": np.tile([1.0, 0, 0, 0], (nb, 1))}
+    return rbm.solver_for(w)
+
+
+@pytest.mark.parametrize("n_points,M,prec", [(5 * 84, 84, 0), (1037, 84, 0), (9 * 512 + 77, 144, 0),
+                                             (1037, 84, 1), (9 * 512 + 77, 144, 1)])
+def test_far_sums_match_oracle(n_points, M, prec):
+    _case(f"far sums n={n_points} M={M} precision={prec}")
+    rng = np.random.default_rng(n_points + M)
+    X = rng.uniform(-4, 4, (n_points, 3))
+    Nn = rng.standard_normal((n_points, 3))
+    Nn /= np.linalg.norm(Nn, axis=1)[:, None]
+    q = rng.standard_normal((n_points, 3))
+    add = rng.standard_normal((n_points, 3))
+    body = np.arange(n_points) // M
+    s = _sum_solver(n_points, M)
+    yt = s.far_traction(_dev(X.T), _dev(Nn.T), _dev(q.T), M, add=_dev(add.T), precision=prec)
+    us = s.far_stokeslet(_dev(X.T), _dev(q.T), M, precision=prec)
+    torch.cuda.synchronize()
+    idx = np.arange(n_points) if n_points < 2000 else rng.choice(n_points, 300, replace=False)
+    ref_t = add[idx] + ff.traction_sum(X[idx], Nn[idx], X, q, body[idx], body)
+    ref_u = ff.stokeslet_sum(X[idx], X, q, body[idx], body)
+    tol = 1e-12 if prec == 0 else 2e-5
+    assert rel_err(yt.cpu().numpy().T[idx], ref_t) < tol
+    assert rel_err(us.cpu().numpy().T[idx], ref_u) < tol
+    s.close()
+
+
+def _body_frame_ops(shape):
+    ops = shape.ops
+    A0 = 0.5 * np.eye(ops["K"].shape[0]) + ops["K"] + sg.L_operator(shape.geom)
+    return ops["S"], A0
+
+
+@pytest.mark.parametrize("name,p", [("tiny", 6), ("two_spheres", 8)])
+def test_setup_operators_match_oracle(name, p):
+    _case(f"setup operators {name} p={p}")
+    w = inputs.tiny(3, p, seed=21) if name == "tiny" else inputs.workload(name)
+    s = rbm.solver_for(w)
+    M = 2 * p * (p + 1)
+    M3 = 3 * M
+    shapes = oracle_shapes(w)
+    for k, sh in enumerate(shapes):
+        S0, A0 = _body_frame_ops(sh)
+        A_gpu = s.read("A0", M3 * M3, offset=k * M3 * M3 * 8).reshape(M3, M3).T
+        P_gpu = s.read("P0", M3 * M3, offset=k * M3 * M3 * 8).reshape(M3, M3).T
+        assert rel_err(A_gpu, A0) < 1e-12
+        assert rel_err(P_gpu, np.linalg.inv(A0)) < 1e-11
+        g = sh.geom
+        assert rel_err(s.read("gw", M, offset=k * M * 8), g["w"]) < 1e-13
+        assert rel_err(s.read("gr", 3 * M, offset=k * 3 * M * 8).reshape(3, M), g["r"]) < 1e-12
+        shp = s.read("shape", 32, offset=k * 32 * 8)
+        assert abs(shp[0] - g["area"]) < 1e-12 * g["area"]
+        assert rel_err(shp[4:13].reshape(3, 3), g["tau"]) < 1e-12
+        # velocity functional G' S0
+        r, wq = g["r"], g["w"]
+        G = np.zeros((6, M3))
+        for c in range(3):
+            G[c, c * M:(c + 1) * M] = wq / g["area"]
+        ti = np.linalg.inv(g["tau"])
+        for kk in range(3):
+            for c in range(3):
+                # (r x u)_e = eps_{efc} r_f u_c
+                col = np.zeros(M)
+                for e in range(3):
+                    f = [ff_ for ff_ in range(3) if ff_ not in (e, c)]
+                    if e == c or not f:
+                        continue
+                    f = f[0]
+                    sign = 1.0 if (e, f, c) in ((0, 1, 2), (1, 2, 0), (2, 0, 1)) else -1.0
+                    col += ti[kk, e] * sign * r[f]
+                G[3 + kk, c * M:(c + 1) * M] = wq * col
+        V_gpu = s.read("V0", 6 * M3, offset=k * 6 * M3 * 8).reshape(6, M3)
+        assert rel_err(V_gpu, G @ S0) < 1e-12
+    s.close()
+
+
+def test_single_sphere_drag_laws():
+    _case("single sphere drag")
+    w = inputs.workload("single_sphere")
+    s = rbm.solver_for(w)
+    FT = np.array([[1.0, -0.5, 0.25, 0.3, 0.0, 1.0]])
+    VW, info = s.solve(FT)
+    assert np.abs(VW[0, :3] - FT[0, :3] / (6 * math.pi)).max() < 1e-13
+    assert np.abs(VW[0, 3:] - FT[0, 3:] / (8 * math.pi)).max() < 1e-13
+    s.close()
+
+
+def test_two_spheres_match_oracle_dense_solve():
+    _case("two spheres p=8 dense oracle")
+    w = inputs.workload("two_spheres")
+    s = rbm.solver_for(w, tol=1e-13)
+    VW, info = s.solve(w["FT"])
+    prob = oracle_problem(w)
+    rho, mu, VW_o = __import__("oracle.system", fromlist=["x"]).solve_dense(prob, w["FT"])
+    assert info["rel_residual"] < 1e-13
+    assert rel_err(VW, VW_o) < 1e-11
+    mu_g, rho_g = s.density()
+    assert rel_err(rho_g.T, rho) < 1e-13
+    assert rel_err(mu_g.T, mu) < 1e-10
+    # reflection symmetry zeros
+    assert np.abs(VW[:, [2, 3, 4]]).max() < 1e-14
+    s.close()
+
+
+@pytest.mark.parametrize("n,p,seed,guess", [(4, 6, 3, rbm.GUESS_BLOCKDIAG), (3, 5, 4, rbm.GUESS_ZERO),
+                                            (7, 5, 5, rbm.GUESS_BLOCKDIAG)])
+def test_random_bodies_match_oracle(n, p, seed, guess):
+    _case(f"random bodies n={n} p={p} seed={seed} guess={guess}")
+    from oracle import system as sy
+    w = inputs.tiny(n, p, seed=seed)
+    s = rbm.solver_for(w, tol=1e-13, guess=guess)
+    VW, info = s.solve(w["FT"])
+    prob = oracle_problem(w)
+    _, mu_o, VW_o = sy.solve_dense(prob, w["FT"])
+    assert info["rel_residual"] < 1e-13
+    assert rel_err(VW, VW_o) < 1e-10
+    mu_g, _ = s.density()
+    assert rel_err(mu_g.T, mu_o) < 1e-9
+    s.close()
+
+
+@pytest.mark.parametrize("prec", [rbm.MIXED_FP32, rbm.MIXED_BF16])
+def test_mixed_precision_reaches_fp64_answer(prec):
+    _case(f"mixed precision {prec} tiny")
+    from oracle import system as sy
+    w = inputs.tiny(5, 6, seed=8)
+    s = rbm.solver_for(w, tol=1e-11, precision=prec)
+    VW, info = s.solve(w["FT"])
+    _, _, VW_o = sy.solve_dense(oracle_problem(w), w["FT"])
+    assert info["rel_residual"] < 1e-11
+    assert info["refinements"] >= 1
+    assert rel_err(VW, VW_o) < 1e-9
+    s.close()
