@@ -92,7 +92,12 @@ typedef struct {
   double ms_total;    /* wall time of the solve on the stream (ms) */
   double ms_far;      /* time in the all-pairs sums (ms, event-timed) */
   double ms_self;     /* time in the per-body operator applies (ms) */
-  double far_pairs;   /* off-body pair interactions evaluated */
+  double far_pairs;   /* off-body pair interactions evaluated (all sums) */
+  int n_traction;     /* launches of the float64/float32 traction sum kernel */
+  int n_stokeslet;    /* launches of the Stokeslet sum kernel */
+  double ms_traction; /* summed duration of the traction kernel launches (ms) */
+  double ms_stokeslet;/* summed duration of the Stokeslet kernel launches (ms) */
+  double pairs_per_launch; /* off-body pairs of one launch: N^2 - n M^2 */
 } rbm_solve_info;
 
 /* Default options: p = 8, p_sing = 0, eta = 1, tol = 1e-12, max_iter = 100,

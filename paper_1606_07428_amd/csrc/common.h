@@ -26,25 +26,58 @@ __host__ __device__ inline int band_index(int l, int m, int p) {
 //   P_lm = a (x P_{l-1,m} - b P_{l-2,m}), a = sqrt((4l^2-1)/(l^2-m^2)),
 //   b = sqrt(((l-1)^2-m^2)/(4(l-1)^2-1)); D follows by differentiating them in theta
 //   (dx/dtheta = -s), with D_mm = m x Q_mm.
+//
+// The recurrence coefficients depend only on (l, m).  With `tab` == nullptr they are
+// computed inline; otherwise tab holds legendre_table() for this L.
+__device__ __forceinline__ int legendre_table_size(int L) { return 2 * (L + 1) * (L + 1) + 2 * (L + 1); }
+
+// tab[2*(l*(L+1)+m)] = a_lm, tab[2*(l*(L+1)+m)+1] = b_lm (l >= m+2);
+// tab[2*(L+1)^2 + 2m] = sqrt((2m+1)/(2m)), tab[2*(L+1)^2 + 2m + 1] = sqrt(2m+3).
+__device__ inline void legendre_table(int L, double* tab, int tid, int nt) {
+  const int n2 = (L + 1) * (L + 1);
+  for (int i = tid; i < n2; i += nt) {
+    const int l = i / (L + 1), m = i % (L + 1);
+    double a = 0.0, b = 0.0;
+    if (l >= m + 2) {
+      a = sqrt((4.0 * l * l - 1.0) / (double)(l * l - m * m));
+      b = sqrt(((l - 1.0) * (l - 1.0) - (double)m * m) / (4.0 * (l - 1.0) * (l - 1.0) - 1.0));
+    }
+    tab[2 * i] = a;
+    tab[2 * i + 1] = b;
+  }
+  for (int m = tid; m <= L; m += nt) {
+    tab[2 * n2 + 2 * m] = m > 0 ? sqrt((2.0 * m + 1.0) / (2.0 * m)) : 0.0;
+    tab[2 * n2 + 2 * m + 1] = sqrt(2.0 * m + 3.0);
+  }
+}
+
 template <class F>
-__device__ __forceinline__ void legendre_sweep(int L, double x, double s, F&& f) {
+__device__ __forceinline__ void legendre_sweep(int L, double x, double s, F&& f,
+                                               const double* tab = nullptr) {
   double pmm = 0.28209479177387814347;  // 1/sqrt(4 pi)
   double qmm = 0.0;
+  const int n2 = (L + 1) * (L + 1);
   for (int m = 0; m <= L; ++m) {
     if (m > 0) {
-      const double c = sqrt((2.0 * m + 1.0) / (2.0 * m));
+      const double c = tab ? tab[2 * n2 + 2 * m] : sqrt((2.0 * m + 1.0) / (2.0 * m));
       qmm = c * pmm;
       pmm = c * s * pmm;
     }
     double p0 = pmm, q0 = qmm, d0 = m * x * qmm;
     f(m, m, p0, q0, d0);
     if (m < L) {
-      const double c = sqrt(2.0 * m + 3.0);
+      const double c = tab ? tab[2 * n2 + 2 * m + 1] : sqrt(2.0 * m + 3.0);
       double p1 = c * x * p0, q1 = c * x * q0, d1 = c * (x * d0 - s * p0);
       f(m + 1, m, p1, q1, d1);
       for (int l = m + 2; l <= L; ++l) {
-        const double a = sqrt((4.0 * l * l - 1.0) / (double)(l * l - m * m));
-        const double b = sqrt(((l - 1.0) * (l - 1.0) - (double)m * m) / (4.0 * (l - 1.0) * (l - 1.0) - 1.0));
+        double a, b;
+        if (tab) {
+          a = tab[2 * (l * (L + 1) + m)];
+          b = tab[2 * (l * (L + 1) + m) + 1];
+        } else {
+          a = sqrt((4.0 * l * l - 1.0) / (double)(l * l - m * m));
+          b = sqrt(((l - 1.0) * (l - 1.0) - (double)m * m) / (4.0 * (l - 1.0) * (l - 1.0) - 1.0));
+        }
         const double p2 = a * (x * p1 - b * p0);
         const double q2 = a * (x * q1 - b * q0);
         const double d2 = a * (x * d1 - s * p1 - b * d0);

@@ -293,7 +293,9 @@ __global__ __launch_bounds__(256) void k_singular(int p, int ps, double eta,
   double* cf = lds;             // [3][nc]
   double* Ych = cf + 3 * nc;    // [nB][NC]
   double* Kw = Ych + nB * NC;   // [12][NC]
+  double* ltab = Kw + 12 * NC;  // Legendre recurrence coefficients
   for (int i = tid; i < 3 * nc; i += 256) cf[i] = coef_all[(size_t)s * 3 * nc + i];
+  legendre_table(p, ltab, tid, 256);
   double st, ct, sp, cp;
   sincos(nth[t], &st, &ct);
   sincos(nph[t], &sp, &cp);
@@ -349,7 +351,7 @@ __global__ __launch_bounds__(256) void k_singular(int p, int ps, double eta,
           Ych[band_index(l, m, p) * NC + tid] = yp;
           const int bm = band_index(l, -m, p);
           if (bm >= 0) Ych[bm * NC + tid] = ym;
-        });
+        }, ltab);
         const double c0 = dt[1] * dp[2] - dt[2] * dp[1];
         const double c1 = dt[2] * dp[0] - dt[0] * dp[2];
         const double c2 = dt[0] * dp[1] - dt[1] * dp[0];
@@ -434,7 +436,8 @@ hipError_t launch_singular_assemble(int ns, int p, int ps, double eta, const dou
                                     const double* Fttab, double* Sop, double* Kop, hipStream_t st) {
   const int M = (p + 1) * 2 * p, nc = (p + 1) * (p + 1), nB = p * p + 2 * p;
   dim3 grid(M, ns);
-  const size_t lds64 = (size_t)(3 * nc + nB * 64 + 12 * 64) * sizeof(double);
+  const size_t ltab = (size_t)(2 * nc + 2 * (p + 1));
+  const size_t lds64 = (size_t)(3 * nc + nB * 64 + 12 * 64 + ltab) * sizeof(double);
   if (lds64 <= 150 * 1024) {
     hipError_t e = hipFuncSetAttribute((const void*)k_singular<64>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds64);
@@ -442,7 +445,7 @@ hipError_t launch_singular_assemble(int ns, int p, int ps, double eta, const dou
     k_singular<64><<<grid, 256, lds64, st>>>(p, ps, eta, coef, gx, gn, node_th, node_ph, rnodes,
                                              rW, Fttab, Sop, Kop);
   } else {
-    const size_t lds32 = (size_t)(3 * nc + nB * 32 + 12 * 32) * sizeof(double);
+    const size_t lds32 = (size_t)(3 * nc + nB * 32 + 12 * 32 + ltab) * sizeof(double);
     hipError_t e = hipFuncSetAttribute((const void*)k_singular<32>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds32);
     if (e != hipSuccess) return e;

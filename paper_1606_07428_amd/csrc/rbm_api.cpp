@@ -356,7 +356,7 @@ struct Timer {
 };
 
 struct SolveState {
-  std::vector<std::pair<int, int>> far_ev, self_ev;  // event index pairs
+  std::vector<std::pair<int, int>> trac_ev, stok_ev, self_ev;  // event index pairs
   double far_pairs = 0.0;
   int matvecs = 0;
 };
@@ -366,16 +366,19 @@ static rbm_status far_traction(rbm_ctx* c, SolveState& S, const double* x, int x
                                int prec) {
   const int N = c->n * c->M;
   const int nsp = split_for(c, N);
-  Timer t(c);
   if (prec == 0) {
     HIPCHECK(launch_pack_sources<double>(N, c->M, c->X, c->W, c->Rm, x, x_is_body, nullptr, c->src, c->st));
+    Timer t(c);
     HIPCHECK(launch_far<double>(0, N, c->M, c->X, c->Nn, c->src, c->part, nsp, c->st));
+    t.stop();
+    if (t.on) S.trac_ev.push_back({c->ev_used - 2, c->ev_used - 1});
   } else {
     HIPCHECK(launch_pack_sources<float>(N, c->M, c->X, c->W, c->Rm, x, x_is_body, nullptr, c->src, c->st));
+    Timer t(c);
     HIPCHECK(launch_far<float>(0, N, c->M, c->Xf, c->Nf, c->src, c->part, nsp, c->st));
+    t.stop();
+    if (t.on) S.trac_ev.push_back({c->ev_used - 2, c->ev_used - 1});
   }
-  t.stop();
-  if (t.on) S.far_ev.push_back({c->ev_used - 2, c->ev_used - 1});
   S.far_pairs += (double)N * N - (double)c->n * c->M * c->M;
   return RBM_OK;
 }
@@ -552,11 +555,11 @@ static rbm_status solve_impl(rbm_ctx* c, const double* dFT, double* dVW, rbm_sol
   // velocities u = S[rho + mu]: far Stokeslet sum + self functional, float64
   HIPCHECK(launch_axpby(len, 1.0, c->rho, 1.0, c->mu, c->t2, st));
   {
-    Timer t(c);
     HIPCHECK(launch_pack_sources<double>(N, M, c->X, c->W, c->Rm, c->t2, 0, nullptr, c->src, st));
+    Timer t(c);
     HIPCHECK(launch_far<double>(1, N, M, c->X, nullptr, c->src, c->part, split_for(c, N), st));
     t.stop();
-    if (t.on) S.far_ev.push_back({c->ev_used - 2, c->ev_used - 1});
+    if (t.on) S.stok_ev.push_back({c->ev_used - 2, c->ev_used - 1});
     S.far_pairs += (double)N * N - (double)n * M * M;
   }
   HIPCHECK(launch_combine(N, M, split_for(c, N), c->part, 1.0 / c->opt.eta, nullptr, 0.0, nullptr, nullptr,
@@ -576,14 +579,22 @@ static rbm_status solve_impl(rbm_ctx* c, const double* dFT, double* dVW, rbm_sol
     info->rel_residual = rel;
     info->bnorm = bnorm;
     info->far_pairs = S.far_pairs;
+    info->n_traction = (int)S.trac_ev.size();
+    info->n_stokeslet = (int)S.stok_ev.size();
+    info->pairs_per_launch = (double)N * N - (double)n * M * M;
     if (total.on) {
       float ms = 0;
       (void)hipEventElapsedTime(&ms, total.a, total.b);
       info->ms_total = ms;
-      for (auto& e : S.far_ev) {
+      for (auto& e : S.trac_ev) {
         (void)hipEventElapsedTime(&ms, c->ev[e.first], c->ev[e.second]);
-        info->ms_far += ms;
+        info->ms_traction += ms;
       }
+      for (auto& e : S.stok_ev) {
+        (void)hipEventElapsedTime(&ms, c->ev[e.first], c->ev[e.second]);
+        info->ms_stokeslet += ms;
+      }
+      info->ms_far = info->ms_traction + info->ms_stokeslet;
       for (auto& e : S.self_ev) {
         (void)hipEventElapsedTime(&ms, c->ev[e.first], c->ev[e.second]);
         info->ms_self += ms;

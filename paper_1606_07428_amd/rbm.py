@@ -36,7 +36,9 @@ class SolveInfo(ctypes.Structure):
     _fields_ = [("iters", ctypes.c_int), ("matvecs", ctypes.c_int), ("refinements", ctypes.c_int),
                 ("cycles", ctypes.c_int), ("rel_residual", ctypes.c_double), ("bnorm", ctypes.c_double),
                 ("ms_total", ctypes.c_double), ("ms_far", ctypes.c_double), ("ms_self", ctypes.c_double),
-                ("far_pairs", ctypes.c_double)]
+                ("far_pairs", ctypes.c_double), ("n_traction", ctypes.c_int),
+                ("n_stokeslet", ctypes.c_int), ("ms_traction", ctypes.c_double),
+                ("ms_stokeslet", ctypes.c_double), ("pairs_per_launch", ctypes.c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
