@@ -145,6 +145,18 @@ rbm_status rbm_solve(rbm_ctx* ctx, const double* FT, double* VW, rbm_solve_info*
  * scalar is read back per GMRES iteration for the stopping test). */
 rbm_status rbm_solve_dev(rbm_ctx* ctx, const double* d_FT, double* d_VW, rbm_solve_info* info);
 
+/* One classical RK4 step of the rigid-body evolution (§3.3; Algorithm 1, evolve
+ * line): four mobility solves with the loads d_FT[n][6] (device pointer, held
+ * fixed over the step), dc/dt = v, dq/dt = 1/2 (0, omega) (x) q with omega in the
+ * lab frame; stage quaternions are normalised before they define a pose, and so is
+ * the final one.  Poses are updated on the device (and mirrored to the host copy
+ * read by rbm_get_bodies).  stage_info[4] may be NULL.  Returns RBM_E_NOCONV if a
+ * stage solve missed its tolerance (the step is still taken). */
+rbm_status rbm_step_rk4(rbm_ctx* ctx, double dt, const double* d_FT, rbm_solve_info* stage_info);
+
+/* Current poses: centre[n][3], quat[n][4] (host arrays). */
+rbm_status rbm_get_bodies(rbm_ctx* ctx, double* centre, double* quat);
+
 /* Initial density for RBM_GUESS_USER: d_mu0[3][N] device array, copied. */
 rbm_status rbm_set_guess_dev(rbm_ctx* ctx, const double* d_mu0);
 

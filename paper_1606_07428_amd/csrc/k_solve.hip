@@ -211,4 +211,74 @@ hipError_t launch_velocity_final(int n, const double* mom_far, const double* vw_
   return hipGetLastError();
 }
 
+// ---- RK4 on centroids and quaternions (§3.3) ----------------------------------------
+// k layout per body: [dc/dt (3), dq/dt (4)].
+__device__ inline void qnormalize(double* q) {
+  const double s = 1.0 / sqrt(q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3]);
+  for (int k = 0; k < 4; ++k) q[k] *= s;
+}
+
+__global__ void k_rk_stage(int n, const double* c0, const double* q0, const double* k, double a,
+                           double dt, double* cen, double* quat) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double q[4];
+  const bool first = (a == 0.0);  // the first stage reads no derivative
+  for (int c = 0; c < 3; ++c) cen[3 * i + c] = c0[3 * i + c] + (first ? 0.0 : a * dt * k[7 * i + c]);
+  for (int c = 0; c < 4; ++c) q[c] = q0[4 * i + c] + (first ? 0.0 : a * dt * k[7 * i + 3 + c]);
+  qnormalize(q);
+  for (int c = 0; c < 4; ++c) quat[4 * i + c] = q[c];
+}
+
+hipError_t launch_rk_stage(int n, const double* c0, const double* q0, const double* k, double a,
+                           double dt, double* cen, double* quat, hipStream_t st) {
+  k_rk_stage<<<(n + 63) / 64, 64, 0, st>>>(n, c0, q0, k, a, dt, cen, quat);
+  return hipGetLastError();
+}
+
+// k = (v, 1/2 (0, omega) (x) q); acc = (first ? 0 : acc) + wgt k
+__global__ void k_rk_deriv(int n, const double* VW, const double* quat, double* k, double* acc,
+                           double wgt, int first) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double* v = VW + 6 * i;
+  const double* q = quat + 4 * i;
+  const double ox = v[3], oy = v[4], oz = v[5];
+  double d[7];
+  d[0] = v[0];
+  d[1] = v[1];
+  d[2] = v[2];
+  d[3] = 0.5 * (-ox * q[1] - oy * q[2] - oz * q[3]);
+  d[4] = 0.5 * (ox * q[0] + oy * q[3] - oz * q[2]);
+  d[5] = 0.5 * (-ox * q[3] + oy * q[0] + oz * q[1]);
+  d[6] = 0.5 * (ox * q[2] - oy * q[1] + oz * q[0]);
+  for (int c = 0; c < 7; ++c) {
+    k[7 * i + c] = d[c];
+    acc[7 * i + c] = (first ? 0.0 : acc[7 * i + c]) + wgt * d[c];
+  }
+}
+
+hipError_t launch_rk_deriv(int n, const double* VW, const double* quat, double* k, double* acc,
+                           double wgt, int first, hipStream_t st) {
+  k_rk_deriv<<<(n + 63) / 64, 64, 0, st>>>(n, VW, quat, k, acc, wgt, first);
+  return hipGetLastError();
+}
+
+__global__ void k_rk_final(int n, const double* c0, const double* q0, const double* acc, double dt,
+                           double* cen, double* quat) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double q[4];
+  for (int c = 0; c < 3; ++c) cen[3 * i + c] = c0[3 * i + c] + dt / 6.0 * acc[7 * i + c];
+  for (int c = 0; c < 4; ++c) q[c] = q0[4 * i + c] + dt / 6.0 * acc[7 * i + 3 + c];
+  qnormalize(q);
+  for (int c = 0; c < 4; ++c) quat[4 * i + c] = q[c];
+}
+
+hipError_t launch_rk_final(int n, const double* c0, const double* q0, const double* acc, double dt,
+                           double* cen, double* quat, hipStream_t st) {
+  k_rk_final<<<(n + 63) / 64, 64, 0, st>>>(n, c0, q0, acc, dt, cen, quat);
+  return hipGetLastError();
+}
+
 }  // namespace rbm

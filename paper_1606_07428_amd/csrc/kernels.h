@@ -58,6 +58,14 @@ hipError_t launch_velocity_final(int n, const double* mom_far, const double* vw_
                                  const double* tauinv_lab, const double* area_b, double* VW,
                                  hipStream_t st);
 
+// RK4 on (c, q): stage pose y0 + a dt k; derivative and weighted accumulation; final update.
+hipError_t launch_rk_stage(int n, const double* c0, const double* q0, const double* k, double a,
+                           double dt, double* cen, double* quat, hipStream_t st);
+hipError_t launch_rk_deriv(int n, const double* VW, const double* quat, double* k, double* acc,
+                           double wgt, int first, hipStream_t st);
+hipError_t launch_rk_final(int n, const double* c0, const double* q0, const double* acc, double dt,
+                           double* cen, double* quat, hipStream_t st);
+
 // ---- per-body operator apply (k_self.hip) ----------------------------------------
 // y_body[3][N] = A_{s(i)} (R_i^T x_lab) per body; A column-major [ns][3M][3M].
 template <typename TM>

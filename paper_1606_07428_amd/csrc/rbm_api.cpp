@@ -57,6 +57,7 @@ struct rbm_ctx {
   // bodies and nodes
   int* sid;
   double *cen, *quat, *FT, *VW, *Rm, *tauinv, *area_b, *mom, *vws;
+  double *cen0, *quat0, *kst, *kacc;
   double *X, *Nn, *W;
   float *Xf, *Nf;
   // vectors
@@ -224,6 +225,7 @@ static size_t layout(rbm_ctx* c, int nmax, bool assign) {
   take(c->sid, nm); take(c->cen, 3 * nm); take(c->quat, 4 * nm); take(c->FT, 6 * nm);
   take(c->VW, 6 * nm); take(c->Rm, 9 * nm); take(c->tauinv, 9 * nm); take(c->area_b, nm);
   take(c->mom, 6 * nm); take(c->vws, 6 * nm);
+  take(c->cen0, 3 * nm); take(c->quat0, 4 * nm); take(c->kst, 7 * nm); take(c->kacc, 7 * nm);
   take(c->X, N3); take(c->Nn, N3); take(c->W, N); take(c->Xf, N3); take(c->Nf, N3);
   take(c->rho, N3); take(c->b, N3); take(c->mu, N3); take(c->r, N3); take(c->t1, N3);
   take(c->t2, N3); take(c->yb, N3); take(c->guess, N3);
@@ -720,5 +722,55 @@ extern "C" rbm_status rbm_debug_read(rbm_ctx* c, const char* name, size_t offset
   if (!p) return fail(RBM_E_INVAL, "unknown array name");
   HIPCHECK(hipStreamSynchronize(c->st));
   HIPCHECK(hipMemcpy(dst, (const char*)p + offset, bytes, hipMemcpyDeviceToHost));
+  return RBM_OK;
+}
+
+static rbm_status refresh_nodes(rbm_ctx* c) {
+  HIPCHECK(launch_body_prep(c->n, c->quat, c->sid, c->shp, c->Rm, c->tauinv, c->area_b, c->st));
+  HIPCHECK(launch_nodes(c->n, c->M, c->sid, c->cen, c->Rm, c->gr, c->gn, c->gw, c->X, c->Nn, c->W,
+                        c->Xf, c->Nf, c->st));
+  return RBM_OK;
+}
+
+extern "C" rbm_status rbm_step_rk4(rbm_ctx* c, double dt, const double* d_FT,
+                                   rbm_solve_info* stage_info) {
+  if (!c || !d_FT) return fail(RBM_E_INVAL, "null argument");
+  if (!(dt > 0.0) || !std::isfinite(dt)) return fail(RBM_E_INVAL, "dt must be > 0");
+  if (!c->ws) return fail(RBM_E_NOMEM, "bind a workspace first");
+  if (!c->setup_done) return fail(RBM_E_STATE, "call rbm_setup first");
+  if (c->n < 1) return fail(RBM_E_STATE, "set bodies first");
+  rbm_status s;
+  if ((s = upload_bodies(c)) != RBM_OK) return s;
+  const int n = c->n;
+  hipStream_t st = c->st;
+  HIPCHECK(hipMemcpyAsync(c->cen0, c->cen, 3 * n * sizeof(double), hipMemcpyDeviceToDevice, st));
+  HIPCHECK(hipMemcpyAsync(c->quat0, c->quat, 4 * n * sizeof(double), hipMemcpyDeviceToDevice, st));
+  const double a[4] = {0.0, 0.5, 0.5, 1.0}, wgt[4] = {1.0, 2.0, 2.0, 1.0};
+  rbm_status worst = RBM_OK;
+  for (int k = 0; k < 4; ++k) {
+    HIPCHECK(launch_rk_stage(n, c->cen0, c->quat0, c->kst, a[k], dt, c->cen, c->quat, st));
+    if ((s = refresh_nodes(c)) != RBM_OK) return s;
+    c->bodies_dirty = false;
+    s = solve_impl(c, d_FT, c->VW, stage_info ? stage_info + k : nullptr);
+    if (s == RBM_E_NOCONV) worst = s;
+    else if (s != RBM_OK) return s;
+    HIPCHECK(launch_rk_deriv(n, c->VW, c->quat, c->kst, c->kacc, wgt[k], k == 0, st));
+  }
+  HIPCHECK(launch_rk_final(n, c->cen0, c->quat0, c->kacc, dt, c->cen, c->quat, st));
+  if ((s = refresh_nodes(c)) != RBM_OK) return s;
+  HIPCHECK(hipMemcpyAsync(c->cen_h.data(), c->cen, 3 * n * sizeof(double), hipMemcpyDeviceToHost, st));
+  HIPCHECK(hipMemcpyAsync(c->quat_h.data(), c->quat, 4 * n * sizeof(double), hipMemcpyDeviceToHost, st));
+  HIPCHECK(hipStreamSynchronize(st));
+  c->bodies_dirty = false;
+  c->have_solution = true;
+  if (worst != RBM_OK) return fail(worst, "a stage solve did not reach tol");
+  return RBM_OK;
+}
+
+extern "C" rbm_status rbm_get_bodies(rbm_ctx* c, double* centre, double* quat) {
+  if (!c || !centre || !quat) return fail(RBM_E_INVAL, "null argument");
+  if (c->n < 1) return fail(RBM_E_STATE, "set bodies first");
+  std::memcpy(centre, c->cen_h.data(), 3 * c->n * sizeof(double));
+  std::memcpy(quat, c->quat_h.data(), 4 * c->n * sizeof(double));
   return RBM_OK;
 }

@@ -21,7 +21,7 @@ EXPORTED = [
     "rbm_default_options", "rbm_create", "rbm_destroy", "rbm_set_shapes", "rbm_set_shapes_radial",
     "rbm_set_bodies", "rbm_workspace_size", "rbm_bind_workspace", "rbm_setup", "rbm_solve",
     "rbm_solve_dev", "rbm_set_guess_dev", "rbm_get_density", "rbm_debug_ptr", "rbm_debug_read",
-    "rbm_far_traction", "rbm_far_stokeslet", "rbm_last_error",
+    "rbm_far_traction", "rbm_far_stokeslet", "rbm_last_error", "rbm_step_rk4", "rbm_get_bodies",
 ]
 
 
@@ -74,6 +74,8 @@ def load():
         "rbm_far_traction": (I, [P, I, I, P, P, P, P, P, I]),
         "rbm_far_stokeslet": (I, [P, I, I, P, P, P, I]),
         "rbm_last_error": (ctypes.c_char_p, []),
+        "rbm_step_rk4": (I, [P, D, P, P]),
+        "rbm_get_bodies": (I, [P, P, P]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -191,6 +193,21 @@ class Solver:
                     allow=(RBM_E_NOCONV,))
         self.last_status = st
         return info.as_dict()
+
+    def step_rk4(self, dt, FT_dev):
+        """One RK4 step with loads FT_dev (float64 (n, 6) CUDA tensor); returns the
+        four stage infos."""
+        infos = (SolveInfo * 4)()
+        st = _check(load().rbm_step_rk4(self.ctx, float(dt), ctypes.c_void_p(FT_dev.data_ptr()), infos),
+                    allow=(RBM_E_NOCONV,))
+        self.last_status = st
+        return [i.as_dict() for i in infos]
+
+    def bodies(self):
+        cen = np.zeros((self.n, 3))
+        q = np.zeros((self.n, 4))
+        _check(load().rbm_get_bodies(self.ctx, _ptr(cen), _ptr(q)))
+        return cen, q
 
     def set_guess_dev(self, mu0_dev):
         _check(load().rbm_set_guess_dev(self.ctx, ctypes.c_void_p(mu0_dev.data_ptr())))
