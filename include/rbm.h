@@ -66,7 +66,9 @@ typedef enum {
 typedef enum {
   RBM_GUESS_ZERO = 0,       /* mu_0 = 0 */
   RBM_GUESS_BLOCKDIAG = 1,  /* mu_0 = P^{-1} b, P = block-diagonal self operator (§3.2) */
-  RBM_GUESS_USER = 2        /* mu_0 taken from rbm_set_guess_dev() (e.g. a learned guess) */
+  RBM_GUESS_USER = 2,       /* mu_0 taken from rbm_set_guess_dev() */
+  RBM_GUESS_LEARNED = 3     /* mu_0 = mu_BD + network correction, falling back to mu_BD when its
+                               residual is worse than the block-diagonal guess's (see learned API) */
 } rbm_guess;
 
 typedef struct {
@@ -98,6 +100,9 @@ typedef struct {
   double ms_traction; /* summed duration of the traction kernel launches (ms) */
   double ms_stokeslet;/* summed duration of the Stokeslet kernel launches (ms) */
   double pairs_per_launch; /* off-body pairs of one launch: N^2 - n M^2 */
+  int guess_used;     /* rbm_guess actually used for mu_0 */
+  int fallback_used;  /* 1 if the learned guess was rejected for the block-diagonal one */
+  double init_rel_residual; /* ||b - A mu_0|| / ||b|| */
 } rbm_solve_info;
 
 /* Default options: p = 8, p_sing = 0, eta = 1, tol = 1e-12, max_iter = 100,
@@ -157,8 +162,63 @@ rbm_status rbm_step_rk4(rbm_ctx* ctx, double dt, const double* d_FT, rbm_solve_i
 /* Current poses: centre[n][3], quat[n][4] (host arrays). */
 rbm_status rbm_get_bodies(rbm_ctx* ctx, double* centre, double* quat);
 
+/* Change the initial-guess mode (rbm_guess) of an existing context. */
+rbm_status rbm_set_guess(rbm_ctx* ctx, int guess);
+
 /* Initial density for RBM_GUESS_USER: d_mu0[3][N] device array, copied. */
 rbm_status rbm_set_guess_dev(rbm_ctx* ctx, const double* d_mu0);
+
+/* ---- Learned GMRES warm start (not in the paper; the block-diagonal guess of §3.2 is
+ * its fallback) ---------------------------------------------------------------------
+ * A per-body MLP maps body-frame features (own load, shape's radial coefficients,
+ * k nearest neighbours' relative position d/|d|^2, relative orientation (two
+ * columns of R_i^T R_j) and loads) to the body-frame band coefficients (§3
+ * forward transform) of mu* - mu_BD, mu_BD = P^{-1} b.  Layers: F -> hidden x
+ * n_hidden -> 3 (p^2 + 2p), SiLU, bf16 MFMA with fp32 accumulation and fp32 Adam
+ * master weights.  Training data are captured from the context's own solves. */
+typedef struct {
+  int k_nbr;                 /* neighbours (1..16), default 8 */
+  int hidden;                /* hidden width, default 256 */
+  int n_hidden;              /* hidden layers (1..6), default 3 */
+  int capacity;              /* captured body states the buffer holds, default 65536 */
+  int batch_max;             /* largest training batch, default 1024 */
+  unsigned long long seed;   /* weight initialisation and epoch shuffles */
+} rbm_learned_config;
+
+void rbm_learned_default_config(rbm_learned_config* cfg);
+/* Device bytes of the learned workspace (weights, Adam state, sample buffer, batch
+ * activations).  Needs shapes and a bound solver workspace. */
+rbm_status rbm_learned_workspace_size(rbm_ctx* ctx, const rbm_learned_config* cfg, size_t* bytes);
+/* Bind it (caller-owned device memory) and initialise the weights. */
+rbm_status rbm_learned_bind(rbm_ctx* ctx, const rbm_learned_config* cfg, void* dptr, size_t bytes);
+/* Append (features, band coefficients of mu - mu_BD) of every body of the last solve,
+ * whose loads were d_FT[n][6] (device).  Silently stops when the buffer is full. */
+rbm_status rbm_learned_capture(rbm_ctx* ctx, const double* d_FT);
+/* on != 0: capture after every solve (including the four RK4 stages). */
+rbm_status rbm_learned_set_capture(rbm_ctx* ctx, int on);
+/* `epochs` passes of Adam (learning rate lr) over the buffer in shuffled batches;
+ * feature/target scalings are fixed from the buffer on the first call.  *loss gets
+ * the last epoch's mean squared error in scaled units. */
+rbm_status rbm_learned_train(rbm_ctx* ctx, int epochs, int batch, double lr, double* loss);
+/* Sizes: captured samples, features F, outputs O, parameter count (weights then
+ * biases per layer, row-major W[in][out]). */
+rbm_status rbm_learned_info(rbm_ctx* ctx, int* samples, int* n_features, int* n_outputs,
+                            int* n_params);
+/* Parameters + scalings: [params (n_params), mean (F), inv_std (F), target scale, 1/scale]. */
+rbm_status rbm_learned_get_params(rbm_ctx* ctx, float* host, size_t count);
+rbm_status rbm_learned_set_params(rbm_ctx* ctx, const float* host, size_t count);
+/* Network on given raw features d_X[rows][F] (device, fp32) -> d_Y[rows][O] (unscaled by
+ * the target scale), rows <= max(batch_max, bodies). */
+rbm_status rbm_learned_forward_dev(rbm_ctx* ctx, const float* d_X, int rows, float* d_Y);
+/* Loss (MSE against d_T[rows][O] times 1/target scale) and the parameter gradient
+ * d_grad[n_params] for one batch; no update. */
+rbm_status rbm_learned_loss_grad_dev(rbm_ctx* ctx, const float* d_X, const float* d_T, int rows,
+                                     float* d_grad, double* loss);
+/* Features of the current bodies for loads d_FT: d_X[n][F] (device, fp32). */
+rbm_status rbm_learned_features_dev(rbm_ctx* ctx, const double* d_FT, float* d_X);
+/* The learned initial density mu_BD + network correction for loads d_FT (device), into
+ * d_mu0[3][N] (device); float64 block-diagonal part.  Overwrites the last solve's state. */
+rbm_status rbm_learned_guess_dev(rbm_ctx* ctx, const double* d_FT, double* d_mu0);
 
 /* Copy out the last solve's densities ([3][N] host arrays; either may be NULL). */
 rbm_status rbm_get_density(rbm_ctx* ctx, double* mu, double* rho);
@@ -166,8 +226,11 @@ rbm_status rbm_get_density(rbm_ctx* ctx, double* mu, double* rho);
 /* Device pointers of internal arrays for inspection (valid until the workspace is
  * rebound).  name: "X","N","W" ([3][N]/[N] lab nodes, normals, weights), "mu",
  * "rho", "b" ([3][N]), "A0","P0" ([n_shapes][3M][3M] column-major body-frame
- * operators), "V0" ([n_shapes][6][3M]), "geom" (per-shape r[3][M], n[3][M], w[M]),
- * "shape" (per-shape area, xc[3], tau[9], tauinv[9]).  Returns NULL if unknown. */
+ * operators), "V0" ([n_shapes][6][3M]), "gx","gn","gr" ([n_shapes][3][M] shape points,
+ * normals, recentred points), "gw" ([n_shapes][M] weights), "coef" ([n_shapes][3][(p+1)^2]),
+ * "shape" (per shape 32 values: area, xc[3], tau[9], tauinv[9]), "Rm" ([n][9]),
+ * "Ftab" ([p^2+2p][M]), "Ytab" ([(p+1)^2][M]), "learned_X" / "learned_T" (captured
+ * features [capacity][F] and targets [capacity][O], fp32).  NULL if unknown. */
 const void* rbm_debug_ptr(rbm_ctx* ctx, const char* name);
 
 /* Copy `bytes` bytes starting `offset` bytes into the internal array `name` (as for

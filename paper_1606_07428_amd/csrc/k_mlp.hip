@@ -1,0 +1,404 @@
+// Learned GMRES warm start: per-body features, band synthesis/analysis of the density
+// correction, and a small MLP trained and run with bf16 MFMA (fp32 accumulation).
+#include "common.h"
+#include "kernels.h"
+
+namespace rbm {
+
+typedef short s4v __attribute__((ext_vector_type(4)));
+typedef float f4v __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ uint16_t f2bf(float f) {
+  uint32_t u = __float_as_uint(f);
+  u += 0x7fffu + ((u >> 16) & 1u);  // round to nearest even (finite values)
+  return (uint16_t)(u >> 16);
+}
+__device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float(((uint32_t)h) << 16); }
+
+// C(i,j) = alpha * sum_kk A(i,kk) B(kk,j) + bias[j] + beta * C(i,j);  A(i,kk) = A[i*sa0 + kk*sa1],
+// B(kk,j) = B[kk*sb0 + j*sb1], bf16 operands, fp32 accumulation with v_mfma_f32_16x16x16_bf16.
+// 64x64 output tile per workgroup, 4 waves of 32x32 (2x2 MFMA tiles), K staged by 16 in LDS.
+// MFMA operand layout (16x16x16): lane l holds A[l%16][4(l/16)+j] and B[4(l/16)+j][l%16],
+// j = 0..3, and receives D[4(l/16)+e][l%16], e = 0..3.
+__global__ __launch_bounds__(256) void k_gemm_bf16(int m, int n, int k, const uint16_t* __restrict__ A,
+                                                   long sa0, long sa1, const uint16_t* __restrict__ B,
+                                                   long sb0, long sb1, float* __restrict__ C, int ldc,
+                                                   const float* __restrict__ bias, float alpha,
+                                                   float beta) {
+  __shared__ uint16_t As[64][20];
+  __shared__ uint16_t Bs[16][68];
+  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+  const int bm = blockIdx.y * 64, bn = blockIdx.x * 64;
+  const int wr = (wid >> 1) * 32, wc = (wid & 1) * 32;
+  f4v acc[2][2];
+  for (int a = 0; a < 2; ++a)
+    for (int b = 0; b < 2; ++b) acc[a][b] = (f4v){0.f, 0.f, 0.f, 0.f};
+  const int lr = lane & 15, lk = 4 * (lane >> 4);
+  for (int k0 = 0; k0 < k; k0 += 16) {
+    for (int e = tid; e < 1024; e += 256) {
+      const int r = e >> 4, kk = e & 15;
+      const int gi = bm + r, gk = k0 + kk;
+      As[r][kk] = (gi < m && gk < k) ? A[(long)gi * sa0 + (long)gk * sa1] : (uint16_t)0;
+    }
+    for (int e = tid; e < 1024; e += 256) {
+      const int kk = e >> 6, c = e & 63;
+      const int gk = k0 + kk, gj = bn + c;
+      Bs[kk][c] = (gk < k && gj < n) ? B[(long)gk * sb0 + (long)gj * sb1] : (uint16_t)0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int ti = 0; ti < 2; ++ti) {
+      s4v av;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) av[j] = (short)As[wr + ti * 16 + lr][lk + j];
+#pragma unroll
+      for (int tj = 0; tj < 2; ++tj) {
+        s4v bv;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) bv[j] = (short)Bs[lk + j][wc + tj * 16 + lr];
+        acc[ti][tj] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av, bv, acc[ti][tj], 0, 0, 0);
+      }
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int ti = 0; ti < 2; ++ti)
+#pragma unroll
+    for (int tj = 0; tj < 2; ++tj)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int i = bm + wr + ti * 16 + lk + e, j = bn + wc + tj * 16 + lr;
+        if (i < m && j < n) {
+          float v = alpha * acc[ti][tj][e];
+          if (bias) v += bias[j];
+          if (beta != 0.f) v += beta * C[(long)i * ldc + j];
+          C[(long)i * ldc + j] = v;
+        }
+      }
+}
+
+hipError_t launch_gemm_bf16(int m, int n, int k, const uint16_t* A, long sa0, long sa1,
+                            const uint16_t* B, long sb0, long sb1, float* C, int ldc,
+                            const float* bias, float alpha, float beta, hipStream_t st) {
+  dim3 grid((n + 63) / 64, (m + 63) / 64);
+  k_gemm_bf16<<<grid, 256, 0, st>>>(m, n, k, A, sa0, sa1, B, sb0, sb1, C, ldc, bias, alpha, beta);
+  return hipGetLastError();
+}
+
+// H = silu(Z) (fp32 and bf16 copies)
+__global__ void k_silu_fwd(size_t cnt, const float* Z, float* H, uint16_t* Hb) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= cnt) return;
+  const float z = Z[i];
+  const float h = z / (1.f + expf(-z));
+  H[i] = h;
+  Hb[i] = f2bf(h);
+}
+
+hipError_t launch_silu_fwd(size_t cnt, const float* Z, float* H, uint16_t* Hb, hipStream_t st) {
+  k_silu_fwd<<<(unsigned)((cnt + 255) / 256), 256, 0, st>>>(cnt, Z, H, Hb);
+  return hipGetLastError();
+}
+
+// dZ = dH * silu'(Z), silu'(z) = s (1 + z (1 - s)), s = sigmoid(z)
+__global__ void k_silu_bwd(size_t cnt, const float* dH, const float* Z, float* dZ, uint16_t* dZb) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= cnt) return;
+  const float z = Z[i];
+  const float s = 1.f / (1.f + expf(-z));
+  const float g = dH[i] * s * (1.f + z * (1.f - s));
+  dZ[i] = g;
+  dZb[i] = f2bf(g);
+}
+
+hipError_t launch_silu_bwd(size_t cnt, const float* dH, const float* Z, float* dZ, uint16_t* dZb,
+                           hipStream_t st) {
+  k_silu_bwd<<<(unsigned)((cnt + 255) / 256), 256, 0, st>>>(cnt, dH, Z, dZ, dZb);
+  return hipGetLastError();
+}
+
+// Mean-squared error over rows x cols: dY = 2 (Y - T) / (rows cols); per-block partial
+// sums of (Y - T)^2 in part[blockIdx.x].
+__global__ __launch_bounds__(256) void k_mse(size_t cnt, float inv, const float* Y, const float* T,
+                                             float* dY, uint16_t* dYb, double* part) {
+  __shared__ double red[4];
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  double e2 = 0.0;
+  if (i < cnt) {
+    const float d = Y[i] - T[i];
+    const float g = 2.f * d * inv;
+    dY[i] = g;
+    dYb[i] = f2bf(g);
+    e2 = (double)d * d;
+  }
+  const double s = block_sum(e2, red);
+  if (threadIdx.x == 0) part[blockIdx.x] = s;
+}
+
+hipError_t launch_mse(size_t cnt, float inv, const float* Y, const float* T, float* dY,
+                      uint16_t* dYb, double* part, hipStream_t st) {
+  k_mse<<<(unsigned)((cnt + 255) / 256), 256, 0, st>>>(cnt, inv, Y, T, dY, dYb, part);
+  return hipGetLastError();
+}
+
+__global__ __launch_bounds__(256) void k_sum_parts(int nparts, const double* part, double scale,
+                                                   double* out) {
+  __shared__ double red[4];
+  double a = 0.0;
+  for (int i = threadIdx.x; i < nparts; i += 256) a += part[i];
+  const double s = block_sum(a, red);
+  if (threadIdx.x == 0) out[0] = s * scale;
+}
+
+hipError_t launch_sum_parts(int nparts, const double* part, double scale, double* out,
+                            hipStream_t st) {
+  k_sum_parts<<<1, 256, 0, st>>>(nparts, part, scale, out);
+  return hipGetLastError();
+}
+
+// db[j] = sum_i dZ[i][j] (fixed order)
+__global__ void k_colsum(int rows, int cols, const float* dZ, float* db) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= cols) return;
+  float a = 0.f;
+  for (int i = 0; i < rows; ++i) a += dZ[(size_t)i * cols + j];
+  db[j] = a;
+}
+
+hipError_t launch_colsum(int rows, int cols, const float* dZ, float* db, hipStream_t st) {
+  k_colsum<<<(cols + 63) / 64, 64, 0, st>>>(rows, cols, dZ, db);
+  return hipGetLastError();
+}
+
+// Adam with bias correction; fp32 master weights, optional bf16 copy.
+__global__ void k_adam(size_t cnt, float* P, const float* G, float* m, float* v, float lr, float b1,
+                       float b2, float eps, float c1, float c2, uint16_t* Pb) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= cnt) return;
+  const float g = G[i];
+  const float mi = b1 * m[i] + (1.f - b1) * g;
+  const float vi = b2 * v[i] + (1.f - b2) * g * g;
+  m[i] = mi;
+  v[i] = vi;
+  const float p = P[i] - lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+  P[i] = p;
+  if (Pb) Pb[i] = f2bf(p);
+}
+
+hipError_t launch_adam(size_t cnt, float* P, const float* G, float* m, float* v, float lr, float b1,
+                       float b2, float eps, int t, uint16_t* Pb, hipStream_t st) {
+  const float c1 = 1.f - powf(b1, (float)t), c2 = 1.f - powf(b2, (float)t);
+  k_adam<<<(unsigned)((cnt + 255) / 256), 256, 0, st>>>(cnt, P, G, m, v, lr, b1, b2, eps, c1, c2, Pb);
+  return hipGetLastError();
+}
+
+__global__ void k_to_bf16(size_t cnt, const float* x, uint16_t* y) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < cnt) y[i] = f2bf(x[i]);
+}
+
+hipError_t launch_to_bf16(size_t cnt, const float* x, uint16_t* y, hipStream_t st) {
+  k_to_bf16<<<(unsigned)((cnt + 255) / 256), 256, 0, st>>>(cnt, x, y);
+  return hipGetLastError();
+}
+
+// Per body i: body-frame features (own load, shape descriptor, k nearest neighbours:
+// R^T d/|d|^2, first two columns of R_i^T R_j, R^T F_j, R^T T_j; zero padding).
+__global__ void k_features(int n, int k, int S, const double* cen, const double* Rm,
+                           const double* FT, const int* sid, const double* desc, float* X) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int F = 6 + S + 15 * k;
+  float* x = X + (size_t)i * F;
+  constexpr int KMAX = 16;
+  double bd[KMAX];
+  int bj[KMAX];
+  for (int s = 0; s < KMAX; ++s) { bd[s] = 1e300; bj[s] = -1; }
+  const double ci0 = cen[3 * i], ci1 = cen[3 * i + 1], ci2 = cen[3 * i + 2];
+  for (int j = 0; j < n; ++j) {
+    if (j == i) continue;
+    const double d0 = cen[3 * j] - ci0, d1 = cen[3 * j + 1] - ci1, d2 = cen[3 * j + 2] - ci2;
+    const double dd = d0 * d0 + d1 * d1 + d2 * d2;
+    if (dd >= bd[k - 1]) continue;
+    int pos = k - 1;
+    while (pos > 0 && bd[pos - 1] > dd) {
+      bd[pos] = bd[pos - 1];
+      bj[pos] = bj[pos - 1];
+      --pos;
+    }
+    bd[pos] = dd;
+    bj[pos] = j;
+  }
+  const double* R = Rm + 9 * i;
+  auto rt = [&](double a0, double a1, double a2, float* o) {  // R^T a
+    o[0] = (float)(R[0] * a0 + R[3] * a1 + R[6] * a2);
+    o[1] = (float)(R[1] * a0 + R[4] * a1 + R[7] * a2);
+    o[2] = (float)(R[2] * a0 + R[5] * a1 + R[8] * a2);
+  };
+  const double* f = FT + 6 * i;
+  rt(f[0], f[1], f[2], x);
+  rt(f[3], f[4], f[5], x + 3);
+  for (int s = 0; s < S; ++s) x[6 + s] = (float)desc[(size_t)sid[i] * S + s];
+  for (int slot = 0; slot < k; ++slot) {
+    float* o = x + 6 + S + 15 * slot;
+    const int j = bj[slot];
+    if (j < 0) {
+      for (int e = 0; e < 15; ++e) o[e] = 0.f;
+      continue;
+    }
+    const double d0 = cen[3 * j] - ci0, d1 = cen[3 * j + 1] - ci1, d2 = cen[3 * j + 2] - ci2;
+    const double id2 = 1.0 / (d0 * d0 + d1 * d1 + d2 * d2);
+    rt(d0 * id2, d1 * id2, d2 * id2, o);
+    const double* Rj = Rm + 9 * j;
+    rt(Rj[0], Rj[3], Rj[6], o + 3);   // first column of R_j
+    rt(Rj[1], Rj[4], Rj[7], o + 6);   // second column of R_j
+    const double* fj = FT + 6 * j;
+    rt(fj[0], fj[1], fj[2], o + 9);
+    rt(fj[3], fj[4], fj[5], o + 12);
+  }
+}
+
+hipError_t launch_features(int n, int k, int S, const double* cen, const double* Rm,
+                           const double* FT, const int* sid, const double* desc, float* X,
+                           hipStream_t st) {
+  if (k > 16) return hipErrorInvalidValue;
+  k_features<<<(n + 63) / 64, 64, 0, st>>>(n, k, S, cen, Rm, FT, sid, desc, X);
+  return hipGetLastError();
+}
+
+// Xb[r][f] = bf16((X[src(r)][f] - mean[f]) * istd[f]); src(r) = idx ? idx[r] : r;
+// optionally Tb[r][o] = T[src(r)][o] * tinv.
+__global__ void k_gather(int rows, int F, int O, const int* idx, const float* X, const float* mean,
+                         const float* istd, uint16_t* Xb, const float* T, float tinv, float* Tb) {
+  const int r = blockIdx.y;
+  if (r >= rows) return;
+  const int src = idx ? idx[r] : r;
+  for (int f = blockIdx.x * blockDim.x + threadIdx.x; f < F; f += gridDim.x * blockDim.x)
+    Xb[(size_t)r * F + f] = f2bf((X[(size_t)src * F + f] - mean[f]) * istd[f]);
+  if (T)
+    for (int o = blockIdx.x * blockDim.x + threadIdx.x; o < O; o += gridDim.x * blockDim.x)
+      Tb[(size_t)r * O + o] = T[(size_t)src * O + o] * tinv;
+}
+
+hipError_t launch_gather(int rows, int F, int O, const int* idx, const float* X, const float* mean,
+                         const float* istd, uint16_t* Xb, const float* T, float tinv, float* Tb,
+                         hipStream_t st) {
+  if (rows < 1) return hipSuccess;
+  dim3 grid(2, rows);
+  k_gather<<<grid, 256, 0, st>>>(rows, F, O, idx, X, mean, istd, Xb, T, tinv, Tb);
+  return hipGetLastError();
+}
+
+// Column statistics over `rows` rows: mean[f] and 1/std[f] (0 for constant columns).
+__global__ __launch_bounds__(256) void k_colstats(int rows, int F, const float* X, float* mean,
+                                                  float* istd) {
+  __shared__ double red[4];
+  const int f = blockIdx.x;
+  double a = 0.0;
+  for (int r = threadIdx.x; r < rows; r += 256) a += X[(size_t)r * F + f];
+  const double mu = block_sum(a, red) / rows;
+  double b = 0.0;
+  for (int r = threadIdx.x; r < rows; r += 256) {
+    const double d = X[(size_t)r * F + f] - mu;
+    b += d * d;
+  }
+  const double var = block_sum(b, red) / rows;
+  if (threadIdx.x == 0) {
+    mean[f] = (float)mu;
+    istd[f] = var > 1e-20 ? (float)(1.0 / sqrt(var)) : 0.f;
+  }
+}
+
+hipError_t launch_colstats(int rows, int F, const float* X, float* mean, float* istd,
+                           hipStream_t st) {
+  k_colstats<<<F, 256, 0, st>>>(rows, F, X, mean, istd);
+  return hipGetLastError();
+}
+
+// RMS of cnt values into out[0] (as 1/rms in out[1]).
+__global__ __launch_bounds__(256) void k_rms(size_t cnt, const float* T, float* out) {
+  __shared__ double red[4];
+  double a = 0.0;
+  for (size_t i = threadIdx.x; i < cnt; i += 256) a += (double)T[i] * T[i];
+  const double s = block_sum(a, red);
+  if (threadIdx.x == 0) {
+    const double rms = sqrt(s / (double)(cnt > 0 ? cnt : 1));
+    out[0] = (float)(rms > 0 ? rms : 1.0);
+    out[1] = (float)(rms > 0 ? 1.0 / rms : 1.0);
+  }
+}
+
+hipError_t launch_rms(size_t cnt, const float* T, float* out, hipStream_t st) {
+  k_rms<<<1, 256, 0, st>>>(cnt, T, out);
+  return hipGetLastError();
+}
+
+// mu[:, body i] += scale * R_i Y_B(grid) coef_i  (band synthesis of a body-frame density)
+__global__ void k_band_synth(int n, int M, int p, const float* coef, const float* scale,
+                             const double* Ytab, const double* Rm, double* mu) {
+  const size_t N = (size_t)n * M;
+  const size_t g = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= N) return;
+  const int i = (int)(g / M), a = (int)(g % M);
+  const int nB = p * p + 2 * p;
+  const float* cf = coef + (size_t)i * 3 * nB;
+  double v[3] = {0, 0, 0};
+  for (int b = 0; b < nB; ++b) {
+    const int full = b < p * p ? b : b + 1;
+    const double y = Ytab[(size_t)full * M + a];
+    v[0] += y * cf[b];
+    v[1] += y * cf[nB + b];
+    v[2] += y * cf[2 * nB + b];
+  }
+  const double sc = scale ? (double)scale[0] : 1.0;
+  const double* R = Rm + 9 * i;
+  for (int c = 0; c < 3; ++c)
+    mu[c * N + g] += sc * (R[3 * c] * v[0] + R[3 * c + 1] * v[1] + R[3 * c + 2] * v[2]);
+}
+
+hipError_t launch_band_synth(int n, int M, int p, const float* coef, const float* scale,
+                             const double* Ytab, const double* Rm, double* mu, hipStream_t st) {
+  const size_t N = (size_t)n * M;
+  k_band_synth<<<(unsigned)((N + 255) / 256), 256, 0, st>>>(n, M, p, coef, scale, Ytab, Rm, mu);
+  return hipGetLastError();
+}
+
+// out[i][c][b] = sum_a F[b][a] (R_i^T dmu)[c][a]  (body-frame band coefficients), fp32 out.
+__global__ __launch_bounds__(256) void k_band_analysis(int n, int M, int p, const double* dmu,
+                                                       const double* Rm, const double* Ftab,
+                                                       float* out) {
+  extern __shared__ double bodyv[];  // [3][M]
+  const size_t N = (size_t)n * M;
+  const int i = blockIdx.x;
+  const int nB = p * p + 2 * p;
+  const double* R = Rm + 9 * i;
+  for (int a = threadIdx.x; a < M; a += 256) {
+    const size_t g = (size_t)i * M + a;
+    const double v0 = dmu[g], v1 = dmu[N + g], v2 = dmu[2 * N + g];
+    bodyv[a] = R[0] * v0 + R[3] * v1 + R[6] * v2;
+    bodyv[M + a] = R[1] * v0 + R[4] * v1 + R[7] * v2;
+    bodyv[2 * M + a] = R[2] * v0 + R[5] * v1 + R[8] * v2;
+  }
+  __syncthreads();
+  for (int b = threadIdx.x; b < nB; b += 256) {
+    double s0 = 0, s1 = 0, s2 = 0;
+    for (int a = 0; a < M; ++a) {
+      const double f = Ftab[(size_t)b * M + a];
+      s0 += f * bodyv[a];
+      s1 += f * bodyv[M + a];
+      s2 += f * bodyv[2 * M + a];
+    }
+    float* o = out + (size_t)i * 3 * nB;
+    o[b] = (float)s0;
+    o[nB + b] = (float)s1;
+    o[2 * nB + b] = (float)s2;
+  }
+}
+
+hipError_t launch_band_analysis(int n, int M, int p, const double* dmu, const double* Rm,
+                                const double* Ftab, float* out, hipStream_t st) {
+  k_band_analysis<<<n, 256, 3 * M * sizeof(double), st>>>(n, M, p, dmu, Rm, Ftab, out);
+  return hipGetLastError();
+}
+
+}  // namespace rbm

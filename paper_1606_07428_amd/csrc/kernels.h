@@ -107,4 +107,33 @@ hipError_t launch_backsolve(int m, int ldh, const double* H, const double* g, do
                             hipStream_t st);
 hipError_t launch_dots_final_sqrt(int nblk, const double* partial, double* h, hipStream_t st);
 
+// ---- learned warm start (k_mlp.hip) --------------------------------------------------
+hipError_t launch_gemm_bf16(int m, int n, int k, const uint16_t* A, long sa0, long sa1,
+                            const uint16_t* B, long sb0, long sb1, float* C, int ldc,
+                            const float* bias, float alpha, float beta, hipStream_t st);
+hipError_t launch_silu_fwd(size_t cnt, const float* Z, float* H, uint16_t* Hb, hipStream_t st);
+hipError_t launch_silu_bwd(size_t cnt, const float* dH, const float* Z, float* dZ, uint16_t* dZb,
+                           hipStream_t st);
+hipError_t launch_mse(size_t cnt, float inv, const float* Y, const float* T, float* dY,
+                      uint16_t* dYb, double* part, hipStream_t st);
+hipError_t launch_sum_parts(int nparts, const double* part, double scale, double* out,
+                            hipStream_t st);
+hipError_t launch_colsum(int rows, int cols, const float* dZ, float* db, hipStream_t st);
+hipError_t launch_adam(size_t cnt, float* P, const float* G, float* m, float* v, float lr, float b1,
+                       float b2, float eps, int t, uint16_t* Pb, hipStream_t st);
+hipError_t launch_to_bf16(size_t cnt, const float* x, uint16_t* y, hipStream_t st);
+hipError_t launch_features(int n, int k, int S, const double* cen, const double* Rm,
+                           const double* FT, const int* sid, const double* desc, float* X,
+                           hipStream_t st);
+hipError_t launch_gather(int rows, int F, int O, const int* idx, const float* X, const float* mean,
+                         const float* istd, uint16_t* Xb, const float* T, float tinv, float* Tb,
+                         hipStream_t st);
+hipError_t launch_colstats(int rows, int F, const float* X, float* mean, float* istd,
+                           hipStream_t st);
+hipError_t launch_rms(size_t cnt, const float* T, float* out, hipStream_t st);
+hipError_t launch_band_synth(int n, int M, int p, const float* coef, const float* scale,
+                             const double* Ytab, const double* Rm, double* mu, hipStream_t st);
+hipError_t launch_band_analysis(int n, int M, int p, const double* dmu, const double* Rm,
+                                const double* Ftab, float* out, hipStream_t st);
+
 }  // namespace rbm

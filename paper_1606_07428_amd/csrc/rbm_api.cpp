@@ -68,6 +68,22 @@ struct rbm_ctx {
   void* src;
   double* part;
   double* pinned = nullptr;
+  // learned warm start
+  struct Learned {
+    bool bound = false, stats_ready = false, capture_on = false;
+    rbm_learned_config cfg;
+    int F = 0, O = 0, S = 0, L = 0, rows_max = 0, count = 0, t = 0, epoch = 0;
+    std::vector<int> dims;
+    std::vector<size_t> woff, boff;
+    size_t nparam = 0;
+    float *P, *G, *Mo, *Vo, *mean, *istd, *tsc, *Xbuf, *Tbuf, *Tb, *dA, *feats, *Yout;
+    uint16_t *Wb, *Xb;
+    int* idx;
+    double *lpart, *lsum;
+    std::vector<float*> Z, H, dZ;
+    std::vector<uint16_t*> Hb, dZb;
+  } L;
+  double bd_ratio = -1.0;
   // events for timing
   std::vector<hipEvent_t> ev;
   int ev_used = 0;
@@ -100,7 +116,7 @@ extern "C" rbm_status rbm_create(const rbm_options* opt, rbm_ctx** out) {
   if (opt->max_iter < 1 || opt->max_iter > 400) return fail(RBM_E_INVAL, "max_iter in [1, 400]");
   if (opt->max_restart < 0) return fail(RBM_E_INVAL, "max_restart >= 0");
   if (opt->precision < 0 || opt->precision > 2) return fail(RBM_E_INVAL, "bad precision");
-  if (opt->guess < 0 || opt->guess > 2) return fail(RBM_E_INVAL, "bad guess");
+  if (opt->guess < 0 || opt->guess > 3) return fail(RBM_E_INVAL, "bad guess");
   rbm_ctx* c = new rbm_ctx();
   c->opt = *opt;
   if (!(c->opt.inner_tol > 0.0)) c->opt.inner_tol = 1e-4;
@@ -489,6 +505,27 @@ static rbm_status gmres_cycle(rbm_ctx* c, SolveState& S, int prec, const double*
   return RBM_OK;
 }
 
+static rbm_status learned_correction(rbm_ctx* c, const double* dFT);
+static rbm_status learned_capture(rbm_ctx* c, const double* dFT);
+
+// Incident density (§2.2) and right-hand side b = -(A_self rho - L rho + K_far rho).
+static rbm_status build_rhs(rbm_ctx* c, SolveState& S, const double* dFT, double* bnorm) {
+  hipStream_t st = c->st;
+  const int n = c->n, M = c->M, N = n * M;
+  rbm_status s;
+  HIPCHECK(launch_rho(n, M, dFT, c->cen, c->X, c->tauinv, c->area_b, c->rho, st));
+  if ((s = self_apply(c, S, 0, 0, c->rho, c->yb)) != RBM_OK) return s;
+  if ((s = far_traction(c, S, c->rho, 0, 0)) != RBM_OK) return s;
+  HIPCHECK(launch_combine(N, M, split_for(c, N), c->part, -1.0, nullptr, 0.0, c->yb, c->Rm, -1.0, c->b, st));
+  HIPCHECK(launch_moments(n, M, c->rho, c->X, c->W, c->cen, c->mom, st));
+  HIPCHECK(launch_add_rigid(n, M, c->mom, c->X, c->cen, 1.0, c->b, st));
+  S.matvecs++;
+  if ((s = norm_into(c, c->b, c->scal + 1)) != RBM_OK) return s;
+  if ((s = read_scalar(c, c->scal + 1, bnorm)) != RBM_OK) return s;
+  if (!std::isfinite(*bnorm)) return fail(RBM_E_INVAL, "non-finite right-hand side");
+  return RBM_OK;
+}
+
 static rbm_status solve_impl(rbm_ctx* c, const double* dFT, double* dVW, rbm_solve_info* info) {
   if (!c->ws) return fail(RBM_E_NOMEM, "bind a workspace first");
   if (!c->setup_done) return fail(RBM_E_STATE, "call rbm_setup first");
@@ -501,34 +538,34 @@ static rbm_status solve_impl(rbm_ctx* c, const double* dFT, double* dVW, rbm_sol
   SolveState S;
   c->ev_used = 0;
   Timer total(c);
-  // incident density and right-hand side b = -(A_self rho - L rho + K_far rho)
-  HIPCHECK(launch_rho(n, M, dFT, c->cen, c->X, c->tauinv, c->area_b, c->rho, st));
-  if ((s = self_apply(c, S, 0, 0, c->rho, c->yb)) != RBM_OK) return s;
-  if ((s = far_traction(c, S, c->rho, 0, 0)) != RBM_OK) return s;
-  HIPCHECK(launch_combine(N, M, split_for(c, N), c->part, -1.0, nullptr, 0.0, c->yb, c->Rm, -1.0, c->b, st));
-  HIPCHECK(launch_moments(n, M, c->rho, c->X, c->W, c->cen, c->mom, st));
-  HIPCHECK(launch_add_rigid(n, M, c->mom, c->X, c->cen, 1.0, c->b, st));
-  S.matvecs++;
   double bnorm;
-  if ((s = norm_into(c, c->b, c->scal + 1)) != RBM_OK) return s;
-  if ((s = read_scalar(c, c->scal + 1, &bnorm)) != RBM_OK) return s;
-  if (!std::isfinite(bnorm)) return fail(RBM_E_INVAL, "non-finite right-hand side");
+  if ((s = build_rhs(c, S, dFT, &bnorm)) != RBM_OK) return s;
   const double abs_tol = c->opt.tol * bnorm;
   const int prec = c->opt.precision;
   // initial guess
-  bool mu_zero = false;
+  bool mu_zero = false, learned_active = false;
+  int guess_used = c->opt.guess, fallback = 0;
   if (bnorm == 0.0 || c->opt.guess == RBM_GUESS_ZERO) {
     HIPCHECK(hipMemsetAsync(c->mu, 0, len * sizeof(double), st));
     mu_zero = true;
-  } else if (c->opt.guess == RBM_GUESS_BLOCKDIAG) {
+    guess_used = RBM_GUESS_ZERO;
+  } else if (c->opt.guess == RBM_GUESS_BLOCKDIAG || c->opt.guess == RBM_GUESS_LEARNED) {
+    // block-diagonal (isolated-particle) guess mu_BD = P^{-1} b (§3.2 preconditioner)
     if ((s = self_apply(c, S, 1, prec, c->b, c->yb)) != RBM_OK) return s;
     HIPCHECK(launch_combine(N, M, 0, nullptr, 0.0, nullptr, 0.0, c->yb, c->Rm, 1.0, c->mu, st));
+    if (c->opt.guess == RBM_GUESS_LEARNED && c->L.bound && c->L.stats_ready) {
+      HIPCHECK(hipMemcpyAsync(c->t2, c->mu, len * sizeof(double), hipMemcpyDeviceToDevice, st));
+      if ((s = learned_correction(c, dFT)) != RBM_OK) return s;
+      learned_active = true;
+    } else {
+      guess_used = RBM_GUESS_BLOCKDIAG;
+    }
   } else {
     if (!c->guess_set) return fail(RBM_E_STATE, "RBM_GUESS_USER needs rbm_set_guess_dev");
     HIPCHECK(hipMemcpyAsync(c->mu, c->guess, len * sizeof(double), hipMemcpyDeviceToDevice, st));
   }
   int total_iters = 0, cycles = 0, refinements = 0;
-  double rel = 0.0;
+  double rel = 0.0, init_rel = 0.0;
   bool converged = false;
   const int max_outer = prec == 0 ? c->opt.max_restart + 1 : 50;
   for (int outer = 0; outer <= max_outer; ++outer) {
@@ -543,6 +580,31 @@ static rbm_status solve_impl(rbm_ctx* c, const double* dFT, double* dVW, rbm_sol
       HIPCHECK(launch_axpby(len, 1.0, c->b, -1.0, c->t1, c->r, st));
       if ((s = norm_into(c, c->r, c->scal + 2)) != RBM_OK) return s;
       if ((s = read_scalar(c, c->scal + 2, &rn)) != RBM_OK) return s;
+    }
+    if (outer == 0 && bnorm > 0.0) {
+      if (learned_active) {
+        // fallback test against the block-diagonal guess's residual ratio
+        if (c->bd_ratio < 0.0) {
+          if ((s = apply_A(c, S, c->t2, c->t1)) != RBM_OK) return s;
+          HIPCHECK(launch_axpby(len, 1.0, c->b, -1.0, c->t1, c->t1, st));
+          double rbd;
+          if ((s = norm_into(c, c->t1, c->scal + 3)) != RBM_OK) return s;
+          if ((s = read_scalar(c, c->scal + 3, &rbd)) != RBM_OK) return s;
+          c->bd_ratio = rbd / bnorm;
+        }
+        if (!(rn <= c->bd_ratio * bnorm)) {
+          fallback = 1;
+          HIPCHECK(hipMemcpyAsync(c->mu, c->t2, len * sizeof(double), hipMemcpyDeviceToDevice, st));
+          if ((s = apply_A(c, S, c->mu, c->t1)) != RBM_OK) return s;
+          HIPCHECK(launch_axpby(len, 1.0, c->b, -1.0, c->t1, c->r, st));
+          if ((s = norm_into(c, c->r, c->scal + 2)) != RBM_OK) return s;
+          if ((s = read_scalar(c, c->scal + 2, &rn)) != RBM_OK) return s;
+          c->bd_ratio = rn / bnorm;
+        }
+      } else if (guess_used == RBM_GUESS_BLOCKDIAG) {
+        c->bd_ratio = rn / bnorm;
+      }
+      init_rel = rn / bnorm;
     }
     rel = bnorm > 0.0 ? rn / bnorm : 0.0;
     if (rn <= abs_tol || bnorm == 0.0) { converged = true; break; }
@@ -572,8 +634,13 @@ static rbm_status solve_impl(rbm_ctx* c, const double* dFT, double* dVW, rbm_sol
   total.stop();
   HIPCHECK(hipStreamSynchronize(st));
   c->have_solution = true;
+  if (c->L.bound && c->L.capture_on)
+    if ((s = learned_capture(c, dFT)) != RBM_OK) return s;
   if (info) {
     std::memset(info, 0, sizeof(*info));
+    info->guess_used = guess_used;
+    info->fallback_used = fallback;
+    info->init_rel_residual = init_rel;
     info->iters = total_iters;
     info->matvecs = S.matvecs;
     info->refinements = refinements;
@@ -665,6 +732,8 @@ extern "C" const void* rbm_debug_ptr(rbm_ctx* c, const char* name) {
   if (s == "Rm") return c->Rm;
   if (s == "Ftab") return c->Ftab;
   if (s == "Ytab") return c->Ytab;
+  if (s == "learned_X") return c->L.bound ? c->L.Xbuf : nullptr;
+  if (s == "learned_T") return c->L.bound ? c->L.Tbuf : nullptr;
   return nullptr;
 }
 
@@ -772,5 +841,380 @@ extern "C" rbm_status rbm_get_bodies(rbm_ctx* c, double* centre, double* quat) {
   if (c->n < 1) return fail(RBM_E_STATE, "set bodies first");
   std::memcpy(centre, c->cen_h.data(), 3 * c->n * sizeof(double));
   std::memcpy(quat, c->quat_h.data(), 4 * c->n * sizeof(double));
+  return RBM_OK;
+}
+
+// ---------------------------------------------------------------------------------
+// Learned warm start
+
+#include <random>
+
+extern "C" void rbm_learned_default_config(rbm_learned_config* cfg) {
+  std::memset(cfg, 0, sizeof(*cfg));
+  cfg->k_nbr = 8;
+  cfg->hidden = 256;
+  cfg->n_hidden = 3;
+  cfg->capacity = 65536;
+  cfg->batch_max = 1024;
+  cfg->seed = 1234;
+}
+
+static size_t learned_layout(rbm_ctx* c, const rbm_learned_config& cfg, char* base, bool assign) {
+  auto& L = c->L;
+  const int S = c->shape_kind == 1 ? (c->shape_lmax + 1) * (c->shape_lmax + 1) : 0;
+  const int F = 6 + S + 15 * cfg.k_nbr, O = 3 * c->nB;
+  std::vector<int> dims;
+  dims.push_back(F);
+  for (int h = 0; h < cfg.n_hidden; ++h) dims.push_back(cfg.hidden);
+  dims.push_back(O);
+  const int nl = (int)dims.size() - 1;
+  std::vector<size_t> woff(nl), boff(nl);
+  size_t np = 0;
+  for (int l = 0; l < nl; ++l) {
+    woff[l] = np;
+    np += (size_t)dims[l] * dims[l + 1];
+    boff[l] = np;
+    np += dims[l + 1];
+  }
+  const int rows = std::max(cfg.batch_max, c->nmax);
+  int maxw = 0;
+  for (int d : dims) maxw = std::max(maxw, d);
+  if (assign) {
+    L.S = S; L.F = F; L.O = O; L.L = nl; L.dims = dims; L.woff = woff; L.boff = boff;
+    L.nparam = np; L.rows_max = rows; L.Z.assign(nl, nullptr); L.H.assign(nl, nullptr);
+    L.dZ.assign(nl, nullptr); L.Hb.assign(nl, nullptr); L.dZb.assign(nl, nullptr);
+  }
+  size_t off = 0;
+  auto take = [&](auto*& ptr, size_t count) {
+    using T = std::remove_reference_t<decltype(*ptr)>;
+    off = (off + 255) & ~(size_t)255;
+    if (assign) ptr = reinterpret_cast<T*>(base + off);
+    off += count * sizeof(T);
+  };
+  float *P, *G, *Mo, *Vo, *mean, *istd, *tsc, *Xbuf, *Tbuf, *Tb, *dA, *feats, *Yout;
+  uint16_t *Wb, *Xb;
+  int* idx;
+  double *lpart, *lsum;
+  take(P, np); take(G, np); take(Mo, np); take(Vo, np); take(Wb, np);
+  take(mean, F); take(istd, F); take(tsc, 2);
+  take(Xbuf, (size_t)cfg.capacity * F); take(Tbuf, (size_t)cfg.capacity * O);
+  take(idx, cfg.capacity);
+  take(Xb, (size_t)rows * F); take(Tb, (size_t)rows * O);
+  take(dA, (size_t)rows * maxw); take(feats, (size_t)c->nmax * F); take(Yout, (size_t)rows * O);
+  take(lpart, (size_t)rows * O / 256 + 2); take(lsum, 4);
+  std::vector<float*> Z(nl), H(nl), dZ(nl);
+  std::vector<uint16_t*> Hb(nl), dZb(nl);
+  for (int l = 0; l < nl; ++l) {
+    const size_t cnt = (size_t)rows * dims[l + 1];
+    take(Z[l], cnt); take(H[l], cnt); take(dZ[l], cnt); take(Hb[l], cnt); take(dZb[l], cnt);
+  }
+  if (assign) {
+    L.P = P; L.G = G; L.Mo = Mo; L.Vo = Vo; L.Wb = Wb; L.mean = mean; L.istd = istd; L.tsc = tsc;
+    L.Xbuf = Xbuf; L.Tbuf = Tbuf; L.idx = idx; L.Xb = Xb; L.Tb = Tb; L.dA = dA; L.feats = feats;
+    L.Yout = Yout; L.lpart = lpart; L.lsum = lsum; L.Z = Z; L.H = H; L.dZ = dZ; L.Hb = Hb;
+    L.dZb = dZb;
+  }
+  return off + 256;
+}
+
+static rbm_status check_cfg(rbm_ctx* c, const rbm_learned_config* cfg) {
+  if (!c || !cfg) return fail(RBM_E_INVAL, "null argument");
+  if (!c->ws) return fail(RBM_E_NOMEM, "bind the solver workspace first");
+  if (cfg->k_nbr < 1 || cfg->k_nbr > 16) return fail(RBM_E_INVAL, "k_nbr in [1, 16]");
+  if (cfg->hidden < 1 || cfg->hidden > 4096) return fail(RBM_E_INVAL, "hidden in [1, 4096]");
+  if (cfg->n_hidden < 1 || cfg->n_hidden > 6) return fail(RBM_E_INVAL, "n_hidden in [1, 6]");
+  if (cfg->capacity < 1 || cfg->batch_max < 1) return fail(RBM_E_INVAL, "capacity, batch_max >= 1");
+  return RBM_OK;
+}
+
+extern "C" rbm_status rbm_learned_workspace_size(rbm_ctx* c, const rbm_learned_config* cfg,
+                                                 size_t* bytes) {
+  rbm_status s = check_cfg(c, cfg);
+  if (s != RBM_OK) return s;
+  if (!bytes) return fail(RBM_E_INVAL, "null argument");
+  *bytes = learned_layout(c, *cfg, nullptr, false);
+  return RBM_OK;
+}
+
+extern "C" rbm_status rbm_learned_bind(rbm_ctx* c, const rbm_learned_config* cfg, void* dptr,
+                                       size_t bytes) {
+  rbm_status s = check_cfg(c, cfg);
+  if (s != RBM_OK) return s;
+  if (!dptr || ((uintptr_t)dptr & 255)) return fail(RBM_E_INVAL, "workspace must be 256-byte aligned");
+  if (learned_layout(c, *cfg, nullptr, false) > bytes) return fail(RBM_E_NOMEM, "learned workspace too small");
+  learned_layout(c, *cfg, (char*)dptr, true);
+  auto& L = c->L;
+  L.cfg = *cfg;
+  L.bound = true;
+  L.stats_ready = false;
+  L.count = 0;
+  L.t = 0;
+  L.epoch = 0;
+  // weights ~ N(0, 1/fan_in) (last layer 0.1/fan_in), biases 0
+  std::vector<float> P(L.nparam, 0.f);
+  std::mt19937_64 rng(cfg->seed);
+  std::normal_distribution<double> nd(0.0, 1.0);
+  for (int l = 0; l < L.L; ++l) {
+    const double sd = (l == L.L - 1 ? 0.1 : 1.0) / std::sqrt((double)L.dims[l]);
+    for (size_t i = 0; i < (size_t)L.dims[l] * L.dims[l + 1]; ++i) P[L.woff[l] + i] = (float)(sd * nd(rng));
+  }
+  HIPCHECK(hipMemcpyAsync(L.P, P.data(), P.size() * sizeof(float), hipMemcpyHostToDevice, c->st));
+  HIPCHECK(hipMemsetAsync(L.Mo, 0, L.nparam * sizeof(float), c->st));
+  HIPCHECK(hipMemsetAsync(L.Vo, 0, L.nparam * sizeof(float), c->st));
+  HIPCHECK(launch_to_bf16(L.nparam, L.P, L.Wb, c->st));
+  std::vector<float> ms(2 * L.F + 2, 0.f);
+  for (int f = 0; f < L.F; ++f) ms[L.F + f] = 1.f;
+  ms[2 * L.F] = 1.f;
+  ms[2 * L.F + 1] = 1.f;
+  HIPCHECK(hipMemcpyAsync(L.mean, ms.data(), L.F * sizeof(float), hipMemcpyHostToDevice, c->st));
+  HIPCHECK(hipMemcpyAsync(L.istd, ms.data() + L.F, L.F * sizeof(float), hipMemcpyHostToDevice, c->st));
+  HIPCHECK(hipMemcpyAsync(L.tsc, ms.data() + 2 * L.F, 2 * sizeof(float), hipMemcpyHostToDevice, c->st));
+  HIPCHECK(hipStreamSynchronize(c->st));
+  return RBM_OK;
+}
+
+// Forward pass on `rows` rows of L.Xb (bf16, standardized); output in L.Z[last].
+static rbm_status mlp_forward(rbm_ctx* c, int rows) {
+  auto& L = c->L;
+  const uint16_t* A = L.Xb;
+  for (int l = 0; l < L.L; ++l) {
+    const int in = L.dims[l], out = L.dims[l + 1];
+    HIPCHECK(launch_gemm_bf16(rows, out, in, A, in, 1, L.Wb + L.woff[l], out, 1, L.Z[l], out,
+                              L.P + L.boff[l], 1.f, 0.f, c->st));
+    if (l < L.L - 1) {
+      HIPCHECK(launch_silu_fwd((size_t)rows * out, L.Z[l], L.H[l], L.Hb[l], c->st));
+      A = L.Hb[l];
+    }
+  }
+  return RBM_OK;
+}
+
+// Loss against L.Tb (scaled targets) and gradients into L.G; loss value in L.lsum[0].
+static rbm_status mlp_backward(rbm_ctx* c, int rows) {
+  auto& L = c->L;
+  const int last = L.L - 1, O = L.dims[last + 1];
+  const size_t cnt = (size_t)rows * O;
+  const int nparts = (int)((cnt + 255) / 256);
+  HIPCHECK(launch_mse(cnt, 1.f / (float)cnt, L.Z[last], L.Tb, L.dZ[last], L.dZb[last], L.lpart, c->st));
+  HIPCHECK(launch_sum_parts(nparts, L.lpart, 1.0 / (double)cnt, L.lsum, c->st));
+  for (int l = last; l >= 0; --l) {
+    const int in = L.dims[l], out = L.dims[l + 1];
+    const uint16_t* Aprev = l == 0 ? L.Xb : L.Hb[l - 1];
+    // dW = Aprev^T dZ (in x out), db = colsum(dZ)
+    HIPCHECK(launch_gemm_bf16(in, out, rows, Aprev, 1, in, L.dZb[l], out, 1, L.G + L.woff[l], out,
+                              nullptr, 1.f, 0.f, c->st));
+    HIPCHECK(launch_colsum(rows, out, L.dZ[l], L.G + L.boff[l], c->st));
+    if (l > 0) {
+      // dA = dZ W^T (rows x in), then dZ_{l-1} = dA * silu'(Z_{l-1})
+      HIPCHECK(launch_gemm_bf16(rows, in, out, L.dZb[l], out, 1, L.Wb + L.woff[l], 1, out, L.dA, in,
+                                nullptr, 1.f, 0.f, c->st));
+      HIPCHECK(launch_silu_bwd((size_t)rows * in, L.dA, L.Z[l - 1], L.dZ[l - 1], L.dZb[l - 1], c->st));
+    }
+  }
+  return RBM_OK;
+}
+
+static rbm_status learned_correction(rbm_ctx* c, const double* dFT) {
+  auto& L = c->L;
+  const int n = c->n;
+  if (n > L.rows_max) return fail(RBM_E_NOMEM, "more bodies than the learned workspace holds");
+  const double* desc = L.S > 0 ? c->rcbuf : nullptr;
+  HIPCHECK(launch_features(n, L.cfg.k_nbr, L.S, c->cen, c->Rm, dFT, c->sid, desc, L.feats, c->st));
+  HIPCHECK(launch_gather(n, L.F, L.O, nullptr, L.feats, L.mean, L.istd, L.Xb, nullptr, 1.f, nullptr, c->st));
+  rbm_status s;
+  if ((s = mlp_forward(c, n)) != RBM_OK) return s;
+  HIPCHECK(launch_band_synth(n, c->M, c->p, L.Z[L.L - 1], L.tsc, c->Ytab, c->Rm, c->mu, c->st));
+  return RBM_OK;
+}
+
+static rbm_status learned_capture(rbm_ctx* c, const double* dFT) {
+  auto& L = c->L;
+  const int n = c->n, M = c->M, N = n * M;
+  const size_t len = 3 * (size_t)N;
+  if (L.count + n > L.cfg.capacity) return RBM_OK;  // buffer full
+  const double* desc = L.S > 0 ? c->rcbuf : nullptr;
+  HIPCHECK(launch_features(n, L.cfg.k_nbr, L.S, c->cen, c->Rm, dFT, c->sid, desc,
+                           L.Xbuf + (size_t)L.count * L.F, c->st));
+  // target: body-frame band coefficients of mu - mu_BD, mu_BD = P^{-1} b in float64
+  HIPCHECK(launch_self_apply<double>(n, M, c->sid, c->P0, c->Rm, c->b, c->yb, c->st));
+  HIPCHECK(launch_combine(N, M, 0, nullptr, 0.0, c->mu, 1.0, c->yb, c->Rm, -1.0, c->t1, c->st));
+  HIPCHECK(launch_band_analysis(n, M, c->p, c->t1, c->Rm, c->Ftab, L.Tbuf + (size_t)L.count * L.O, c->st));
+  HIPCHECK(hipStreamSynchronize(c->st));
+  (void)len;
+  L.count += n;
+  return RBM_OK;
+}
+
+extern "C" rbm_status rbm_learned_capture(rbm_ctx* c, const double* d_FT) {
+  if (!c || !d_FT) return fail(RBM_E_INVAL, "null argument");
+  if (!c->L.bound) return fail(RBM_E_STATE, "bind the learned workspace first");
+  if (!c->have_solution) return fail(RBM_E_STATE, "no solve to capture");
+  return learned_capture(c, d_FT);
+}
+
+extern "C" rbm_status rbm_learned_set_capture(rbm_ctx* c, int on) {
+  if (!c) return fail(RBM_E_INVAL, "null argument");
+  if (!c->L.bound) return fail(RBM_E_STATE, "bind the learned workspace first");
+  c->L.capture_on = on != 0;
+  return RBM_OK;
+}
+
+extern "C" rbm_status rbm_learned_train(rbm_ctx* c, int epochs, int batch, double lr, double* loss) {
+  if (!c) return fail(RBM_E_INVAL, "null argument");
+  auto& L = c->L;
+  if (!L.bound) return fail(RBM_E_STATE, "bind the learned workspace first");
+  if (L.count < 1) return fail(RBM_E_STATE, "no captured samples");
+  if (epochs < 0 || batch < 1 || batch > L.rows_max || !(lr > 0.0))
+    return fail(RBM_E_INVAL, "bad training arguments");
+  hipStream_t st = c->st;
+  if (!L.stats_ready) {
+    HIPCHECK(launch_colstats(L.count, L.F, L.Xbuf, L.mean, L.istd, st));
+    HIPCHECK(launch_rms((size_t)L.count * L.O, L.Tbuf, L.tsc, st));
+    L.stats_ready = true;
+  }
+  float tsc[2];
+  HIPCHECK(hipMemcpyAsync(tsc, L.tsc, 2 * sizeof(float), hipMemcpyDeviceToHost, st));
+  HIPCHECK(hipStreamSynchronize(st));
+  std::vector<int> perm(L.count);
+  double last = 0.0;
+  for (int e = 0; e < epochs; ++e) {
+    std::mt19937_64 rng(L.cfg.seed * 1000003ULL + (unsigned long long)(++L.epoch));
+    for (int i = 0; i < L.count; ++i) perm[i] = i;
+    std::shuffle(perm.begin(), perm.end(), rng);
+    HIPCHECK(hipMemcpyAsync(L.idx, perm.data(), L.count * sizeof(int), hipMemcpyHostToDevice, st));
+    double acc = 0.0;
+    int nb = 0;
+    for (int off = 0; off < L.count; off += batch) {
+      const int rows = std::min(batch, L.count - off);
+      HIPCHECK(launch_gather(rows, L.F, L.O, L.idx + off, L.Xbuf, L.mean, L.istd, L.Xb, L.Tbuf,
+                             tsc[1], L.Tb, st));
+      rbm_status s;
+      if ((s = mlp_forward(c, rows)) != RBM_OK) return s;
+      if ((s = mlp_backward(c, rows)) != RBM_OK) return s;
+      HIPCHECK(launch_adam(L.nparam, L.P, L.G, L.Mo, L.Vo, (float)lr, 0.9f, 0.999f, 1e-8f, ++L.t,
+                           L.Wb, st));
+      double lv;
+      if ((s = read_scalar(c, L.lsum, &lv)) != RBM_OK) return s;
+      acc += lv;
+      ++nb;
+    }
+    last = acc / nb;
+  }
+  HIPCHECK(hipStreamSynchronize(st));
+  if (loss) *loss = last;
+  return RBM_OK;
+}
+
+extern "C" rbm_status rbm_learned_info(rbm_ctx* c, int* samples, int* n_features, int* n_outputs,
+                                       int* n_params) {
+  if (!c) return fail(RBM_E_INVAL, "null argument");
+  if (!c->L.bound) return fail(RBM_E_STATE, "bind the learned workspace first");
+  if (samples) *samples = c->L.count;
+  if (n_features) *n_features = c->L.F;
+  if (n_outputs) *n_outputs = c->L.O;
+  if (n_params) *n_params = (int)c->L.nparam;
+  return RBM_OK;
+}
+
+extern "C" rbm_status rbm_learned_get_params(rbm_ctx* c, float* host, size_t count) {
+  if (!c || !host) return fail(RBM_E_INVAL, "null argument");
+  auto& L = c->L;
+  if (!L.bound) return fail(RBM_E_STATE, "bind the learned workspace first");
+  if (count != L.nparam + 2 * L.F + 2) return fail(RBM_E_INVAL, "count must be n_params + 2F + 2");
+  HIPCHECK(hipStreamSynchronize(c->st));
+  HIPCHECK(hipMemcpy(host, L.P, L.nparam * sizeof(float), hipMemcpyDeviceToHost));
+  HIPCHECK(hipMemcpy(host + L.nparam, L.mean, L.F * sizeof(float), hipMemcpyDeviceToHost));
+  HIPCHECK(hipMemcpy(host + L.nparam + L.F, L.istd, L.F * sizeof(float), hipMemcpyDeviceToHost));
+  HIPCHECK(hipMemcpy(host + L.nparam + 2 * L.F, L.tsc, 2 * sizeof(float), hipMemcpyDeviceToHost));
+  return RBM_OK;
+}
+
+extern "C" rbm_status rbm_learned_set_params(rbm_ctx* c, const float* host, size_t count) {
+  if (!c || !host) return fail(RBM_E_INVAL, "null argument");
+  auto& L = c->L;
+  if (!L.bound) return fail(RBM_E_STATE, "bind the learned workspace first");
+  if (count != L.nparam + 2 * L.F + 2) return fail(RBM_E_INVAL, "count must be n_params + 2F + 2");
+  for (size_t i = 0; i < count; ++i)
+    if (!std::isfinite(host[i])) return fail(RBM_E_INVAL, "non-finite parameter");
+  HIPCHECK(hipMemcpy(L.P, host, L.nparam * sizeof(float), hipMemcpyHostToDevice));
+  HIPCHECK(hipMemcpy(L.mean, host + L.nparam, L.F * sizeof(float), hipMemcpyHostToDevice));
+  HIPCHECK(hipMemcpy(L.istd, host + L.nparam + L.F, L.F * sizeof(float), hipMemcpyHostToDevice));
+  HIPCHECK(hipMemcpy(L.tsc, host + L.nparam + 2 * L.F, 2 * sizeof(float), hipMemcpyHostToDevice));
+  HIPCHECK(launch_to_bf16(L.nparam, L.P, L.Wb, c->st));
+  HIPCHECK(hipStreamSynchronize(c->st));
+  L.stats_ready = true;
+  return RBM_OK;
+}
+
+extern "C" rbm_status rbm_learned_forward_dev(rbm_ctx* c, const float* d_X, int rows, float* d_Y) {
+  if (!c || !d_X || !d_Y) return fail(RBM_E_INVAL, "null argument");
+  auto& L = c->L;
+  if (!L.bound) return fail(RBM_E_STATE, "bind the learned workspace first");
+  if (rows < 1 || rows > L.rows_max) return fail(RBM_E_INVAL, "rows out of range");
+  HIPCHECK(launch_gather(rows, L.F, L.O, nullptr, d_X, L.mean, L.istd, L.Xb, nullptr, 1.f, nullptr, c->st));
+  rbm_status s;
+  if ((s = mlp_forward(c, rows)) != RBM_OK) return s;
+  HIPCHECK(hipMemcpyAsync(d_Y, L.Z[L.L - 1], (size_t)rows * L.O * sizeof(float),
+                          hipMemcpyDeviceToDevice, c->st));
+  HIPCHECK(hipStreamSynchronize(c->st));
+  return RBM_OK;
+}
+
+extern "C" rbm_status rbm_learned_loss_grad_dev(rbm_ctx* c, const float* d_X, const float* d_T,
+                                                int rows, float* d_grad, double* loss) {
+  if (!c || !d_X || !d_T || !d_grad) return fail(RBM_E_INVAL, "null argument");
+  auto& L = c->L;
+  if (!L.bound) return fail(RBM_E_STATE, "bind the learned workspace first");
+  if (rows < 1 || rows > L.rows_max) return fail(RBM_E_INVAL, "rows out of range");
+  float tsc[2];
+  HIPCHECK(hipMemcpyAsync(tsc, L.tsc, 2 * sizeof(float), hipMemcpyDeviceToHost, c->st));
+  HIPCHECK(hipStreamSynchronize(c->st));
+  HIPCHECK(launch_gather(rows, L.F, L.O, nullptr, d_X, L.mean, L.istd, L.Xb, d_T, tsc[1], L.Tb, c->st));
+  rbm_status s;
+  if ((s = mlp_forward(c, rows)) != RBM_OK) return s;
+  if ((s = mlp_backward(c, rows)) != RBM_OK) return s;
+  HIPCHECK(hipMemcpyAsync(d_grad, L.G, L.nparam * sizeof(float), hipMemcpyDeviceToDevice, c->st));
+  double lv;
+  if ((s = read_scalar(c, L.lsum, &lv)) != RBM_OK) return s;
+  if (loss) *loss = lv;
+  return RBM_OK;
+}
+
+extern "C" rbm_status rbm_learned_features_dev(rbm_ctx* c, const double* d_FT, float* d_X) {
+  if (!c || !d_FT || !d_X) return fail(RBM_E_INVAL, "null argument");
+  auto& L = c->L;
+  if (!L.bound) return fail(RBM_E_STATE, "bind the learned workspace first");
+  rbm_status s;
+  if ((s = upload_bodies(c)) != RBM_OK) return s;
+  const double* desc = L.S > 0 ? c->rcbuf : nullptr;
+  HIPCHECK(launch_features(c->n, L.cfg.k_nbr, L.S, c->cen, c->Rm, d_FT, c->sid, desc, d_X, c->st));
+  HIPCHECK(hipStreamSynchronize(c->st));
+  return RBM_OK;
+}
+
+extern "C" rbm_status rbm_learned_guess_dev(rbm_ctx* c, const double* d_FT, double* d_mu0) {
+  if (!c || !d_FT || !d_mu0) return fail(RBM_E_INVAL, "null argument");
+  if (!c->L.bound) return fail(RBM_E_STATE, "bind the learned workspace first");
+  if (!c->setup_done) return fail(RBM_E_STATE, "call rbm_setup first");
+  rbm_status s;
+  if ((s = upload_bodies(c)) != RBM_OK) return s;
+  const int N = c->n * c->M;
+  SolveState S;
+  c->ev_used = 0;
+  double bnorm;
+  if ((s = build_rhs(c, S, d_FT, &bnorm)) != RBM_OK) return s;
+  if ((s = self_apply(c, S, 1, 0, c->b, c->yb)) != RBM_OK) return s;
+  HIPCHECK(launch_combine(N, c->M, 0, nullptr, 0.0, nullptr, 0.0, c->yb, c->Rm, 1.0, c->mu, c->st));
+  if ((s = learned_correction(c, d_FT)) != RBM_OK) return s;
+  HIPCHECK(hipMemcpyAsync(d_mu0, c->mu, 3 * (size_t)N * sizeof(double), hipMemcpyDeviceToDevice, c->st));
+  HIPCHECK(hipStreamSynchronize(c->st));
+  c->have_solution = false;
+  return RBM_OK;
+}
+
+extern "C" rbm_status rbm_set_guess(rbm_ctx* c, int guess) {
+  if (!c) return fail(RBM_E_INVAL, "null argument");
+  if (guess < 0 || guess > 3) return fail(RBM_E_INVAL, "bad guess");
+  c->opt.guess = guess;
   return RBM_OK;
 }

@@ -15,13 +15,17 @@ LIB_PATH = os.path.join(HERE, "librbm.so")
 
 RBM_OK, RBM_E_INVAL, RBM_E_NOMEM, RBM_E_DEVICE, RBM_E_NOCONV, RBM_E_STATE = 0, -1, -2, -3, -4, -6
 FP64, MIXED_FP32, MIXED_BF16 = 0, 1, 2
-GUESS_ZERO, GUESS_BLOCKDIAG, GUESS_USER = 0, 1, 2
+GUESS_ZERO, GUESS_BLOCKDIAG, GUESS_USER, GUESS_LEARNED = 0, 1, 2, 3
 
 EXPORTED = [
     "rbm_default_options", "rbm_create", "rbm_destroy", "rbm_set_shapes", "rbm_set_shapes_radial",
     "rbm_set_bodies", "rbm_workspace_size", "rbm_bind_workspace", "rbm_setup", "rbm_solve",
     "rbm_solve_dev", "rbm_set_guess_dev", "rbm_get_density", "rbm_debug_ptr", "rbm_debug_read",
     "rbm_far_traction", "rbm_far_stokeslet", "rbm_last_error", "rbm_step_rk4", "rbm_get_bodies",
+    "rbm_learned_default_config", "rbm_learned_workspace_size", "rbm_learned_bind",
+    "rbm_learned_capture", "rbm_learned_set_capture", "rbm_learned_train", "rbm_learned_info",
+    "rbm_learned_get_params", "rbm_learned_set_params", "rbm_learned_forward_dev",
+    "rbm_learned_loss_grad_dev", "rbm_learned_features_dev", "rbm_learned_guess_dev", "rbm_set_guess",
 ]
 
 
@@ -38,7 +42,14 @@ class SolveInfo(ctypes.Structure):
                 ("ms_total", ctypes.c_double), ("ms_far", ctypes.c_double), ("ms_self", ctypes.c_double),
                 ("far_pairs", ctypes.c_double), ("n_traction", ctypes.c_int),
                 ("n_stokeslet", ctypes.c_int), ("ms_traction", ctypes.c_double),
-                ("ms_stokeslet", ctypes.c_double), ("pairs_per_launch", ctypes.c_double)]
+                ("ms_stokeslet", ctypes.c_double), ("pairs_per_launch", ctypes.c_double),
+                ("guess_used", ctypes.c_int), ("fallback_used", ctypes.c_int),
+                ("init_rel_residual", ctypes.c_double)]
+
+
+class LearnedConfig(ctypes.Structure):
+    _fields_ = [("k_nbr", ctypes.c_int), ("hidden", ctypes.c_int), ("n_hidden", ctypes.c_int),
+                ("capacity", ctypes.c_int), ("batch_max", ctypes.c_int), ("seed", ctypes.c_ulonglong)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -76,6 +87,20 @@ def load():
         "rbm_last_error": (ctypes.c_char_p, []),
         "rbm_step_rk4": (I, [P, D, P, P]),
         "rbm_get_bodies": (I, [P, P, P]),
+        "rbm_learned_default_config": (None, [P]),
+        "rbm_learned_workspace_size": (I, [P, P, P]),
+        "rbm_learned_bind": (I, [P, P, P, S]),
+        "rbm_learned_capture": (I, [P, P]),
+        "rbm_learned_set_capture": (I, [P, I]),
+        "rbm_learned_train": (I, [P, I, I, D, P]),
+        "rbm_learned_info": (I, [P, P, P, P, P]),
+        "rbm_learned_get_params": (I, [P, P, S]),
+        "rbm_learned_set_params": (I, [P, P, S]),
+        "rbm_learned_forward_dev": (I, [P, P, I, P]),
+        "rbm_learned_loss_grad_dev": (I, [P, P, P, I, P, P]),
+        "rbm_learned_features_dev": (I, [P, P, P]),
+        "rbm_learned_guess_dev": (I, [P, P, P]),
+        "rbm_set_guess": (I, [P, I]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -208,6 +233,71 @@ class Solver:
         q = np.zeros((self.n, 4))
         _check(load().rbm_get_bodies(self.ctx, _ptr(cen), _ptr(q)))
         return cen, q
+
+    # -- learned warm start -----------------------------------------------------------
+    def learned_bind(self, k_nbr=8, hidden=256, n_hidden=3, capacity=65536, batch_max=1024, seed=1234):
+        lib = load()
+        cfg = LearnedConfig()
+        lib.rbm_learned_default_config(ctypes.byref(cfg))
+        cfg.k_nbr, cfg.hidden, cfg.n_hidden = k_nbr, hidden, n_hidden
+        cfg.capacity, cfg.batch_max, cfg.seed = capacity, batch_max, seed
+        nb = ctypes.c_size_t()
+        _check(lib.rbm_learned_workspace_size(self.ctx, ctypes.byref(cfg), ctypes.byref(nb)))
+        self.learned_ws = self.torch.empty(nb.value, dtype=self.torch.uint8, device=self.device)
+        _check(lib.rbm_learned_bind(self.ctx, ctypes.byref(cfg), ctypes.c_void_p(self.learned_ws.data_ptr()),
+                                    nb.value))
+        self.learned_cfg = cfg
+        return self.learned_info()
+
+    def learned_info(self):
+        a, b, c, d = (ctypes.c_int() for _ in range(4))
+        _check(load().rbm_learned_info(self.ctx, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c),
+                                       ctypes.byref(d)))
+        return {"samples": a.value, "F": b.value, "O": c.value, "n_params": d.value}
+
+    def learned_capture(self, FT_dev):
+        _check(load().rbm_learned_capture(self.ctx, ctypes.c_void_p(FT_dev.data_ptr())))
+
+    def learned_set_capture(self, on):
+        _check(load().rbm_learned_set_capture(self.ctx, int(bool(on))))
+
+    def learned_train(self, epochs, batch, lr):
+        loss = ctypes.c_double()
+        _check(load().rbm_learned_train(self.ctx, int(epochs), int(batch), float(lr), ctypes.byref(loss)))
+        return loss.value
+
+    def learned_params(self):
+        info = self.learned_info()
+        out = np.zeros(info["n_params"] + 2 * info["F"] + 2, dtype=np.float32)
+        _check(load().rbm_learned_get_params(self.ctx, _ptr(out), out.size))
+        return out
+
+    def learned_set_params(self, arr):
+        arr = np.ascontiguousarray(arr, dtype=np.float32)
+        _check(load().rbm_learned_set_params(self.ctx, _ptr(arr), arr.size))
+
+    def learned_forward(self, X_dev, Y_dev):
+        _check(load().rbm_learned_forward_dev(self.ctx, ctypes.c_void_p(X_dev.data_ptr()), X_dev.shape[0],
+                                              ctypes.c_void_p(Y_dev.data_ptr())))
+
+    def learned_loss_grad(self, X_dev, T_dev, G_dev):
+        loss = ctypes.c_double()
+        _check(load().rbm_learned_loss_grad_dev(self.ctx, ctypes.c_void_p(X_dev.data_ptr()),
+                                                ctypes.c_void_p(T_dev.data_ptr()), X_dev.shape[0],
+                                                ctypes.c_void_p(G_dev.data_ptr()), ctypes.byref(loss)))
+        return loss.value
+
+    def learned_features(self, FT_dev, X_dev):
+        _check(load().rbm_learned_features_dev(self.ctx, ctypes.c_void_p(FT_dev.data_ptr()),
+                                               ctypes.c_void_p(X_dev.data_ptr())))
+
+    def learned_guess(self, FT_dev, mu_dev):
+        _check(load().rbm_learned_guess_dev(self.ctx, ctypes.c_void_p(FT_dev.data_ptr()),
+                                            ctypes.c_void_p(mu_dev.data_ptr())))
+
+    def set_guess_mode(self, guess):
+        _check(load().rbm_set_guess(self.ctx, int(guess)))
+        self.opt.guess = guess
 
     def set_guess_dev(self, mu0_dev):
         _check(load().rbm_set_guess_dev(self.ctx, ctypes.c_void_p(mu0_dev.data_ptr())))
