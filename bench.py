@@ -1,19 +1,29 @@
 """Benchmark of the mobility solve on one MI355X.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload random64]
+    python bench.py --learned-experiment [--workload sediment512]
 
-A step is one full mobility solve (incident density, right-hand side, GMRES to
-the relative residual tolerance, velocities) with the loads already resident in
+A step is one full mobility solve (incident density, right-hand side, GMRES to the
+relative residual tolerance 1e-8, velocities) with the loads already resident in
 HBM; setup (singular operators, block inverses) happens once before timing.
-Prints ONE JSON line.  ``value`` is the whole-solve pair-interaction throughput of
-the plain float64 solve (off-body pair interactions evaluated by all of its sums,
-divided by its wall time).  The same run also times the mixed-precision
-(GMRES-IR) solve at the same tolerance, the roofline of the dominant kernel (the
-float64 traction sum, timed with HIP events on the library stream), and the FP64
-NumPy oracle's pair rate on the host (cpu_baseline).
+
+Default mode (one JSON line):
+  1. a mixed-precision context with the learned warm start runs a short RK4
+     trajectory from the workload's configuration, capturing every stage solve, and
+     trains its network on them;
+  2. at the configuration the trajectory reached (not in the training data) it
+     times K solves each of: plain float64 with the block-diagonal guess (this is
+     ``value``: off-body pair interactions evaluated by all of the solve's sums per
+     second of wall time), mixed precision with the block-diagonal guess, and mixed
+     precision with the learned guess;
+  3. the roofline of the dominant kernel (float64 traction sum; HIP events on the
+     library stream) and the FP64 NumPy oracle's pair rate on the host.
+--learned-experiment: paired learned-vs-block-diagonal iteration counts along a
+trajectory (train on the first steps, evaluate on the following ones).
 """
 import argparse
 import json
+import math
 import os
 import sys
 import time
@@ -25,8 +35,11 @@ sys.path.insert(0, ROOT)
 
 METRIC = "mobility solve time @1e-8 rel. residual (mixed+learned vs FP64); Gpairs/s"
 FP64_PEAK_TFLOPS = 78.6      # MI355X vector FP64
-FP32_PEAK_TFLOPS = 157.3     # MI355X vector FP32 (packed issue)
 TRACTION_FLOPS_PER_PAIR = 30
+
+
+def _log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
 def _cpu_baseline(w, budget_s):
@@ -52,16 +65,197 @@ def _cpu_baseline(w, budget_s):
                       f"{prob.N} sources ({pairs:.3e} pairs, {dt:.1f} s, NumPy single thread)"}
 
 
+def _timed(torch, solver, FT, VW, steps, warmup):
+    for _ in range(warmup):
+        solver.solve_dev(FT, VW)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    infos = [solver.solve_dev(FT, VW) for _ in range(steps)]
+    torch.cuda.synchronize()
+    return time.perf_counter() - t0, infos
+
+
+def _dt_rule(VW):
+    """Time step from the first solve: 0.02 / max_i |v_i - mean v|."""
+    v = VW[:, :3]
+    return 0.02 / max(np.abs(v - v.mean(axis=0)).max(), 1e-12)
+
+
+def _train_on_trajectory(rbm, torch, w, FT, tol, steps, epochs, lr, precision):
+    s = rbm.solver_for(w, tol=tol, precision=precision, guess=rbm.GUESS_BLOCKDIAG)
+    s.learned_bind(k_nbr=8, hidden=256, n_hidden=3, capacity=max(4 * steps * s.n, 1),
+                   batch_max=1024, seed=7)
+    VW = torch.zeros_like(FT)
+    s.solve_dev(FT, VW)
+    dt = _dt_rule(VW.cpu().numpy())
+    s.learned_set_capture(True)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        s.step_rk4(dt, FT)
+    torch.cuda.synchronize()
+    t_traj = time.perf_counter() - t0
+    s.learned_set_capture(False)
+    t0 = time.perf_counter()
+    loss0 = s.learned_train(1, 256, lr)
+    loss = s.learned_train(epochs - 1, 256, lr) if epochs > 1 else loss0
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    return s, dt, {"trajectory_steps": steps, "dt": dt, "samples": s.learned_info()["samples"],
+                   "epochs": epochs, "loss_first_epoch": loss0, "loss_last_epoch": loss,
+                   "trajectory_s": t_traj, "train_s": t_train}
+
+
+def main_bench(args):
+    import torch
+    from paper_1606_07428_amd import inputs, rbm
+
+    w = inputs.workload(args.workload)
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    n = len(w["shape_id"])
+    _log(f"workload {args.workload}: n={n} p={w['p']}")
+    FT = torch.as_tensor(np.asarray(w["FT"], dtype=np.float64), device=dev)
+    VW = torch.zeros_like(FT)
+
+    learned = None
+    if not args.no_learned:
+        sl, dt, learned = _train_on_trajectory(rbm, torch, w, FT, args.tol, args.train_steps,
+                                               args.epochs, 1e-3, rbm.MIXED_FP32)
+        cen, quat = sl.bodies()
+        _log(f"trained on {learned['samples']} samples, loss {learned['loss_first_epoch']:.3e} -> "
+             f"{learned['loss_last_epoch']:.3e}")
+    else:
+        cen, quat = np.asarray(w["centres"]), np.asarray(w["quats"])
+
+    t0 = time.perf_counter()
+    s64 = rbm.solver_for(w, tol=args.tol, precision=rbm.FP64, guess=rbm.GUESS_BLOCKDIAG)
+    s64.set_bodies(w["shape_id"], cen, quat)
+    torch.cuda.synchronize()
+    setup_s = time.perf_counter() - t0
+    dt64, infos = _timed(torch, s64, FT, VW, args.steps, args.warmup)
+    VW64 = VW.cpu().numpy().copy()
+    _log(f"fp64 block-diagonal: {dt64 / args.steps * 1e3:.3f} ms/solve, iters {infos[-1]['iters']}")
+
+    pairs = sum(i["far_pairs"] for i in infos)
+    ms_trac = sum(i["ms_traction"] for i in infos)
+    n_trac = sum(i["n_traction"] for i in infos)
+    ppl = infos[-1]["pairs_per_launch"]
+    trac_avg_s = ms_trac / max(n_trac, 1) / 1e3
+    achieved = TRACTION_FLOPS_PER_PAIR * ppl / trac_avg_s / 1e12
+    result = {
+        "metric": METRIC,
+        "value": pairs / dt64 / 1e9,
+        "unit": "Gpairs/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": dt64 / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": args.workload, "bodies": n, "p": w["p"],
+                   "points": int(n * 2 * w["p"] * (w["p"] + 1)), "tol": args.tol,
+                   "precision": "fp64", "guess": "block-diagonal",
+                   "state": f"after {args.train_steps} RK4 steps" if learned else "initial"},
+        "roofline": {"bound": "alu", "kernel": "k_far<double, traction>",
+                     "achieved": achieved, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+                     "frac": achieved / FP64_PEAK_TFLOPS, "traffic": None,
+                     "launch_ms": trac_avg_s * 1e3, "pairs_per_launch": ppl,
+                     "flops_per_pair": TRACTION_FLOPS_PER_PAIR},
+        "solve": {"fp64_bd_ms": dt64 / args.steps * 1e3, "fp64_bd_iters": infos[-1]["iters"],
+                  "fp64_bd_matvecs": infos[-1]["matvecs"],
+                  "fp64_bd_rel_residual": infos[-1]["rel_residual"],
+                  "solves_per_s": args.steps / dt64,
+                  "matvecs_per_s": sum(i["matvecs"] for i in infos) / dt64,
+                  "traction_gpairs_per_s": ppl / trac_avg_s / 1e9, "setup_s": setup_s},
+    }
+    s64.close()
+    del s64
+    torch.cuda.empty_cache()
+
+    if learned is not None:
+        out = result["solve"]
+        for name, g in (("mixed_bd", rbm.GUESS_BLOCKDIAG), ("mixed_learned", rbm.GUESS_LEARNED)):
+            sl.set_guess_mode(g)
+            dtm, inf = _timed(torch, sl, FT, VW, args.steps, args.warmup)
+            err = float(np.abs(VW.cpu().numpy() - VW64).max() / np.abs(VW64).max())
+            out.update({f"{name}_ms": dtm / args.steps * 1e3, f"{name}_iters": inf[-1]["iters"],
+                        f"{name}_refinements": inf[-1]["refinements"],
+                        f"{name}_rel_residual": inf[-1]["rel_residual"],
+                        f"{name}_init_rel_residual": inf[-1]["init_rel_residual"],
+                        f"{name}_fallback": inf[-1]["fallback_used"],
+                        f"{name}_vs_fp64_velocity_rel_err": err})
+            _log(f"{name}: {dtm / args.steps * 1e3:.3f} ms/solve, iters {inf[-1]['iters']}")
+        out["speedup_mixed_learned_vs_fp64"] = out["fp64_bd_ms"] / out["mixed_learned_ms"]
+        result["learned"] = learned
+        sl.close()
+
+    if not args.no_cpu:
+        result["cpu_baseline"] = _cpu_baseline(w, args.cpu_budget)
+    print(json.dumps(result), flush=True)
+
+
+def main_learned_experiment(args):
+    """Paired comparison along a trajectory: train on the first `train_steps` RK4
+    steps, then at each of the next `eval_steps` states solve from both guesses."""
+    import torch
+    from paper_1606_07428_amd import inputs, rbm
+
+    w = inputs.workload(args.workload)
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    FT = torch.as_tensor(np.asarray(w["FT"], dtype=np.float64), device=dev)
+    VW = torch.zeros_like(FT)
+    prec = {"fp64": rbm.FP64, "fp32": rbm.MIXED_FP32, "bf16": rbm.MIXED_BF16}[args.precision]
+    s, dt, learned = _train_on_trajectory(rbm, torch, w, FT, args.tol, args.train_steps, args.epochs,
+                                          1e-3, prec)
+    _log(f"trained: {learned}")
+    rows = []
+    for k in range(args.eval_steps):
+        row = {"step": args.train_steps + k}
+        for name, g in (("bd", rbm.GUESS_BLOCKDIAG), ("learned", rbm.GUESS_LEARNED)):
+            s.set_guess_mode(g)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            info = s.solve_dev(FT, VW)
+            torch.cuda.synchronize()
+            row[name] = {"iters": info["iters"], "ms": (time.perf_counter() - t0) * 1e3,
+                         "init_rel_residual": info["init_rel_residual"],
+                         "rel_residual": info["rel_residual"], "fallback": info["fallback_used"]}
+        rows.append(row)
+        _log(json.dumps(row))
+        s.set_guess_mode(rbm.GUESS_BLOCKDIAG)
+        s.step_rk4(dt, FT)
+    it_bd = [r["bd"]["iters"] for r in rows]
+    it_l = [r["learned"]["iters"] for r in rows]
+    print(json.dumps({"experiment": "learned warm start, paired", "workload": args.workload,
+                      "precision": args.precision, "tol": args.tol, "training": learned,
+                      "eval_steps": args.eval_steps, "mean_iters_bd": float(np.mean(it_bd)),
+                      "mean_iters_learned": float(np.mean(it_l)),
+                      "mean_ms_bd": float(np.mean([r["bd"]["ms"] for r in rows])),
+                      "mean_ms_learned": float(np.mean([r["learned"]["ms"] for r in rows])),
+                      "fallbacks": int(sum(r["learned"]["fallback"] for r in rows)), "rows": rows}),
+          flush=True)
+    s.close()
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="random64")
+    ap.add_argument("--workload", default=None)
     ap.add_argument("--tol", type=float, default=1e-8)
+    ap.add_argument("--train-steps", type=int, default=None)
+    ap.add_argument("--eval-steps", type=int, default=10)
+    ap.add_argument("--epochs", type=int, default=60)
+    ap.add_argument("--precision", default="fp32", choices=["fp64", "fp32", "bf16"])
     ap.add_argument("--cpu-budget", type=float, default=12.0)
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--no-mixed", action="store_true")
+    ap.add_argument("--no-learned", action="store_true")
+    ap.add_argument("--learned-experiment", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (HBM counter calibration)")
     args = ap.parse_args()
@@ -79,103 +273,14 @@ def main():
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the multi-GPU path is "
               "not part of this build", file=sys.stderr)
         sys.exit(2)
-
-    import torch
-    from paper_1606_07428_amd import inputs, rbm
-
-    w = inputs.workload(args.workload)
-    dev = torch.device("cuda:0")
-    torch.cuda.set_device(dev)
-    print(f"[bench] workload {args.workload}: n={len(w['shape_id'])} p={w['p']}", file=sys.stderr,
-          flush=True)
-    t0 = time.perf_counter()
-    s64 = rbm.solver_for(w, tol=args.tol, precision=rbm.FP64, guess=rbm.GUESS_BLOCKDIAG)
-    torch.cuda.synchronize()
-    setup_s = time.perf_counter() - t0
-    FT = torch.as_tensor(np.asarray(w["FT"], dtype=np.float64), device=dev)
-    VW = torch.zeros_like(FT)
-
-    def run(solver, steps, out):
-        infos = []
-        for _ in range(steps):
-            infos.append(solver.solve_dev(FT, out))
-        return infos
-
-    run(s64, args.warmup, VW)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    infos = run(s64, args.steps, VW)
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
-    VW64 = VW.cpu().numpy().copy()
-    print(f"[bench] fp64: {dt / args.steps * 1e3:.3f} ms/solve, iters {infos[-1]['iters']}",
-          file=sys.stderr, flush=True)
-
-    pairs = sum(i["far_pairs"] for i in infos)
-    ms_trac = sum(i["ms_traction"] for i in infos)
-    n_trac = sum(i["n_traction"] for i in infos)
-    ppl = infos[-1]["pairs_per_launch"]
-    trac_avg_s = ms_trac / max(n_trac, 1) / 1e3
-    achieved = TRACTION_FLOPS_PER_PAIR * ppl / trac_avg_s / 1e12
-    result = {
-        "metric": METRIC,
-        "value": pairs / dt / 1e9,
-        "unit": "Gpairs/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": dt / args.steps * 1e3,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f64",
-        "data": "synthetic",
-        "config": {"workload": args.workload, "bodies": int(len(w["shape_id"])), "p": w["p"],
-                   "points": int(len(w["shape_id"]) * 2 * w["p"] * (w["p"] + 1)),
-                   "tol": args.tol, "precision": "fp64", "guess": "block-diagonal"},
-        "roofline": {"bound": "alu", "kernel": "k_far<double, traction>",
-                     "achieved": achieved, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / FP64_PEAK_TFLOPS, "traffic": None,
-                     "launch_ms": trac_avg_s * 1e3, "pairs_per_launch": ppl,
-                     "flops_per_pair": TRACTION_FLOPS_PER_PAIR},
-        "solve": {"fp64_ms": dt / args.steps * 1e3, "iters": infos[-1]["iters"],
-                  "matvecs": infos[-1]["matvecs"], "rel_residual": infos[-1]["rel_residual"],
-                  "solves_per_s": args.steps / dt,
-                  "matvecs_per_s": sum(i["matvecs"] for i in infos) / dt,
-                  "traction_gpairs_per_s": ppl / trac_avg_s / 1e9,
-                  "setup_s": setup_s},
-    }
-    s64.close()
-    del s64
-    torch.cuda.empty_cache()
-
-    if not args.no_mixed:
-        s32 = rbm.solver_for(w, tol=args.tol, precision=rbm.MIXED_FP32, guess=rbm.GUESS_BLOCKDIAG)
-        run(s32, args.warmup, VW)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        inf32 = run(s32, args.steps, VW)
-        torch.cuda.synchronize()
-        dt32 = time.perf_counter() - t0
-        VW32 = VW.cpu().numpy()
-        err = float(np.abs(VW32 - VW64).max() / np.abs(VW64).max())
-        ms32 = sum(i["ms_traction"] for i in inf32)
-        n32 = sum(i["n_traction"] for i in inf32)
-        result["solve"].update({
-            "mixed_fp32_ms": dt32 / args.steps * 1e3, "mixed_iters": inf32[-1]["iters"],
-            "mixed_refinements": inf32[-1]["refinements"],
-            "mixed_rel_residual": inf32[-1]["rel_residual"],
-            "mixed_vs_fp64_velocity_rel_err": err,
-            "mixed_speedup": (dt / args.steps) / (dt32 / args.steps),
-        })
-        # the fp32 launches include the fp64 residual launches; report the mixed average
-        result["solve"]["mixed_traction_launch_ms_avg"] = ms32 / max(n32, 1)
-        s32.close()
-        print(f"[bench] mixed fp32: {dt32 / args.steps * 1e3:.3f} ms/solve", file=sys.stderr, flush=True)
-
-    if not args.no_cpu:
-        result["cpu_baseline"] = _cpu_baseline(w, args.cpu_budget)
-    print(json.dumps(result), flush=True)
+    if args.learned_experiment:
+        args.workload = args.workload or "sediment512"
+        args.train_steps = 25 if args.train_steps is None else args.train_steps
+        main_learned_experiment(args)
+    else:
+        args.workload = args.workload or "random64"
+        args.train_steps = 8 if args.train_steps is None else args.train_steps
+        main_bench(args)
 
 
 if __name__ == "__main__":

@@ -136,7 +136,7 @@ __global__ __launch_bounds__(256) void k_far(int N, int M, const T* __restrict__
   }
 }
 
-constexpr int kTPL = 2;
+constexpr int kTPL = 1;
 
 template <typename T>
 hipError_t launch_far(int kind, int N, int M, const T* tx, const T* nrm, const void* src,

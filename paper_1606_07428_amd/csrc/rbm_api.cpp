@@ -196,13 +196,25 @@ extern "C" rbm_status rbm_set_bodies(rbm_ctx* c, int n, const int* shape_id, con
   return RBM_OK;
 }
 
+// Source-range split of the far sum for N points.  The grid has nbx = ceil(N/256)
+// target blocks (one target per lane) times `split` source chunks; 256 CUs hold 8
+// resident 4-wave workgroups each (2048 slots), so the split is the smallest one
+// whose grid fills whole rounds of 2048 workgroups to >= 97 % (else the best one up
+// to 64).
 static int far_split(int N) {
-  const int nbx = (N + 511) / 512;
-  int s = (2048 + nbx - 1) / nbx;
-  if (s < 1) s = 1;
-  if (s > 64) s = 64;
-  if (s > (N + 255) / 256) s = (N + 255) / 256;
-  return s < 1 ? 1 : s;
+  const long slots = 2048;
+  const int nbx = (N + 255) / 256;
+  const int smax = std::max(1, std::min(64, (N + 255) / 256));
+  int best = 1;
+  double best_eff = -1.0;
+  for (int s = 1; s <= smax; ++s) {
+    const long w = (long)nbx * s;
+    const long rounds = (w + slots - 1) / slots;
+    const double eff = (double)w / (double)(rounds * slots);
+    if (w >= (long)(0.97 * slots) && eff >= 0.97) return s;
+    if (eff > best_eff + 1e-9) { best_eff = eff; best = s; }
+  }
+  return best;
 }
 
 // Split of the source range for N points, bounded by the partial-sum buffer.

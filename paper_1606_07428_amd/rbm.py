@@ -46,13 +46,13 @@ class SolveInfo(ctypes.Structure):
                 ("guess_used", ctypes.c_int), ("fallback_used", ctypes.c_int),
                 ("init_rel_residual", ctypes.c_double)]
 
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
 
 class LearnedConfig(ctypes.Structure):
     _fields_ = [("k_nbr", ctypes.c_int), ("hidden", ctypes.c_int), ("n_hidden", ctypes.c_int),
                 ("capacity", ctypes.c_int), ("batch_max", ctypes.c_int), ("seed", ctypes.c_ulonglong)]
-
-    def as_dict(self):
-        return {k: getattr(self, k) for k, _ in self._fields_}
 
 
 _LIB = None

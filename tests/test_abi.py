@@ -104,3 +104,19 @@ def test_workspace_grows_with_bodies_and_order():
         sizes.append(nb.value)
         lib.rbm_destroy(ctx)
     assert sizes[0] < sizes[1] < sizes[2]
+
+
+def test_binding_structures_match_header():
+    # field order and size of the option / info / config structs of include/rbm.h
+    src = open(os.path.join(ROOT, "include", "rbm.h")).read()
+    for cls, tag in ((rbm.Options, "rbm_options"), (rbm.SolveInfo, "rbm_solve_info"),
+                     (rbm.LearnedConfig, "rbm_learned_config")):
+        body = src[:src.index("} " + tag + ";")]
+        body = body[body.rindex("typedef struct {"):]
+        body = re.sub(r"/\*.*?\*/", "", body, flags=re.S)
+        names = re.findall(r"(\w+)\s*;", body)
+        names = [x for part in re.findall(r"(?:int|double|void\*|unsigned long long)\s+([\w ,]+);", body)
+                 for x in re.split(r"\s*,\s*", part.strip())]
+        assert [f for f, _ in cls._fields_] == names, (tag, names)
+    info = rbm.SolveInfo()
+    assert set(info.as_dict()) == {f for f, _ in rbm.SolveInfo._fields_}
