@@ -136,7 +136,74 @@ __global__ __launch_bounds__(256) void k_far(int N, int M, const T* __restrict__
   }
 }
 
+// Small-N variant: the workgroup stages a tile of TS sources (AoS in HBM) into LDS as
+// SoA once for its four waves, which then read them as broadcasts.  Below ~64k points
+// the source range per workgroup is short and sharing the load across the four waves
+// beats per-wave scalar loads (+20 % fp32, +7 % fp64 at 20k points on MI355X); above
+// it the scalar-load kernel is faster (-5 %).
+template <typename T, int KIND, int TS>
+__global__ __launch_bounds__(256) void k_far_lds(int N, int M, const T* __restrict__ tx,
+                                                 const T* __restrict__ tn,
+                                                 const Src8<T>* __restrict__ src,
+                                                 double* __restrict__ part, int chunk) {
+  __shared__ T sh[6][TS];
+  const int split = blockIdx.y;
+  const int b0 = split * chunk, b1 = min(N, b0 + chunk);
+  const int base = blockIdx.x * 256;
+  const int a = min(base + (int)threadIdx.x, N - 1);
+  const T xa = tx[a], ya = tx[N + a], za = tx[2 * N + a];
+  T nx = 0, ny = 0, nz = 0;
+  if (KIND == 0) {
+    nx = tn[a];
+    ny = tn[N + a];
+    nz = tn[2 * N + a];
+  }
+  T ax = 0, ay = 0, az = 0;
+  const int blo_t = (a / M) * M;
+  const int last = min(N, base + 256) - 1;
+  const int blo = (base / M) * M, bhi = (last / M + 1) * M;
+  for (int t0 = b0; t0 < b1; t0 += TS) {
+    const int cnt = min(TS, b1 - t0);
+    __syncthreads();
+    for (int e = threadIdx.x; e < cnt; e += 256) {
+      const Src8<T> q = src[t0 + e];
+#pragma unroll
+      for (int c = 0; c < 6; ++c) sh[c][e] = q.v[c];
+    }
+    __syncthreads();
+    Src8<T> q;
+    q.v[6] = q.v[7] = 0;
+    if (t0 + cnt <= blo || t0 >= bhi) {
+#pragma unroll 4
+      for (int k = 0; k < cnt; ++k) {
+#pragma unroll
+        for (int c = 0; c < 6; ++c) q.v[c] = sh[c][k];
+        Pair<T, KIND>::add(xa, ya, za, nx, ny, nz, q, ax, ay, az);
+      }
+    } else {
+      for (int k = 0; k < cnt; ++k) {
+#pragma unroll
+        for (int c = 0; c < 6; ++c) q.v[c] = sh[c][k];
+        T px = 0, py = 0, pz = 0;
+        Pair<T, KIND>::add(xa, ya, za, nx, ny, nz, q, px, py, pz);
+        const bool other = (unsigned)(t0 + k - blo_t) >= (unsigned)M;
+        ax += other ? px : (T)0;
+        ay += other ? py : (T)0;
+        az += other ? pz : (T)0;
+      }
+    }
+  }
+  const double scale = KIND == 0 ? -3.0 / (4.0 * RBM_PI) : 1.0 / (8.0 * RBM_PI);
+  if (base + (int)threadIdx.x < N) {
+    double* o = part + (size_t)split * 3 * N;
+    o[a] = scale * (double)ax;
+    o[N + a] = scale * (double)ay;
+    o[2 * (size_t)N + a] = scale * (double)az;
+  }
+}
+
 constexpr int kTPL = 1;
+constexpr int kLdsMaxN = 65536;
 
 template <typename T>
 hipError_t launch_far(int kind, int N, int M, const T* tx, const T* nrm, const void* src,
@@ -144,10 +211,17 @@ hipError_t launch_far(int kind, int N, int M, const T* tx, const T* nrm, const v
   const int chunk = (N + nsplit - 1) / nsplit;
   dim3 grid((N + 256 * kTPL - 1) / (256 * kTPL), nsplit);
   const Src8<T>* s = reinterpret_cast<const Src8<T>*>(src);
-  if (kind == 0)
+  constexpr int TS = sizeof(T) == 8 ? 512 : 256;
+  if (N <= kLdsMaxN) {
+    if (kind == 0)
+      k_far_lds<T, 0, TS><<<grid, 256, 0, st>>>(N, M, tx, nrm, s, part, chunk);
+    else
+      k_far_lds<T, 1, TS><<<grid, 256, 0, st>>>(N, M, tx, nrm, s, part, chunk);
+  } else if (kind == 0) {
     k_far<T, 0, kTPL><<<grid, 256, 0, st>>>(N, M, tx, nrm, s, part, chunk);
-  else
+  } else {
     k_far<T, 1, kTPL><<<grid, 256, 0, st>>>(N, M, tx, nrm, s, part, chunk);
+  }
   return hipGetLastError();
 }
 

@@ -37,7 +37,8 @@ def _sum_solver(n_points, M):
 
 
 @pytest.mark.parametrize("n_points,M,prec", [(5 * 84, 84, 0), (1037, 84, 0), (9 * 512 + 77, 144, 0),
-                                             (1037, 84, 1), (9 * 512 + 77, 144, 1)])
+                                             (1037, 84, 1), (9 * 512 + 77, 144, 1),
+                                             (70001, 312, 0), (70001, 312, 1)])
 def test_far_sums_match_oracle(n_points, M, prec):
     _case(f"far sums n={n_points} M={M} precision={prec}")
     rng = np.random.default_rng(n_points + M)
