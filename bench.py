@@ -65,6 +65,22 @@ def _cpu_baseline(w, budget_s):
                       f"{prob.N} sources ({pairs:.3e} pairs, {dt:.1f} s, NumPy single thread)"}
 
 
+def _traffic(kernel, workload):
+    """HBM bytes per launch of `kernel` at `workload` from the committed counter
+    summary (FETCH_SIZE and WRITE_SIZE passes, scaled by the plain-copy calibration),
+    or None when no summary exists for the current kernel."""
+    path = os.path.join(ROOT, "profiles", f"traffic_{workload}.json")
+    try:
+        with open(path) as f:
+            t = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if t.get("kernel") != kernel:
+        return None
+    return {"bytes_per_launch": t["fetch_bytes"] + t["write_bytes"], "fetch_bytes": t["fetch_bytes"],
+            "write_bytes": t["write_bytes"], "source": os.path.basename(path)}
+
+
 def _timed(torch, solver, FT, VW, steps, warmup):
     for _ in range(warmup):
         solver.solve_dev(FT, VW)
@@ -142,6 +158,8 @@ def main_bench(args):
     ppl = infos[-1]["pairs_per_launch"]
     trac_avg_s = ms_trac / max(n_trac, 1) / 1e3
     achieved = TRACTION_FLOPS_PER_PAIR * ppl / trac_avg_s / 1e12
+    points = int(n * 2 * w["p"] * (w["p"] + 1))
+    kernel = "k_far_lds<double, traction>" if points <= 65536 else "k_far<double, traction>"
     result = {
         "metric": METRIC,
         "value": pairs / dt64 / 1e9,
@@ -159,9 +177,10 @@ def main_bench(args):
                    "points": int(n * 2 * w["p"] * (w["p"] + 1)), "tol": args.tol,
                    "precision": "fp64", "guess": "block-diagonal",
                    "state": f"after {args.train_steps} RK4 steps" if learned else "initial"},
-        "roofline": {"bound": "alu", "kernel": "k_far<double, traction>",
+        "roofline": {"bound": "alu", "kernel": kernel,
                      "achieved": achieved, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / FP64_PEAK_TFLOPS, "traffic": None,
+                     "frac": achieved / FP64_PEAK_TFLOPS,
+                     "traffic": _traffic(kernel, args.workload),
                      "launch_ms": trac_avg_s * 1e3, "pairs_per_launch": ppl,
                      "flops_per_pair": TRACTION_FLOPS_PER_PAIR},
         "solve": {"fp64_bd_ms": dt64 / args.steps * 1e3, "fp64_bd_iters": infos[-1]["iters"],
@@ -241,6 +260,47 @@ def main_learned_experiment(args):
     s.close()
 
 
+def main_compare(args):
+    """One configuration, several solver forms, same state: float64 with the
+    block-diagonal guess, then GMRES-IR with fp32 and with bf16 preconditioners.
+    Velocity differences are stated against the float64 solve."""
+    import torch
+    from paper_1606_07428_amd import inputs, rbm
+
+    w = inputs.workload(args.workload)
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    n = len(w["shape_id"])
+    FT = torch.as_tensor(np.asarray(w["FT"], dtype=np.float64), device=dev)
+    VW = torch.zeros_like(FT)
+    out = {"experiment": "solver forms", "workload": args.workload, "bodies": n, "p": w["p"],
+           "points": int(n * 2 * w["p"] * (w["p"] + 1)), "tol": args.tol, "forms": {}}
+    ref = None
+    for name, prec in (("fp64", rbm.FP64), ("mixed_fp32", rbm.MIXED_FP32), ("mixed_bf16", rbm.MIXED_BF16)):
+        t0 = time.perf_counter()
+        s = rbm.solver_for(w, tol=args.tol, precision=prec, guess=rbm.GUESS_BLOCKDIAG)
+        torch.cuda.synchronize()
+        setup = time.perf_counter() - t0
+        dt, infos = _timed(torch, s, FT, VW, args.steps, args.warmup)
+        v = VW.cpu().numpy().copy()
+        if ref is None:
+            ref = v
+        i = infos[-1]
+        out["forms"][name] = {
+            "setup_s": setup, "solve_ms": dt / args.steps * 1e3, "iters": i["iters"],
+            "matvecs": i["matvecs"], "refinements": i["refinements"], "rel_residual": i["rel_residual"],
+            "traction_launch_ms_avg": i["ms_traction"] / max(i["n_traction"], 1),
+            "stokeslet_ms": i["ms_stokeslet"], "self_ms": i["ms_self"],
+            "pairs_per_launch": i["pairs_per_launch"],
+            "velocity_rel_err_vs_fp64": float(np.abs(v - ref).max() / np.abs(ref).max()),
+            "workspace_GB": s.workspace_bytes / 1e9}
+        _log(f"{name}: {json.dumps(out['forms'][name])}")
+        s.close()
+        del s
+        torch.cuda.empty_cache()
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -256,6 +316,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-learned", action="store_true")
     ap.add_argument("--learned-experiment", action="store_true")
+    ap.add_argument("--compare", action="store_true",
+                    help="time fp64 / mixed fp32 / mixed bf16 solves of one workload")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (HBM counter calibration)")
     args = ap.parse_args()
@@ -273,6 +335,10 @@ def main():
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the multi-GPU path is "
               "not part of this build", file=sys.stderr)
         sys.exit(2)
+    if args.compare:
+        args.workload = args.workload or "ellipsoids1000"
+        main_compare(args)
+        return
     if args.learned_experiment:
         args.workload = args.workload or "sediment512"
         args.train_steps = 25 if args.train_steps is None else args.train_steps

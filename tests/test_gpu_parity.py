@@ -55,7 +55,14 @@ def test_far_sums_match_oracle(n_points, M, prec):
     idx = np.arange(n_points) if n_points < 2000 else rng.choice(n_points, 300, replace=False)
     ref_t = add[idx] + ff.traction_sum(X[idx], Nn[idx], X, q, body[idx], body)
     ref_u = ff.stokeslet_sum(X[idx], X, q, body[idx], body)
-    tol = 1e-12 if prec == 0 else 2e-5
+    if prec == 0:
+        tol = 1e-12
+    else:
+        # fp32 positions carry 2^-24 |X| absolute error, so a pair term at distance d
+        # has relative error ~ 2^-24 |X| / d; the sums are dominated by the closest
+        # pairs, so the bound uses the nearest off-body source of the sampled targets
+        dmin = min(np.linalg.norm(X[body != body[a]] - X[a], axis=1).min() for a in idx[:50])
+        tol = 16 * 2.0 ** -24 * np.abs(X).max() / dmin
     assert rel_err(yt.cpu().numpy().T[idx], ref_t) < tol
     assert rel_err(us.cpu().numpy().T[idx], ref_u) < tol
     s.close()
