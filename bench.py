@@ -275,10 +275,30 @@ def main_compare(args):
     VW = torch.zeros_like(FT)
     out = {"experiment": "solver forms", "workload": args.workload, "bodies": n, "p": w["p"],
            "points": int(n * 2 * w["p"] * (w["p"] + 1)), "tol": args.tol, "forms": {}}
+    params = None
+    if args.learned_from:
+        ws = inputs.workload(args.learned_from)
+        FTs = torch.as_tensor(np.asarray(ws["FT"], dtype=np.float64), device=dev)
+        st, _, learned = _train_on_trajectory(rbm, torch, ws, FTs, args.tol, args.train_steps or 25,
+                                              args.epochs, 1e-3, rbm.MIXED_FP32)
+        params = st.learned_params()
+        out["learned_transfer"] = dict(learned, trained_on=args.learned_from)
+        st.close()
+        del st
+        torch.cuda.empty_cache()
+        _log(f"trained on {args.learned_from}: {learned}")
+    forms = [("fp64", rbm.FP64, False), ("mixed_fp32", rbm.MIXED_FP32, False),
+             ("mixed_bf16", rbm.MIXED_BF16, False)]
+    if params is not None:
+        forms.append(("mixed_fp32_learned", rbm.MIXED_FP32, True))
     ref = None
-    for name, prec in (("fp64", rbm.FP64), ("mixed_fp32", rbm.MIXED_FP32), ("mixed_bf16", rbm.MIXED_BF16)):
+    for name, prec, use_net in forms:
         t0 = time.perf_counter()
         s = rbm.solver_for(w, tol=args.tol, precision=prec, guess=rbm.GUESS_BLOCKDIAG)
+        if use_net:
+            s.learned_bind(k_nbr=8, hidden=256, n_hidden=3, capacity=1, batch_max=1024, seed=7)
+            s.learned_set_params(params)
+            s.set_guess_mode(rbm.GUESS_LEARNED)
         torch.cuda.synchronize()
         setup = time.perf_counter() - t0
         dt, infos = _timed(torch, s, FT, VW, args.steps, args.warmup)
@@ -293,6 +313,7 @@ def main_compare(args):
             "stokeslet_ms": i["ms_stokeslet"], "self_ms": i["ms_self"],
             "pairs_per_launch": i["pairs_per_launch"],
             "velocity_rel_err_vs_fp64": float(np.abs(v - ref).max() / np.abs(ref).max()),
+            "init_rel_residual": i["init_rel_residual"], "fallback": i["fallback_used"],
             "workspace_GB": s.workspace_bytes / 1e9}
         _log(f"{name}: {json.dumps(out['forms'][name])}")
         s.close()
@@ -318,6 +339,9 @@ def main():
     ap.add_argument("--learned-experiment", action="store_true")
     ap.add_argument("--compare", action="store_true",
                     help="time fp64 / mixed fp32 / mixed bf16 solves of one workload")
+    ap.add_argument("--learned-from", default=None,
+                    help="with --compare: train the warm start on this workload's trajectory and "
+                         "add a mixed fp32 + learned solve (same p and feature layout)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (HBM counter calibration)")
     args = ap.parse_args()

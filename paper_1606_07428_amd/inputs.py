@@ -60,23 +60,38 @@ def _uniform_quats(rng, n):
     return q / np.linalg.norm(q, axis=1)[:, None]
 
 
-def _rsa(rng, rb, side, gap, max_tries=2_000_000):
+def _rsa(rng, rb, side, gap, max_tries=20_000_000):
+    """Random sequential addition: draw uniform centres in the cube, keep one if its
+    bounding sphere clears every placed one by `gap`.  A cell list (cell size >= the
+    largest exclusion distance) limits each test to the 27 neighbouring cells."""
     n = len(rb)
     pos = np.zeros((n, 3))
     placed = 0
     tries = 0
     order = np.argsort(-rb)
+    cell = 2.0 * float(rb.max()) + gap
+    nc = max(1, int(side // cell))
+    h = side / nc
+    cells = {}
     while placed < n:
         tries += 1
         if tries > max_tries:
             raise RuntimeError("random sequential addition did not converge")
         i = order[placed]
         c = rng.uniform(0.0, side, 3)
-        if placed:
-            d = np.linalg.norm(pos[order[:placed]] - c, axis=1)
-            if np.any(d < rb[order[:placed]] + rb[i] + gap):
+        key = tuple(np.minimum((c // h).astype(int), nc - 1))
+        near = []
+        for dx in (-1, 0, 1):
+            for dy in (-1, 0, 1):
+                for dz in (-1, 0, 1):
+                    near.extend(cells.get((key[0] + dx, key[1] + dy, key[2] + dz), ()))
+        if near:
+            near = np.asarray(near)
+            d = np.linalg.norm(pos[near] - c, axis=1)
+            if np.any(d < rb[near] + rb[i] + gap):
                 continue
         pos[i] = c
+        cells.setdefault(key, []).append(i)
         placed += 1
     return pos
 
