@@ -65,6 +65,12 @@ def _cpu_baseline(w, budget_s):
                       f"{prob.N} sources ({pairs:.3e} pairs, {dt:.1f} s, NumPy single thread)"}
 
 
+def _kernel_source_hash():
+    import hashlib
+    with open(os.path.join(ROOT, "paper_1606_07428_amd", "csrc", "k_far.hip"), "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()
+
+
 def _traffic(kernel, workload):
     """HBM bytes per launch of `kernel` at `workload` from the committed counter
     summary (FETCH_SIZE and WRITE_SIZE passes, scaled by the plain-copy calibration),
@@ -75,7 +81,7 @@ def _traffic(kernel, workload):
             t = json.load(f)
     except (OSError, ValueError):
         return None
-    if t.get("kernel") != kernel:
+    if t.get("kernel") != kernel or t.get("source_sha256") != _kernel_source_hash():
         return None
     return {"bytes_per_launch": t["fetch_bytes"] + t["write_bytes"], "fetch_bytes": t["fetch_bytes"],
             "write_bytes": t["write_bytes"], "source": os.path.basename(path)}
@@ -291,6 +297,9 @@ def main_compare(args):
              ("mixed_bf16", rbm.MIXED_BF16, False)]
     if params is not None:
         forms.append(("mixed_fp32_learned", rbm.MIXED_FP32, True))
+    if args.forms:
+        keep = set(args.forms.split(","))
+        forms = [f for f in forms if f[0] in keep]
     ref = None
     for name, prec, use_net in forms:
         t0 = time.perf_counter()
@@ -339,6 +348,8 @@ def main():
     ap.add_argument("--learned-experiment", action="store_true")
     ap.add_argument("--compare", action="store_true",
                     help="time fp64 / mixed fp32 / mixed bf16 solves of one workload")
+    ap.add_argument("--forms", default=None,
+                    help="with --compare: comma list among fp64,mixed_fp32,mixed_bf16,mixed_fp32_learned")
     ap.add_argument("--learned-from", default=None,
                     help="with --compare: train the warm start on this workload's trajectory and "
                          "add a mixed fp32 + learned solve (same p and feature layout)")

@@ -23,7 +23,8 @@ namespace rbm {
 template <typename T> struct alignas(8 * sizeof(T)) Src8 { T v[8]; };
 
 // 1/sqrt(x) in float64: hardware estimate plus one third-order correction
-// y <- y + y e (1/2 + 3/8 e), e = 1 - x y^2 (error cubes each step).
+// y <- y + y e (1/2 + 3/8 e), e = 1 - x y^2 (error cubes each step).  Used by the
+// Stokeslet sum, which needs |r|^-1 and |r|^-3.
 __device__ __forceinline__ double rsqrt_t(double x) {
   double y = __builtin_amdgcn_rsq(x);
   const double t = x * y;
@@ -32,22 +33,37 @@ __device__ __forceinline__ double rsqrt_t(double x) {
 }
 __device__ __forceinline__ float rsqrt_t(float x) { return __builtin_amdgcn_rsqf(x); }
 
+// |r|^-5 from r2 = |r|^2.  float64: with the hardware estimate y (relative error
+// < 2^-24 on gfx950) and e = 1 - r2 y^2, |r|^-5 = y^5 (1 - e)^(-5/2)
+// = y^5 (1 + 5e/2 + 35e^2/8 + O(e^3)), accurate to float64 rounding with the two terms.
+__device__ __forceinline__ double rinv5_t(double r2) {
+  const double y = __builtin_amdgcn_rsq(r2);
+  const double y2 = y * y;
+  const double e = fma(-r2, y2, 1.0);
+  const double y5 = y2 * y2 * y;
+  return y5 * fma(e, fma(e, 4.375, 2.5), 1.0);
+}
+__device__ __forceinline__ float rinv5_t(float r2) {
+  const float y = __builtin_amdgcn_rsqf(r2);
+  const float y2 = y * y;
+  return y2 * y2 * y;
+}
+
 template <typename T, int KIND>
 struct Pair {
   __device__ __forceinline__ static void add(T xa, T ya, T za, T nx, T ny, T nz,
                                              const Src8<T>& s, T& ax, T& ay, T& az) {
     const T dx = xa - s.v[0], dy = ya - s.v[1], dz = za - s.v[2];
     const T r2 = dx * dx + dy * dy + dz * dz;
-    const T ri = rsqrt_t(r2);
     const T dq = dx * s.v[3] + dy * s.v[4] + dz * s.v[5];
     if (KIND == 0) {
       const T dn = dx * nx + dy * ny + dz * nz;
-      const T ri2 = ri * ri;
-      const T f = (dn * dq) * (ri2 * ri2 * ri);
+      const T f = (dn * dq) * rinv5_t(r2);
       ax += f * dx;
       ay += f * dy;
       az += f * dz;
     } else {
+      const T ri = rsqrt_t(r2);
       const T f = dq * (ri * ri * ri);
       ax += s.v[3] * ri + f * dx;
       ay += s.v[4] * ri + f * dy;
@@ -86,6 +102,30 @@ __global__ __launch_bounds__(256) void k_far(int N, int M, const T* __restrict__
   const int blo = (base / M) * M, bhi = (last / M + 1) * M;
   auto fast = [&](int s0, int e) {
     int b = s0;
+    if (sizeof(T) == 4 && b + 4 <= e) {
+      // fp32: the next four sources are loaded while the current four are used
+      Src8<T> cur[4];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) cur[k] = src[b + k];
+      for (; b + 8 <= e; b += 4) {
+        Src8<T> nxt[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) nxt[k] = src[b + 4 + k];
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+#pragma unroll
+          for (int u = 0; u < TPL; ++u)
+            Pair<T, KIND>::add(xa[u], ya[u], za[u], nx[u], ny[u], nz[u], cur[k], ax[u], ay[u], az[u]);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) cur[k] = nxt[k];
+      }
+#pragma unroll
+      for (int k = 0; k < 4; ++k)
+#pragma unroll
+        for (int u = 0; u < TPL; ++u)
+          Pair<T, KIND>::add(xa[u], ya[u], za[u], nx[u], ny[u], nz[u], cur[k], ax[u], ay[u], az[u]);
+      b += 4;
+    }
     for (; b + 4 <= e; b += 4) {
       const Src8<T> q0 = src[b], q1 = src[b + 1], q2 = src[b + 2], q3 = src[b + 3];
 #pragma unroll
