@@ -87,3 +87,168 @@ template hipError_t launch_self_apply<uint16_t>(int, int, const int*, const uint
                                                 hipStream_t);
 
 }  // namespace rbm
+
+namespace rbm {
+
+// ---- one shape shared by every body: the self apply is a GEMM ------------------------
+// Z (3M x n) = A (3M x 3M, column-major) . B (3M x n),  B[:, i] = R_i^T x_i (body frame),
+// on MFMA: v_mfma_f64_16x16x4_f64 (float64) or v_mfma_f32_16x16x4_f32 (float32).  A 64x64
+// output tile per workgroup (4 waves of 32x32 = 2x2 MFMA tiles), K staged by 16 through
+// LDS.  Operand layout (16x16x4): lane l holds A[l%16][l/16] and B[l/16][l%16]; it
+// receives D[4(l/16)+e][l%16] from the f32 instruction but D[(l/16)+4e][l%16] from the
+// f64 one (e = 0..3; both measured on gfx950 with a known product).
+
+// B[i*3M + c*M + a] = (R_i^T x_lab)[c] at node a, in the GEMM's operand type
+template <typename TB>
+__global__ void k_rotate_in(int n, int M, const double* __restrict__ Rm,
+                            const double* __restrict__ x_lab, TB* __restrict__ B) {
+  const size_t N = (size_t)n * M;
+  const size_t g = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= N) return;
+  const int i = (int)(g / M), a = (int)(g % M);
+  const double* R = Rm + 9 * i;
+  const double v0 = x_lab[g], v1 = x_lab[N + g], v2 = x_lab[2 * N + g];
+  TB* o = B + (size_t)i * 3 * M;
+  o[a] = (TB)(R[0] * v0 + R[3] * v1 + R[6] * v2);
+  o[M + a] = (TB)(R[1] * v0 + R[4] * v1 + R[7] * v2);
+  o[2 * M + a] = (TB)(R[2] * v0 + R[5] * v1 + R[8] * v2);
+}
+
+__global__ void k_rotate_in_bf16(int n, int M, const double* __restrict__ Rm,
+                                 const double* __restrict__ x_lab, uint16_t* __restrict__ B) {
+  const size_t N = (size_t)n * M;
+  const size_t g = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= N) return;
+  const int i = (int)(g / M), a = (int)(g % M);
+  const double* R = Rm + 9 * i;
+  const double v0 = x_lab[g], v1 = x_lab[N + g], v2 = x_lab[2 * N + g];
+  uint16_t* o = B + (size_t)i * 3 * M;
+  const double b[3] = {R[0] * v0 + R[3] * v1 + R[6] * v2, R[1] * v0 + R[4] * v1 + R[7] * v2,
+                       R[2] * v0 + R[5] * v1 + R[8] * v2};
+  for (int c = 0; c < 3; ++c) {
+    uint32_t u = __float_as_uint((float)b[c]);
+    u += 0x7fffu + ((u >> 16) & 1u);
+    o[c * M + a] = (uint16_t)(u >> 16);
+  }
+}
+
+typedef double d4v __attribute__((ext_vector_type(4)));
+typedef float f4v_ __attribute__((ext_vector_type(4)));
+
+template <typename T> struct MfmaAcc;
+template <> struct MfmaAcc<double> {
+  using V = d4v;
+  __device__ static V mfma(double a, double b, V c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  __device__ static int row(int lk, int e) { return lk + 4 * e; }
+};
+template <> struct MfmaAcc<float> {
+  using V = f4v_;
+  __device__ static V mfma(float a, float b, V c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  __device__ static int row(int lk, int e) { return 4 * lk + e; }
+};
+
+// y_body[(row/M)*N + i*M + row%M] = Z[row][i]
+template <typename T>
+__global__ __launch_bounds__(256) void k_self_gemm(int M3, int n, int M, const T* __restrict__ A,
+                                                   const T* __restrict__ B,
+                                                   double* __restrict__ y_body) {
+  __shared__ T As[64][17];
+  __shared__ T Bs[16][65];
+  using V = typename MfmaAcc<T>::V;
+  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+  const int bm = blockIdx.y * 64, bn = blockIdx.x * 64;
+  const int wr = (wid >> 1) * 32, wc = (wid & 1) * 32;
+  V acc[2][2];
+  for (int a = 0; a < 2; ++a)
+    for (int b = 0; b < 2; ++b)
+      for (int e = 0; e < 4; ++e) acc[a][b][e] = 0;
+  const int lr = lane & 15, lk = lane >> 4;
+  for (int k0 = 0; k0 < M3; k0 += 16) {
+    for (int e = tid; e < 1024; e += 256) {
+      const int r = e & 63, kk = e >> 6;  // A column-major: consecutive rows are contiguous
+      const int gi = bm + r, gk = k0 + kk;
+      As[r][kk] = (gi < M3 && gk < M3) ? A[(size_t)gk * M3 + gi] : (T)0;
+    }
+    for (int e = tid; e < 1024; e += 256) {
+      const int kk = e & 15, c = e >> 4;  // B column-major (one body per column)
+      const int gk = k0 + kk, gj = bn + c;
+      Bs[kk][c] = (gk < M3 && gj < n) ? B[(size_t)gj * M3 + gk] : (T)0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int ks = 0; ks < 16; ks += 4) {
+#pragma unroll
+      for (int ti = 0; ti < 2; ++ti) {
+        const T av = As[wr + ti * 16 + lr][ks + lk];
+#pragma unroll
+        for (int tj = 0; tj < 2; ++tj) {
+          const T bv = Bs[ks + lk][wc + tj * 16 + lr];
+          acc[ti][tj] = MfmaAcc<T>::mfma(av, bv, acc[ti][tj]);
+        }
+      }
+    }
+    __syncthreads();
+  }
+  const size_t N = (size_t)n * M;
+#pragma unroll
+  for (int ti = 0; ti < 2; ++ti)
+#pragma unroll
+    for (int tj = 0; tj < 2; ++tj)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int row = bm + wr + ti * 16 + MfmaAcc<T>::row(lk, e), i = bn + wc + tj * 16 + lr;
+        if (row < M3 && i < n)
+          y_body[(size_t)(row / M) * N + (size_t)i * M + row % M] = (double)acc[ti][tj][e];
+      }
+}
+
+// scatter of a float32 (3M x n, row-major [row][i]) product into y_body
+__global__ void k_scatter_f32(int M3, int n, int M, const float* __restrict__ Z,
+                              double* __restrict__ y_body) {
+  const size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (size_t)M3 * n) return;
+  const int row = (int)(e / n), i = (int)(e % n);
+  const size_t N = (size_t)n * M;
+  y_body[(size_t)(row / M) * N + (size_t)i * M + row % M] = (double)Z[e];
+}
+
+template <typename TM>
+hipError_t launch_self_apply_shared(int n, int M, const TM* A, const double* Rm,
+                                    const double* x_lab, void* scratchB, void* scratchZ,
+                                    double* y_body, hipStream_t st) {
+  const int M3 = 3 * M;
+  const size_t N = (size_t)n * M;
+  const unsigned gblocks = (unsigned)((N + 255) / 256);
+  if constexpr (sizeof(TM) == 2) {
+    uint16_t* B = reinterpret_cast<uint16_t*>(scratchB);
+    float* Z = reinterpret_cast<float*>(scratchZ);
+    k_rotate_in_bf16<<<gblocks, 256, 0, st>>>(n, M, Rm, x_lab, B);
+    // Z[row][i] = sum_k A[k*M3 + row] B[i*M3 + k]
+    hipError_t e = launch_gemm_bf16(M3, n, M3, reinterpret_cast<const uint16_t*>(A), 1, M3, B, 1,
+                                    M3, Z, n, nullptr, 1.f, 0.f, st);
+    if (e != hipSuccess) return e;
+    k_scatter_f32<<<(unsigned)(((size_t)M3 * n + 255) / 256), 256, 0, st>>>(M3, n, M, Z, y_body);
+  } else {
+    TM* B = reinterpret_cast<TM*>(scratchB);
+    k_rotate_in<TM><<<gblocks, 256, 0, st>>>(n, M, Rm, x_lab, B);
+    dim3 grid((n + 63) / 64, (M3 + 63) / 64);
+    k_self_gemm<TM><<<grid, 256, 0, st>>>(M3, n, M, A, B, y_body);
+  }
+  return hipGetLastError();
+}
+
+template hipError_t launch_self_apply_shared<double>(int, int, const double*, const double*,
+                                                     const double*, void*, void*, double*,
+                                                     hipStream_t);
+template hipError_t launch_self_apply_shared<float>(int, int, const float*, const double*,
+                                                    const double*, void*, void*, double*,
+                                                    hipStream_t);
+template hipError_t launch_self_apply_shared<uint16_t>(int, int, const uint16_t*, const double*,
+                                                       const double*, void*, void*, double*,
+                                                       hipStream_t);
+
+}  // namespace rbm

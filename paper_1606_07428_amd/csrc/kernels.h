@@ -7,6 +7,10 @@
 
 namespace rbm {
 
+hipError_t launch_gemm_bf16(int m, int n, int k, const uint16_t* A, long sa0, long sa1,
+                            const uint16_t* B, long sb0, long sb1, float* C, int ldc,
+                            const float* bias, float alpha, float beta, hipStream_t st);
+
 // ---- setup (k_setup.hip) ------------------------------------------------------
 hipError_t launch_gauss_legendre(int n, double* t, double* w, hipStream_t st);
 // grid tables: Y, dY/dtheta, (dY/dphi)/sin(theta) [(p+1)^2][M]; forward matrix F [nB][M];
@@ -71,6 +75,13 @@ hipError_t launch_rk_final(int n, const double* c0, const double* q0, const doub
 template <typename TM>
 hipError_t launch_self_apply(int n, int M, const int* sid, const TM* A, const double* Rm,
                              const double* x_lab, double* y_body, hipStream_t st);
+
+// One shape shared by every body: Z = A [R_i^T x_i] as an MFMA GEMM (float64, float32) or
+// the bf16 MFMA GEMM; scratchB holds 3N operand values, scratchZ 3N floats (bf16 only).
+template <typename TM>
+hipError_t launch_self_apply_shared(int n, int M, const TM* A, const double* Rm,
+                                    const double* x_lab, void* scratchB, void* scratchZ,
+                                    double* y_body, hipStream_t st);
 
 // ---- far field (k_far.hip) -------------------------------------------------------
 // Pack sources: (X_g, q_g) with q_g = W_g * (R_i z_body or z_lab)[g] into AoS of T.

@@ -62,6 +62,8 @@ struct rbm_ctx {
   float *Xf, *Nf;
   // vectors
   double *rho, *b, *mu, *r, *t1, *t2, *yb, *guess;
+  double* gB = nullptr;  // shared-shape GEMM operand (3N values)
+  float* gZ = nullptr;   // shared-shape bf16 GEMM product (3N floats)
   // Krylov
   double *V, *H, *cs, *sn, *g, *y, *htmp, *scal, *partial;
   // far field
@@ -257,6 +259,13 @@ static size_t layout(rbm_ctx* c, int nmax, bool assign) {
   take(c->X, N3); take(c->Nn, N3); take(c->W, N); take(c->Xf, N3); take(c->Nf, N3);
   take(c->rho, N3); take(c->b, N3); take(c->mu, N3); take(c->r, N3); take(c->t1, N3);
   take(c->t2, N3); take(c->yb, N3); take(c->guess, N3);
+  if (c->ns == 1) {
+    take(c->gB, N3);
+    take(c->gZ, N3);
+  } else if (assign) {
+    c->gB = nullptr;
+    c->gZ = nullptr;
+  }
   const int m = c->opt.max_iter;
   take(c->V, (size_t)(m + 1) * N3); take(c->H, (size_t)(m + 1) * (m + 1)); take(c->cs, m + 1);
   take(c->sn, m + 1); take(c->g, m + 2); take(c->y, m + 2); take(c->htmp, m + 2);
@@ -413,11 +422,21 @@ static rbm_status far_traction(rbm_ctx* c, SolveState& S, const double* x, int x
   return RBM_OK;
 }
 
-// y_body = A (R^T x) with A = A0 (which 0), P0 (which 1) in the given precision.
+// y_body = A (R^T x) with A = A0 (which 0), P0 (which 1) in the given precision.  With one
+// shape shared by all bodies (and enough of them) this is a GEMM on MFMA.
 static rbm_status self_apply(rbm_ctx* c, SolveState& S, int which, int prec, const double* x,
                              double* ybody) {
   Timer t(c);
-  if (which == 0 || prec == 0) {
+  if (c->ns == 1 && c->n >= 8 && c->gB) {
+    if (which == 0 || prec == 0) {
+      HIPCHECK(launch_self_apply_shared<double>(c->n, c->M, which == 0 ? c->A0 : c->P0, c->Rm, x,
+                                                c->gB, c->gZ, ybody, c->st));
+    } else if (prec == 1) {
+      HIPCHECK(launch_self_apply_shared<float>(c->n, c->M, c->P0f, c->Rm, x, c->gB, c->gZ, ybody, c->st));
+    } else {
+      HIPCHECK(launch_self_apply_shared<uint16_t>(c->n, c->M, c->P0h, c->Rm, x, c->gB, c->gZ, ybody, c->st));
+    }
+  } else if (which == 0 || prec == 0) {
     HIPCHECK(launch_self_apply<double>(c->n, c->M, c->sid, which == 0 ? c->A0 : c->P0, c->Rm, x,
                                        ybody, c->st));
   } else if (prec == 1) {

@@ -174,3 +174,17 @@ def test_mixed_precision_reaches_fp64_answer(prec):
     assert info["refinements"] >= 1
     assert rel_err(VW, VW_o) < 1e-9
     s.close()
+
+
+@pytest.mark.parametrize("prec", [rbm.FP64, rbm.MIXED_FP32, rbm.MIXED_BF16])
+def test_shared_shape_gemm_path_matches_oracle(prec):
+    # one shape for all 20 bodies: the self apply runs as an MFMA GEMM (ragged 64x64 tiles)
+    _case(f"shared shape n=20 p=6 precision={prec}")
+    from oracle import system as sy
+    w = inputs.tiny(20, 6, seed=61, shared=True)
+    s = rbm.solver_for(w, tol=1e-12, precision=prec)
+    VW, info = s.solve(w["FT"])
+    _, mu_o, VW_o = sy.solve_dense(oracle_problem(w), w["FT"])
+    assert info["rel_residual"] < 1e-12
+    assert rel_err(VW, VW_o) < 1e-10
+    s.close()
