@@ -166,6 +166,7 @@ def main_bench(args):
     achieved = TRACTION_FLOPS_PER_PAIR * ppl / trac_avg_s / 1e12
     points = int(n * 2 * w["p"] * (w["p"] + 1))
     kernel = "k_far_lds<double, traction>" if points <= 65536 else "k_far<double, traction>"
+    traffic = _traffic(kernel, args.workload)
     result = {
         "metric": METRIC,
         "value": pairs / dt64 / 1e9,
@@ -186,7 +187,8 @@ def main_bench(args):
         "roofline": {"bound": "alu", "kernel": kernel,
                      "achieved": achieved, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / FP64_PEAK_TFLOPS,
-                     "traffic": _traffic(kernel, args.workload),
+                     "traffic": traffic["bytes_per_launch"] if traffic else None,
+                     "traffic_detail": traffic,
                      "launch_ms": trac_avg_s * 1e3, "pairs_per_launch": ppl,
                      "flops_per_pair": TRACTION_FLOPS_PER_PAIR},
         "solve": {"fp64_bd_ms": dt64 / args.steps * 1e3, "fp64_bd_iters": infos[-1]["iters"],
