@@ -15,6 +15,7 @@ sphharm    Gauss-Legendre x trapezoid grid, real spherical harmonics, transforms
 geometry   surface geometry, smooth quadrature weights, area, centroid, tau (§2.2, §3)
 singular   weakly singular self-interaction operators by grid rotation (§3, §3.1)
 farfield   off-body Stokeslet / traction / pressure sums (§2.1, §3.1)
+nearfield  upsampled smooth rule for near body pairs (§3)
 system     incident density, augmented second-kind system, solves, velocities (§2.2-§3.3)
 timestep   quaternion RK4 evolution of centres and orientations (§3.3)
 mlp        FP64 reference of the warm-start network (forward, backward, Adam)

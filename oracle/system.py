@@ -6,7 +6,8 @@ Given body shapes, poses and loads (F_i, T_i):
   1. incident density rho_i = F_i/|Gamma_i| + tau_i^{-1} T_i x (x - x^c_i)   (§2.2)
   2. solve the augmented second-kind system (§2.3)
         (1/2 I + K + L) mu = -(1/2 I + K) rho,
-     K = K_self (singular rule, body blocks) + K_far (smooth rule, other bodies);
+     K = K_self (singular rule, body blocks) + K_far (smooth rule, other bodies;
+     optionally upsampled for near body pairs, see ``nearfield``);
   3. u = S[rho + mu] on every node; v_i = (1/|Gamma_i|) int u,
      omega_i = tau_i^{-1} int (y - x^c_i) x u                               (§3.3)
 
@@ -23,6 +24,7 @@ import numpy as np
 
 from . import farfield as ff
 from . import geometry as geo
+from . import nearfield as nf
 from . import singular as sg
 
 
@@ -53,7 +55,10 @@ class Shape:
 
 
 class Problem:
-    def __init__(self, shapes, shape_id, centres, quats, eta=1.0):
+    """The discrete problem; ``upsample = (p_u, kappa)`` switches on the near-singular
+    rule of ``nearfield`` for body pairs that are near (None: plain smooth rule)."""
+
+    def __init__(self, shapes, shape_id, centres, quats, eta=1.0, upsample=None):
         self.shapes = shapes
         self.shape_id = np.asarray(shape_id, dtype=np.int64)
         self.n = len(self.shape_id)
@@ -82,6 +87,42 @@ class Problem:
             wi = self.w[sl]
             self.area[i] = wi.sum()
             self.tau[i] = np.eye(3) * np.sum(wi * np.sum(rr * rr, axis=1)) - (rr * wi[:, None]).T @ rr
+        self.upsample = upsample
+        self.near = np.zeros((self.n, self.n), dtype=bool)
+        if upsample is not None:
+            p_u, kappa = upsample
+            p = shapes[0].p
+            self.fine = [nf.fine_geometry(s.coef, s.geom["xc"], p_u) for s in shapes]
+            self.U = nf.interp_matrix(p, p_u)
+            h = [math.sqrt(s.geom["area"] / s.M) for s in shapes]
+            self.near = nf.near_matrix(self.c, [f["R"] for f in self.fine], h, self.shape_id, kappa)
+
+    def fine_sources(self, j):
+        """Lab-frame fine nodes X' of body j and their weights w'."""
+        f = self.fine[self.shape_id[j]]
+        return (self.c[j][:, None] + self.R[j] @ f["r"]).T, f["w"]
+
+    def _far_upsampled(self, kind, vec, idx):
+        """Off-body sum at the targets idx with the plain rule for pairs that are not
+        near and the upsampled rule for near ones."""
+        out = np.zeros((len(idx), 3))
+        tb = self.body[idx]
+        for i in np.unique(tb):
+            sel = np.where(tb == i)[0]
+            Xt = self.X[idx[sel]]
+            for j in range(self.n):
+                if j == i:
+                    continue
+                if self.near[i, j]:
+                    Xs, ws = self.fine_sources(j)
+                    q = ws[:, None] * (self.U @ vec[self.sl(j)])
+                else:
+                    Xs, q = self.X[self.sl(j)], self.w[self.sl(j)][:, None] * vec[self.sl(j)]
+                if kind == "K":
+                    out[sel] += nf.traction_block(Xt, self.Nn[idx[sel]], Xs, q)
+                else:
+                    out[sel] += nf.stokeslet_block(Xt, Xs, q, self.eta)
+        return out
 
     def sl(self, i):
         return slice(i * self.M, (i + 1) * self.M)
@@ -120,13 +161,17 @@ class Problem:
         return out
 
     def K_far(self, mu, targets=None):
-        q = self.w[:, None] * mu
         idx = np.arange(self.N) if targets is None else np.asarray(targets)
+        if self.upsample is not None:
+            return self._far_upsampled("K", mu, idx)
+        q = self.w[:, None] * mu
         return ff.traction_sum(self.X[idx], self.Nn[idx], self.X, q, self.body[idx], self.body)
 
     def S_far(self, sig, targets=None):
-        q = self.w[:, None] * sig
         idx = np.arange(self.N) if targets is None else np.asarray(targets)
+        if self.upsample is not None:
+            return self._far_upsampled("S", sig, idx)
+        q = self.w[:, None] * sig
         return ff.stokeslet_sum(self.X[idx], self.X, q, self.body[idx], self.body, self.eta)
 
     # ---- the method ----------------------------------------------------------
@@ -175,8 +220,12 @@ class Problem:
         dn = np.einsum("abk,ak->ab", d, self.Nn)
         fac = -(3.0 / (4.0 * math.pi)) * dn / (r2 * r2 * np.sqrt(r2)) * self.w[None, :]
         fac[~other] = 0.0
-        Kf = np.einsum("ab,abi,abj->aibj", fac, d, d).reshape(3 * N, 3 * N)
-        return A + Kf
+        Kf = np.einsum("ab,abi,abj->aibj", fac, d, d)
+        for i, j in zip(*np.nonzero(self.near)):
+            Xs, ws = self.fine_sources(j)
+            Bf = nf.traction_matrix_block(self.X[self.sl(i)], self.Nn[self.sl(i)], Xs, ws)
+            Kf[self.sl(i), :, self.sl(j), :] = np.einsum("aibj,bc->aicj", Bf, self.U)
+        return A + Kf.reshape(3 * N, 3 * N)
 
     def velocities(self, rho, mu):
         """(v_i, omega_i) from u = S[rho + mu] (§3.3)."""
