@@ -82,6 +82,12 @@ typedef struct {
   int guess;        /* rbm_guess */
   double inner_tol; /* GMRES-IR inner relative tolerance (0 -> 1e-4) */
   void* stream;     /* hipStream_t or NULL */
+  int p_up;           /* near-singular upsampling (§3): 0 = off (every off-body pair uses the
+                         smooth rule of order p); else the order p_u of the finer grid, in
+                         [p+1, 48], used for every pair of bodies that are near */
+  double near_factor; /* kappa of the near test |c_i - c_j| < R_i + R_j + kappa h_j (R: largest
+                         centroid-to-node distance on the fine grid, h_j = sqrt(|Gamma_j|/M));
+                         0 -> 5 */
 } rbm_options;
 
 typedef struct {
@@ -103,6 +109,8 @@ typedef struct {
   int guess_used;     /* rbm_guess actually used for mu_0 */
   int fallback_used;  /* 1 if the learned guess was rejected for the block-diagonal one */
   double init_rel_residual; /* ||b - A mu_0|| / ||b|| */
+  int near_pairs;     /* ordered near body pairs of the upsampled rule (0 when off) */
+  double ms_near;     /* device time of the near-singular corrections (interpolation, sums) */
 } rbm_solve_info;
 
 /* Default options: p = 8, p_sing = 0, eta = 1, tol = 1e-12, max_iter = 100,
@@ -223,6 +231,12 @@ rbm_status rbm_learned_guess_dev(rbm_ctx* ctx, const double* d_FT, double* d_mu0
 /* Copy out the last solve's densities ([3][N] host arrays; either may be NULL). */
 rbm_status rbm_get_density(rbm_ctx* ctx, double* mu, double* rho);
 
+/* y = A mu on the device ([3][N] lab frame, float64): the augmented operator of §2.3,
+ * 1/2 I + K + L, with K the singular self blocks plus the off-body sum (upsampled for
+ * near pairs when p_up > 0), at the current poses.  d_mu and d_y must not alias.
+ * Synchronous on the context stream. */
+rbm_status rbm_apply_dev(rbm_ctx* ctx, const double* d_mu, double* d_y);
+
 /* Device pointers of internal arrays for inspection (valid until the workspace is
  * rebound).  name: "X","N","W" ([3][N]/[N] lab nodes, normals, weights), "mu",
  * "rho", "b" ([3][N]), "A0","P0" ([n_shapes][3M][3M] column-major body-frame
@@ -230,7 +244,11 @@ rbm_status rbm_get_density(rbm_ctx* ctx, double* mu, double* rho);
  * normals, recentred points), "gw" ([n_shapes][M] weights), "coef" ([n_shapes][3][(p+1)^2]),
  * "shape" (per shape 32 values: area, xc[3], tau[9], tauinv[9]), "Rm" ([n][9]),
  * "Ftab" ([p^2+2p][M]), "Ytab" ([(p+1)^2][M]), "learned_X" / "learned_T" (captured
- * features [capacity][F] and targets [capacity][O], fp32).  NULL if unknown. */
+ * features [capacity][F] and targets [capacity][O], fp32); with p_up > 0 also "U" (band-
+ * limited interpolation, column-major [M][Mu], Mu = 2 p_up (p_up+1)), "fr" ([n_shapes][3][Mu]
+ * fine nodes minus the centroid), "fw" ([n_shapes][Mu] fine weights), "rb" ([n_shapes]
+ * bounding radii), "near_list" ([n][64] int, increasing j) and "near_count" ([n] int).
+ * NULL if unknown. */
 const void* rbm_debug_ptr(rbm_ctx* ctx, const char* name);
 
 /* Copy `bytes` bytes starting `offset` bytes into the internal array `name` (as for

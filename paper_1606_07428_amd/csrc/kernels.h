@@ -147,4 +147,29 @@ hipError_t launch_band_synth(int n, int M, int p, const float* coef, const float
 hipError_t launch_band_analysis(int n, int M, int p, const double* dmu, const double* Rm,
                                 const double* Ftab, float* out, hipStream_t st);
 
+// ---- near-singular correction by upsampling (k_near.hip) --------------------------
+// fine nodes r' [ns][3][Mu], weights w' [ns][Mu], bounding radii rb [ns] at order pu
+hipError_t launch_fine_geometry(int ns, int p, int pu, const double* coef, const double* glu_t,
+                                const double* glu_w, const double* shp, double* fr, double* fw,
+                                double* rb, hipStream_t st);
+// band-limited interpolation coarse -> fine, column-major [M][Mu]
+hipError_t launch_interp_matrix(int p, int pu, const double* gl_t, const double* gl_w,
+                                const double* glu_t, double* U, hipStream_t st);
+// near list per body (increasing j, at most kmax stored) and true counts
+hipError_t launch_near_list(int n, int M, int kmax, double kappa, const double* cen, const int* sid,
+                            const double* rb, const double* shp, int* nbr, int* cnt, hipStream_t st);
+// zt = U z (per component and body), then packed fine sources of precision T
+template <typename T>
+hipError_t launch_fine_sources(int n, int M, int Mu, const double* U, const double* z, int z_is_body,
+                               const int* sid, const double* cen, const double* Rm, const double* fr,
+                               const double* fw, double* zt, void* srcf, hipStream_t st);
+// fine-minus-plain sums for near pairs into S slots [S][3][N]; kind 0 traction, 1 Stokeslet
+template <typename T>
+hipError_t launch_near_corr(int kind, int n, int M, int Mu, int kmax, int S, const T* tx,
+                            const T* tn, const void* src, const void* srcf, const int* nbr,
+                            const int* cnt, double* out, hipStream_t st);
+// C (Mr x Nc) = A (Mr x K) B (K x Nc), column-major float64 on MFMA
+hipError_t launch_gemm_f64_cm(int Mr, int K, int Nc, const double* A, const double* B, double* C,
+                              hipStream_t st);
+
 }  // namespace rbm

@@ -1,0 +1,61 @@
+// Pair arithmetic of the smooth-rule sums between bodies (§2.1, §3): the packed
+// source record and the traction / Stokeslet contribution of one source to one target,
+// shared by the all-pairs sum (k_far.hip) and the near-singular correction (k_near.hip).
+#pragma once
+#include "common.h"
+
+namespace rbm {
+
+template <typename T> struct alignas(8 * sizeof(T)) Src8 { T v[8]; };
+
+// 1/sqrt(x) in float64: hardware estimate plus one third-order correction
+// y <- y + y e (1/2 + 3/8 e), e = 1 - x y^2 (error cubes each step).  Used by the
+// Stokeslet sum, which needs |r|^-1 and |r|^-3.
+__device__ __forceinline__ double rsqrt_t(double x) {
+  double y = __builtin_amdgcn_rsq(x);
+  const double t = x * y;
+  const double e = fma(-t, y, 1.0);
+  return fma(y * e, fma(e, 0.375, 0.5), y);
+}
+__device__ __forceinline__ float rsqrt_t(float x) { return __builtin_amdgcn_rsqf(x); }
+
+// |r|^-5 from r2 = |r|^2.  float64: with the hardware estimate y (relative error
+// < 2^-24 on gfx950) and e = 1 - r2 y^2, |r|^-5 = y^5 (1 - e)^(-5/2)
+// = y^5 (1 + 5e/2 + 35e^2/8 + O(e^3)), accurate to float64 rounding with the two terms.
+__device__ __forceinline__ double rinv5_t(double r2) {
+  const double y = __builtin_amdgcn_rsq(r2);
+  const double y2 = y * y;
+  const double e = fma(-r2, y2, 1.0);
+  const double y5 = y2 * y2 * y;
+  return y5 * fma(e, fma(e, 4.375, 2.5), 1.0);
+}
+__device__ __forceinline__ float rinv5_t(float r2) {
+  const float y = __builtin_amdgcn_rsqf(r2);
+  const float y2 = y * y;
+  return y2 * y2 * y;
+}
+
+template <typename T, int KIND>
+struct Pair {
+  __device__ __forceinline__ static void add(T xa, T ya, T za, T nx, T ny, T nz,
+                                             const Src8<T>& s, T& ax, T& ay, T& az) {
+    const T dx = xa - s.v[0], dy = ya - s.v[1], dz = za - s.v[2];
+    const T r2 = dx * dx + dy * dy + dz * dz;
+    const T dq = dx * s.v[3] + dy * s.v[4] + dz * s.v[5];
+    if (KIND == 0) {
+      const T dn = dx * nx + dy * ny + dz * nz;
+      const T f = (dn * dq) * rinv5_t(r2);
+      ax += f * dx;
+      ay += f * dy;
+      az += f * dz;
+    } else {
+      const T ri = rsqrt_t(r2);
+      const T f = dq * (ri * ri * ri);
+      ax += s.v[3] * ri + f * dx;
+      ay += s.v[4] * ri + f * dy;
+      az += s.v[5] * ri + f * dz;
+    }
+  }
+};
+
+}  // namespace rbm

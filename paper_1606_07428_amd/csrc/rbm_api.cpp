@@ -29,6 +29,14 @@ static rbm_status fail(rbm_status s, const std::string& msg) {
       return fail(RBM_E_DEVICE, std::string(#expr) + ": " + hipGetErrorString(e_)); \
   } while (0)
 
+// Near-singular correction: at most kNearMax near bodies per body, the source list of
+// a body split over at most kNearSlotsMax workgroups (and partial-sum slots).
+constexpr int kMaxPup = 48;
+constexpr int kNearMax = 64;
+constexpr int kNearSlotsMax = 16;
+
+static int near_slots(int n) { return std::max(1, std::min(kNearSlotsMax, (2048 + n - 1) / n)); }
+
 struct rbm_ctx {
   rbm_options opt;
   int p = 0, ps = 0, M = 0, M3 = 0, nc = 0, nB = 0, Ms = 0;
@@ -69,6 +77,14 @@ struct rbm_ctx {
   // far field
   void* src;
   double* part;
+  // near-singular correction by upsampling (p_up > 0)
+  int pu = 0, Mu = 0, near_pairs = 0;
+  double kappa = 5.0;
+  double *glu_t = nullptr, *glu_w = nullptr, *fr = nullptr, *fw = nullptr, *rb = nullptr,
+         *U = nullptr, *zt = nullptr;
+  void* srcf = nullptr;
+  int *nbr = nullptr, *ncnt = nullptr;
+  std::vector<int> ncnt_h;
   double* pinned = nullptr;
   // learned warm start
   struct Learned {
@@ -104,6 +120,8 @@ extern "C" void rbm_default_options(rbm_options* o) {
   o->guess = RBM_GUESS_BLOCKDIAG;
   o->inner_tol = 1e-4;
   o->stream = nullptr;
+  o->p_up = 0;
+  o->near_factor = 5.0;
 }
 
 extern "C" const char* rbm_last_error(void) { return g_err.c_str(); }
@@ -119,6 +137,10 @@ extern "C" rbm_status rbm_create(const rbm_options* opt, rbm_ctx** out) {
   if (opt->max_restart < 0) return fail(RBM_E_INVAL, "max_restart >= 0");
   if (opt->precision < 0 || opt->precision > 2) return fail(RBM_E_INVAL, "bad precision");
   if (opt->guess < 0 || opt->guess > 3) return fail(RBM_E_INVAL, "bad guess");
+  if (opt->p_up != 0 && (opt->p_up < opt->p + 1 || opt->p_up > kMaxPup))
+    return fail(RBM_E_INVAL, "p_up must be 0 or in [p+1, 48]");
+  if (!(opt->near_factor >= 0.0) || !std::isfinite(opt->near_factor))
+    return fail(RBM_E_INVAL, "near_factor must be >= 0");
   rbm_ctx* c = new rbm_ctx();
   c->opt = *opt;
   if (!(c->opt.inner_tol > 0.0)) c->opt.inner_tol = 1e-4;
@@ -130,6 +152,9 @@ extern "C" rbm_status rbm_create(const rbm_options* opt, rbm_ctx** out) {
   c->nB = c->p * c->p + 2 * c->p;
   c->Ms = (ps + 1) * 2 * ps;
   c->st = (hipStream_t)opt->stream;
+  c->pu = opt->p_up;
+  c->Mu = c->pu ? (c->pu + 1) * 2 * c->pu : 0;
+  c->kappa = opt->near_factor > 0.0 ? opt->near_factor : 5.0;
   *out = c;
   return RBM_OK;
 }
@@ -274,7 +299,17 @@ static size_t layout(rbm_ctx* c, int nmax, bool assign) {
   double* srcd = nullptr;
   take(srcd, 8 * N);
   if (assign) c->src = srcd;
-  take(c->part, (size_t)far_split((int)N) * N3);
+  take(c->part, (size_t)(far_split((int)N) + (c->pu ? kNearSlotsMax : 0)) * N3);
+  if (c->pu) {
+    const size_t Mu = c->Mu, Nu = nm * Mu;
+    take(c->glu_t, c->pu + 1); take(c->glu_w, c->pu + 1);
+    take(c->fr, ns * 3 * Mu); take(c->fw, ns * Mu); take(c->rb, ns);
+    take(c->U, Mu * M); take(c->zt, 3 * Nu);
+    double* sf = nullptr;
+    take(sf, 8 * Nu);
+    if (assign) c->srcf = sf;
+    take(c->nbr, nm * kNearMax); take(c->ncnt, nm);
+  }
   return off + 256;
 }
 
@@ -351,6 +386,12 @@ extern "C" rbm_status rbm_setup(rbm_ctx* c) {
   HIPCHECK(launch_gauss_jordan(c->ns, M3, c->P0, c->piv, st));
   if (c->P0f) HIPCHECK(launch_cast_f32((size_t)c->ns * M3 * M3, c->P0, c->P0f, st));
   if (c->P0h) HIPCHECK(launch_cast_bf16((size_t)c->ns * M3 * M3, c->P0, c->P0h, st));
+  if (c->pu) {
+    HIPCHECK(launch_gauss_legendre(c->pu + 1, c->glu_t, c->glu_w, st));
+    HIPCHECK(launch_fine_geometry(c->ns, p, c->pu, c->coef, c->glu_t, c->glu_w, c->shp, c->fr, c->fw,
+                                  c->rb, st));
+    HIPCHECK(launch_interp_matrix(p, c->pu, c->gl_t, c->gl_w, c->glu_t, c->U, st));
+  }
   HIPCHECK(hipStreamSynchronize(st));
   c->setup_done = true;
   c->bodies_dirty = true;
@@ -359,6 +400,23 @@ extern "C" rbm_status rbm_setup(rbm_ctx* c) {
 
 // ---------------------------------------------------------------------------------
 // Solve
+
+// Near list of the current poses (upsampling on); reads the counts back to check them
+// against kNearMax and to report the number of near pairs.
+static rbm_status build_near(rbm_ctx* c) {
+  if (!c->pu) return RBM_OK;
+  HIPCHECK(launch_near_list(c->n, c->M, kNearMax, c->kappa, c->cen, c->sid, c->rb, c->shp, c->nbr,
+                            c->ncnt, c->st));
+  c->ncnt_h.resize(c->n);
+  HIPCHECK(hipMemcpyAsync(c->ncnt_h.data(), c->ncnt, c->n * sizeof(int), hipMemcpyDeviceToHost, c->st));
+  HIPCHECK(hipStreamSynchronize(c->st));
+  int tot = 0, mx = 0;
+  for (int v : c->ncnt_h) { tot += v; mx = std::max(mx, v); }
+  if (mx > kNearMax)
+    return fail(RBM_E_INVAL, "a body has more than 64 near bodies: lower near_factor");
+  c->near_pairs = tot;
+  return RBM_OK;
+}
 
 static rbm_status upload_bodies(rbm_ctx* c) {
   if (!c->bodies_dirty) return RBM_OK;
@@ -371,6 +429,8 @@ static rbm_status upload_bodies(rbm_ctx* c) {
   HIPCHECK(launch_nodes(n, c->M, c->sid, c->cen, c->Rm, c->gr, c->gn, c->gw, c->X, c->Nn, c->W,
                         c->Xf, c->Nf, st));
   HIPCHECK(hipStreamSynchronize(st));
+  rbm_status s = build_near(c);
+  if (s != RBM_OK) return s;
   c->bodies_dirty = false;
   return RBM_OK;
 }
@@ -395,12 +455,44 @@ struct Timer {
 };
 
 struct SolveState {
-  std::vector<std::pair<int, int>> trac_ev, stok_ev, self_ev;  // event index pairs
+  std::vector<std::pair<int, int>> trac_ev, stok_ev, self_ev, near_ev;  // event index pairs
   double far_pairs = 0.0;
   int matvecs = 0;
 };
 
-// Far traction of x (lab [3][N] or body frame), precision prec: part sums in c->part.
+// Partial-sum slots the combine adds for N points: the far sum's split plus, with
+// upsampling, the near-correction slots that follow it.
+static int far_slots(const rbm_ctx* c, int N) {
+  return split_for(c, N) + (c->pu ? near_slots(c->n) : 0);
+}
+
+// Near-singular correction of the far sum of kind (0 traction, 1 Stokeslet) for the
+// density x whose plain sources are already packed in c->src: fine sources of x, then
+// fine-minus-plain sums for the near pairs into the slots after the far split.
+static rbm_status near_correction(rbm_ctx* c, SolveState& S, int kind, const double* x,
+                                  int x_is_body, int prec) {
+  if (!c->pu) return RBM_OK;
+  const int n = c->n, M = c->M, N = n * M;
+  double* out = c->part + (size_t)split_for(c, N) * 3 * N;
+  Timer t(c);
+  if (prec == 0) {
+    HIPCHECK(launch_fine_sources<double>(n, M, c->Mu, c->U, x, x_is_body, c->sid, c->cen, c->Rm, c->fr,
+                                         c->fw, c->zt, c->srcf, c->st));
+    HIPCHECK(launch_near_corr<double>(kind, n, M, c->Mu, kNearMax, near_slots(n), c->X, c->Nn, c->src,
+                                      c->srcf, c->nbr, c->ncnt, out, c->st));
+  } else {
+    HIPCHECK(launch_fine_sources<float>(n, M, c->Mu, c->U, x, x_is_body, c->sid, c->cen, c->Rm, c->fr,
+                                        c->fw, c->zt, c->srcf, c->st));
+    HIPCHECK(launch_near_corr<float>(kind, n, M, c->Mu, kNearMax, near_slots(n), c->Xf, c->Nf, c->src,
+                                     c->srcf, c->nbr, c->ncnt, out, c->st));
+  }
+  t.stop();
+  if (t.on) S.near_ev.push_back({c->ev_used - 2, c->ev_used - 1});
+  return RBM_OK;
+}
+
+// Far traction of x (lab [3][N] or body frame), precision prec: part sums in c->part
+// (far_slots() of them, the near correction included).
 static rbm_status far_traction(rbm_ctx* c, SolveState& S, const double* x, int x_is_body,
                                int prec) {
   const int N = c->n * c->M;
@@ -419,7 +511,7 @@ static rbm_status far_traction(rbm_ctx* c, SolveState& S, const double* x, int x
     if (t.on) S.trac_ev.push_back({c->ev_used - 2, c->ev_used - 1});
   }
   S.far_pairs += (double)N * N - (double)c->n * c->M * c->M;
-  return RBM_OK;
+  return near_correction(c, S, 0, x, x_is_body, prec == 0 ? 0 : 1);
 }
 
 // y_body = A (R^T x) with A = A0 (which 0), P0 (which 1) in the given precision.  With one
@@ -455,7 +547,7 @@ static rbm_status apply_A(rbm_ctx* c, SolveState& S, const double* x, double* ou
   rbm_status s;
   if ((s = self_apply(c, S, 0, 0, x, c->yb)) != RBM_OK) return s;
   if ((s = far_traction(c, S, x, 0, 0)) != RBM_OK) return s;
-  HIPCHECK(launch_combine(N, c->M, split_for(c, N), c->part, 1.0, nullptr, 0.0, c->yb, c->Rm, 1.0, out, c->st));
+  HIPCHECK(launch_combine(N, c->M, far_slots(c, N), c->part, 1.0, nullptr, 0.0, c->yb, c->Rm, 1.0, out, c->st));
   S.matvecs++;
   return RBM_OK;
 }
@@ -466,7 +558,7 @@ static rbm_status apply_AP(rbm_ctx* c, SolveState& S, int prec, const double* v,
   rbm_status s;
   if ((s = self_apply(c, S, 1, prec, v, c->yb)) != RBM_OK) return s;
   if ((s = far_traction(c, S, c->yb, 1, prec == 0 ? 0 : 1)) != RBM_OK) return s;
-  HIPCHECK(launch_combine(N, c->M, split_for(c, N), c->part, 1.0, v, 1.0, nullptr, nullptr, 0.0, out, c->st));
+  HIPCHECK(launch_combine(N, c->M, far_slots(c, N), c->part, 1.0, v, 1.0, nullptr, nullptr, 0.0, out, c->st));
   S.matvecs++;
   return RBM_OK;
 }
@@ -547,7 +639,7 @@ static rbm_status build_rhs(rbm_ctx* c, SolveState& S, const double* dFT, double
   HIPCHECK(launch_rho(n, M, dFT, c->cen, c->X, c->tauinv, c->area_b, c->rho, st));
   if ((s = self_apply(c, S, 0, 0, c->rho, c->yb)) != RBM_OK) return s;
   if ((s = far_traction(c, S, c->rho, 0, 0)) != RBM_OK) return s;
-  HIPCHECK(launch_combine(N, M, split_for(c, N), c->part, -1.0, nullptr, 0.0, c->yb, c->Rm, -1.0, c->b, st));
+  HIPCHECK(launch_combine(N, M, far_slots(c, N), c->part, -1.0, nullptr, 0.0, c->yb, c->Rm, -1.0, c->b, st));
   HIPCHECK(launch_moments(n, M, c->rho, c->X, c->W, c->cen, c->mom, st));
   HIPCHECK(launch_add_rigid(n, M, c->mom, c->X, c->cen, 1.0, c->b, st));
   S.matvecs++;
@@ -656,8 +748,9 @@ static rbm_status solve_impl(rbm_ctx* c, const double* dFT, double* dVW, rbm_sol
     t.stop();
     if (t.on) S.stok_ev.push_back({c->ev_used - 2, c->ev_used - 1});
     S.far_pairs += (double)N * N - (double)n * M * M;
+    if ((s = near_correction(c, S, 1, c->t2, 0, 0)) != RBM_OK) return s;
   }
-  HIPCHECK(launch_combine(N, M, split_for(c, N), c->part, 1.0 / c->opt.eta, nullptr, 0.0, nullptr, nullptr,
+  HIPCHECK(launch_combine(N, M, far_slots(c, N), c->part, 1.0 / c->opt.eta, nullptr, 0.0, nullptr, nullptr,
                           0.0, c->t1, st));
   HIPCHECK(launch_moments(n, M, c->t1, c->X, c->W, c->cen, c->mom, st));
   HIPCHECK(launch_velocity_self(n, M, c->sid, c->V0, c->Rm, c->t2, c->vws, st));
@@ -682,6 +775,7 @@ static rbm_status solve_impl(rbm_ctx* c, const double* dFT, double* dVW, rbm_sol
     info->n_traction = (int)S.trac_ev.size();
     info->n_stokeslet = (int)S.stok_ev.size();
     info->pairs_per_launch = (double)N * N - (double)n * M * M;
+    info->near_pairs = c->pu ? c->near_pairs : 0;
     if (total.on) {
       float ms = 0;
       (void)hipEventElapsedTime(&ms, total.a, total.b);
@@ -698,6 +792,10 @@ static rbm_status solve_impl(rbm_ctx* c, const double* dFT, double* dVW, rbm_sol
       for (auto& e : S.self_ev) {
         (void)hipEventElapsedTime(&ms, c->ev[e.first], c->ev[e.second]);
         info->ms_self += ms;
+      }
+      for (auto& e : S.near_ev) {
+        (void)hipEventElapsedTime(&ms, c->ev[e.first], c->ev[e.second]);
+        info->ms_near += ms;
       }
     }
   }
@@ -742,6 +840,21 @@ extern "C" rbm_status rbm_get_density(rbm_ctx* c, double* mu, double* rho) {
   return RBM_OK;
 }
 
+extern "C" rbm_status rbm_apply_dev(rbm_ctx* c, const double* d_mu, double* d_y) {
+  if (!c || !d_mu || !d_y) return fail(RBM_E_INVAL, "null argument");
+  if (!c->ws) return fail(RBM_E_NOMEM, "bind a workspace first");
+  if (!c->setup_done) return fail(RBM_E_STATE, "call rbm_setup first");
+  if (c->n < 1) return fail(RBM_E_STATE, "set bodies first");
+  if (d_mu == d_y) return fail(RBM_E_INVAL, "d_mu and d_y must not alias");
+  rbm_status s;
+  if ((s = upload_bodies(c)) != RBM_OK) return s;
+  SolveState S;
+  c->ev_used = 0;
+  if ((s = apply_A(c, S, d_mu, d_y)) != RBM_OK) return s;
+  HIPCHECK(hipStreamSynchronize(c->st));
+  return RBM_OK;
+}
+
 extern "C" const void* rbm_debug_ptr(rbm_ctx* c, const char* name) {
   if (!c || !name || !c->ws) return nullptr;
   const std::string s(name);
@@ -763,6 +876,12 @@ extern "C" const void* rbm_debug_ptr(rbm_ctx* c, const char* name) {
   if (s == "Rm") return c->Rm;
   if (s == "Ftab") return c->Ftab;
   if (s == "Ytab") return c->Ytab;
+  if (s == "U") return c->U;
+  if (s == "fr") return c->fr;
+  if (s == "fw") return c->fw;
+  if (s == "rb") return c->rb;
+  if (s == "near_list") return c->nbr;
+  if (s == "near_count") return c->ncnt;
   if (s == "learned_X") return c->L.bound ? c->L.Xbuf : nullptr;
   if (s == "learned_T") return c->L.bound ? c->L.Tbuf : nullptr;
   return nullptr;
@@ -829,7 +948,7 @@ static rbm_status refresh_nodes(rbm_ctx* c) {
   HIPCHECK(launch_body_prep(c->n, c->quat, c->sid, c->shp, c->Rm, c->tauinv, c->area_b, c->st));
   HIPCHECK(launch_nodes(c->n, c->M, c->sid, c->cen, c->Rm, c->gr, c->gn, c->gw, c->X, c->Nn, c->W,
                         c->Xf, c->Nf, c->st));
-  return RBM_OK;
+  return build_near(c);
 }
 
 extern "C" rbm_status rbm_step_rk4(rbm_ctx* c, double dt, const double* d_FT,

@@ -26,6 +26,7 @@ EXPORTED = [
     "rbm_learned_capture", "rbm_learned_set_capture", "rbm_learned_train", "rbm_learned_info",
     "rbm_learned_get_params", "rbm_learned_set_params", "rbm_learned_forward_dev",
     "rbm_learned_loss_grad_dev", "rbm_learned_features_dev", "rbm_learned_guess_dev", "rbm_set_guess",
+    "rbm_apply_dev",
 ]
 
 
@@ -33,7 +34,7 @@ class Options(ctypes.Structure):
     _fields_ = [("p", ctypes.c_int), ("p_sing", ctypes.c_int), ("eta", ctypes.c_double),
                 ("tol", ctypes.c_double), ("max_iter", ctypes.c_int), ("max_restart", ctypes.c_int),
                 ("precision", ctypes.c_int), ("guess", ctypes.c_int), ("inner_tol", ctypes.c_double),
-                ("stream", ctypes.c_void_p)]
+                ("stream", ctypes.c_void_p), ("p_up", ctypes.c_int), ("near_factor", ctypes.c_double)]
 
 
 class SolveInfo(ctypes.Structure):
@@ -44,7 +45,8 @@ class SolveInfo(ctypes.Structure):
                 ("n_stokeslet", ctypes.c_int), ("ms_traction", ctypes.c_double),
                 ("ms_stokeslet", ctypes.c_double), ("pairs_per_launch", ctypes.c_double),
                 ("guess_used", ctypes.c_int), ("fallback_used", ctypes.c_int),
-                ("init_rel_residual", ctypes.c_double)]
+                ("init_rel_residual", ctypes.c_double), ("near_pairs", ctypes.c_int),
+                ("ms_near", ctypes.c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -101,6 +103,7 @@ def load():
         "rbm_learned_features_dev": (I, [P, P, P]),
         "rbm_learned_guess_dev": (I, [P, P, P]),
         "rbm_set_guess": (I, [P, I]),
+        "rbm_apply_dev": (I, [P, P, P]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -138,7 +141,7 @@ class Solver:
 
     def __init__(self, p, shapes, shape_id, centres, quats, eta=1.0, p_sing=0, tol=1e-12,
                  max_iter=100, max_restart=4, precision=FP64, guess=GUESS_BLOCKDIAG,
-                 inner_tol=1e-4, n_max=None, stream=None, device="cuda"):
+                 inner_tol=1e-4, n_max=None, stream=None, device="cuda", p_up=0, near_factor=5.0):
         import torch
         lib = load()
         self.torch = torch
@@ -148,6 +151,7 @@ class Solver:
         opt.p, opt.p_sing, opt.eta, opt.tol = p, p_sing, eta, tol
         opt.max_iter, opt.max_restart, opt.precision, opt.guess = max_iter, max_restart, precision, guess
         opt.inner_tol = inner_tol
+        opt.p_up, opt.near_factor = p_up, near_factor
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
         opt.stream = ctypes.c_void_p(self.stream.cuda_stream)
         self.opt = opt
@@ -218,6 +222,13 @@ class Solver:
                     allow=(RBM_E_NOCONV,))
         self.last_status = st
         return info.as_dict()
+
+    def apply_dev(self, mu_dev):
+        """y = A mu at the current poses; mu_dev: float64 (3, N) CUDA tensor."""
+        y = self.torch.empty_like(mu_dev)
+        _check(load().rbm_apply_dev(self.ctx, ctypes.c_void_p(mu_dev.data_ptr()),
+                                    ctypes.c_void_p(y.data_ptr())))
+        return y
 
     def step_rk4(self, dt, FT_dev):
         """One RK4 step with loads FT_dev (float64 (n, 6) CUDA tensor); returns the

@@ -16,11 +16,11 @@ def oracle_shapes(w, with_ops=True, ps=None):
             for s in w["shapes"]]
 
 
-def oracle_problem(w, with_ops=True, ps=None):
+def oracle_problem(w, with_ops=True, ps=None, upsample=None):
     shapes = oracle_shapes(w, with_ops, ps)
     q = np.asarray(w["quats"], dtype=np.float64)
     q = q / np.linalg.norm(q, axis=1)[:, None]
-    return sy.Problem(shapes, w["shape_id"], w["centres"], q, eta=w.get("eta", 1.0))
+    return sy.Problem(shapes, w["shape_id"], w["centres"], q, eta=w.get("eta", 1.0), upsample=upsample)
 
 
 def rel_err(a, b):
