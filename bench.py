@@ -66,9 +66,13 @@ def _cpu_baseline(w, budget_s):
 
 
 def _kernel_source_hash():
+    """sha256 of the far-sum kernel's sources (the kernel file and its pair arithmetic)."""
     import hashlib
-    with open(os.path.join(ROOT, "paper_1606_07428_amd", "csrc", "k_far.hip"), "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()
+    h = hashlib.sha256()
+    for name in ("k_far.hip", "pair.h"):
+        with open(os.path.join(ROOT, "paper_1606_07428_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
 
 
 def _traffic(kernel, workload):
@@ -295,17 +299,24 @@ def main_compare(args):
         del st
         torch.cuda.empty_cache()
         _log(f"trained on {args.learned_from}: {learned}")
-    forms = [("fp64", rbm.FP64, False), ("mixed_fp32", rbm.MIXED_FP32, False),
-             ("mixed_bf16", rbm.MIXED_BF16, False)]
+    pu = args.p_up
+    forms = [("fp64", rbm.FP64, False, pu), ("mixed_fp32", rbm.MIXED_FP32, False, pu),
+             ("mixed_bf16", rbm.MIXED_BF16, False, pu)]
     if params is not None:
-        forms.append(("mixed_fp32_learned", rbm.MIXED_FP32, True))
+        forms.append(("mixed_fp32_learned", rbm.MIXED_FP32, True, pu))
     if args.forms:
         keep = set(args.forms.split(","))
         forms = [f for f in forms if f[0] in keep]
+    if pu:
+        # the plain smooth rule first: the upsampled float64 solve is then the reference
+        forms.insert(0, ("fp64_plain", rbm.FP64, False, 0))
+        out["p_up"], out["near_factor"] = pu, args.near_factor
     ref = None
-    for name, prec, use_net in forms:
+    plain = None
+    for name, prec, use_net, form_pu in forms:
         t0 = time.perf_counter()
-        s = rbm.solver_for(w, tol=args.tol, precision=prec, guess=rbm.GUESS_BLOCKDIAG)
+        s = rbm.solver_for(w, tol=args.tol, precision=prec, guess=rbm.GUESS_BLOCKDIAG, p_up=form_pu,
+                           near_factor=args.near_factor)
         if use_net:
             s.learned_bind(k_nbr=8, hidden=256, n_hidden=3, capacity=1, batch_max=1024, seed=7)
             s.learned_set_params(params)
@@ -314,7 +325,9 @@ def main_compare(args):
         setup = time.perf_counter() - t0
         dt, infos = _timed(torch, s, FT, VW, args.steps, args.warmup)
         v = VW.cpu().numpy().copy()
-        if ref is None:
+        if form_pu == 0 and pu:
+            plain = v
+        elif ref is None:
             ref = v
         i = infos[-1]
         out["forms"][name] = {
@@ -323,14 +336,64 @@ def main_compare(args):
             "traction_launch_ms_avg": i["ms_traction"] / max(i["n_traction"], 1),
             "stokeslet_ms": i["ms_stokeslet"], "self_ms": i["ms_self"],
             "pairs_per_launch": i["pairs_per_launch"],
-            "velocity_rel_err_vs_fp64": float(np.abs(v - ref).max() / np.abs(ref).max()),
+            "velocity_rel_err_vs_fp64": float(np.abs(v - ref).max() / np.abs(ref).max()) if ref is not None else 0.0,
             "init_rel_residual": i["init_rel_residual"], "fallback": i["fallback_used"],
+            "near_pairs": i["near_pairs"], "near_ms": i["ms_near"],
             "workspace_GB": s.workspace_bytes / 1e9}
+        if plain is not None and form_pu:
+            out["forms"][name]["velocity_change_vs_plain_rule"] = float(np.abs(v - plain).max() / np.abs(plain).max())
         _log(f"{name}: {json.dumps(out['forms'][name])}")
         s.close()
         del s
         torch.cuda.empty_cache()
     print(json.dumps(out), flush=True)
+
+
+# Table 2 of the paper (§4): seconds per time step on one Xeon core with an FMM, for the
+# 2 x 2 x n/4 sphere lattice; "Apply" is one application of the operator, "Solve" the GMRES
+# solve to 1e-6.  Context only (other hardware, other far-field algorithm).
+PAPER_TABLE2 = {(32, 8): (1.09, 10.25), (64, 8): (2.26, 19.51), (128, 8): (4.75, 38.41),
+                (32, 16): (10.7, 108.9), (64, 16): (21.5, 220.3), (128, 16): (42.9, 439.9)}
+
+
+def main_lattice(args):
+    """Per-matvec and per-solve times on the paper's sphere lattice (float64, block-diagonal
+    guess, tolerance 1e-6 as in the paper), next to the paper's Table 2."""
+    import torch
+    from paper_1606_07428_amd import inputs, rbm
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    rows = []
+    for (n, p), (apply_s, solve_s) in sorted(PAPER_TABLE2.items(), key=lambda t: (t[0][1], t[0][0])):
+        w = inputs.lattice(n, p)
+        s = rbm.solver_for(w, tol=1e-6, precision=rbm.FP64, guess=rbm.GUESS_BLOCKDIAG)
+        N = n * 2 * p * (p + 1)
+        mu = torch.randn(3, N, dtype=torch.float64, device=dev)
+        s.apply_dev(mu)
+        torch.cuda.synchronize()
+        reps = 20
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            s.apply_dev(mu)
+        torch.cuda.synchronize()
+        t_apply = (time.perf_counter() - t0) / reps
+        FT = torch.as_tensor(np.asarray(w["FT"]), device=dev)
+        VW = torch.zeros_like(FT)
+        dt, infos = _timed(torch, s, FT, VW, args.steps, args.warmup)
+        row = {"n": n, "p": p, "unknowns": 3 * N, "apply_ms": t_apply * 1e3,
+               "solve_ms": dt / args.steps * 1e3, "iters": infos[-1]["iters"],
+               "rel_residual": infos[-1]["rel_residual"],
+               "paper_apply_s": apply_s, "paper_solve_s": solve_s,
+               "apply_ratio_paper_over_ours": apply_s / t_apply,
+               "solve_ratio_paper_over_ours": solve_s / (dt / args.steps)}
+        _log(json.dumps(row))
+        rows.append(row)
+        s.close()
+        del s
+        torch.cuda.empty_cache()
+    print(json.dumps({"experiment": "paper lattice (§4, Table 2)", "precision": "fp64", "tol": 1e-6,
+                      "rows": rows}), flush=True)
 
 
 def main():
@@ -355,6 +418,13 @@ def main():
     ap.add_argument("--learned-from", default=None,
                     help="with --compare: train the warm start on this workload's trajectory and "
                          "add a mixed fp32 + learned solve (same p and feature layout)")
+    ap.add_argument("--p-up", type=int, default=0,
+                    help="compare mode: near-singular upsampling order (0 = off); adds a plain-rule "
+                         "float64 reference solve")
+    ap.add_argument("--near-factor", type=float, default=5.0,
+                    help="compare mode: kappa of the near test (mean node spacings)")
+    ap.add_argument("--lattice", action="store_true",
+                    help="per-matvec and per-solve times on the paper's sphere lattice (Table 2)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (HBM counter calibration)")
     args = ap.parse_args()
@@ -375,6 +445,9 @@ def main():
     if args.compare:
         args.workload = args.workload or "ellipsoids1000"
         main_compare(args)
+        return
+    if args.lattice:
+        main_lattice(args)
         return
     if args.learned_experiment:
         args.workload = args.workload or "sediment512"

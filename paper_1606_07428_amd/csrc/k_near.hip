@@ -2,9 +2,9 @@
 // smooth rule over that body is evaluated on a finer grid of order p_u.  The geometry
 // is evaluated exactly from the shape's SH coefficients at the fine nodes and the
 // density by its band-limited interpolant.  This file holds the setup (fine geometry,
-// bounding radii, interpolation matrix), the per-pose near list, the interpolation
-// GEMM, the packing of fine sources and the correction sum, which uses the same pair
-// arithmetic (pair.h) as the all-pairs sum of k_far.hip.
+// bounding radii, interpolation matrix), the per-pose near list, the interpolation of
+// fine sources and the correction sum, which uses the same pair arithmetic (pair.h) as
+// the all-pairs sum of k_far.hip.
 #include "common.h"
 #include "kernels.h"
 #include "pair.h"
@@ -141,93 +141,6 @@ __global__ void k_near_list(int n, int M, int kmax, double kappa, const double* 
   cnt[i] = c;
 }
 
-// Fine sources: X' = c_i + R_i r'_{s(i)}, q' = w' (R_i) zt, zt = U z per component
-// ([3][n*Mu]); z in body frames when z_is_body.
-template <typename T>
-__global__ void k_pack_fine(int n, int Mu, const int* __restrict__ sid, const double* __restrict__ cen,
-                            const double* __restrict__ Rm, const double* __restrict__ fr_all,
-                            const double* __restrict__ fw_all, const double* __restrict__ zt,
-                            int z_is_body, Src8<T>* __restrict__ srcf) {
-  const size_t Nu = (size_t)n * Mu;
-  const size_t g = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (g >= Nu) return;
-  const int i = (int)(g / Mu), b = (int)(g % Mu), s = sid[i];
-  const double* R = Rm + 9 * i;
-  const double* fr = fr_all + (size_t)s * 3 * Mu;
-  const double r0 = fr[b], r1 = fr[Mu + b], r2 = fr[2 * (size_t)Mu + b];
-  double v0 = zt[g], v1 = zt[Nu + g], v2 = zt[2 * Nu + g];
-  if (z_is_body) {
-    const double a0 = R[0] * v0 + R[1] * v1 + R[2] * v2;
-    const double a1 = R[3] * v0 + R[4] * v1 + R[5] * v2;
-    const double a2 = R[6] * v0 + R[7] * v1 + R[8] * v2;
-    v0 = a0; v1 = a1; v2 = a2;
-  }
-  const double w = fw_all[(size_t)s * Mu + b];
-  Src8<T> o;
-  o.v[0] = (T)(cen[3 * i] + R[0] * r0 + R[1] * r1 + R[2] * r2);
-  o.v[1] = (T)(cen[3 * i + 1] + R[3] * r0 + R[4] * r1 + R[5] * r2);
-  o.v[2] = (T)(cen[3 * i + 2] + R[6] * r0 + R[7] * r1 + R[8] * r2);
-  o.v[3] = (T)(w * v0);
-  o.v[4] = (T)(w * v1);
-  o.v[5] = (T)(w * v2);
-  o.v[6] = 0;
-  o.v[7] = 0;
-  srcf[g] = o;
-}
-
-// C (Mr x Nc) = A (Mr x K) B (K x Nc), all column-major with leading dimensions Mr, K,
-// Mr, on v_mfma_f64_16x16x4_f64: 64 x 64 tile per workgroup, 2 x 2 MFMA tiles per wave,
-// K staged by 16 through LDS.  Lane l holds A[l%16][l/16] and B[l/16][l%16] and
-// receives D[(l/16) + 4e][l%16] (the float64 instruction's result layout on gfx950).
-typedef double d4v_n __attribute__((ext_vector_type(4)));
-__global__ __launch_bounds__(256) void k_gemm_f64(int Mr, int K, int Nc, const double* __restrict__ A,
-                                                  const double* __restrict__ B, double* __restrict__ C) {
-  __shared__ double As[64][17];
-  __shared__ double Bs[16][65];
-  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
-  const int bm = blockIdx.y * 64, bn = blockIdx.x * 64;
-  const int wr = (wid >> 1) * 32, wc = (wid & 1) * 32;
-  d4v_n acc[2][2];
-  for (int x = 0; x < 2; ++x)
-    for (int y = 0; y < 2; ++y)
-      for (int e = 0; e < 4; ++e) acc[x][y][e] = 0.0;
-  const int lr = lane & 15, lk = lane >> 4;
-  for (int k0 = 0; k0 < K; k0 += 16) {
-    for (int e = tid; e < 1024; e += 256) {
-      const int r = e & 63, kk = e >> 6;
-      const int gi = bm + r, gk = k0 + kk;
-      As[r][kk] = (gi < Mr && gk < K) ? A[(size_t)gk * Mr + gi] : 0.0;
-    }
-    for (int e = tid; e < 1024; e += 256) {
-      const int kk = e & 15, c = e >> 4;
-      const int gk = k0 + kk, gj = bn + c;
-      Bs[kk][c] = (gk < K && gj < Nc) ? B[(size_t)gj * K + gk] : 0.0;
-    }
-    __syncthreads();
-#pragma unroll
-    for (int ks = 0; ks < 16; ks += 4) {
-#pragma unroll
-      for (int ti = 0; ti < 2; ++ti) {
-        const double av = As[wr + ti * 16 + lr][ks + lk];
-#pragma unroll
-        for (int tj = 0; tj < 2; ++tj)
-          acc[ti][tj] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, Bs[ks + lk][wc + tj * 16 + lr],
-                                                             acc[ti][tj], 0, 0, 0);
-      }
-    }
-    __syncthreads();
-  }
-#pragma unroll
-  for (int ti = 0; ti < 2; ++ti)
-#pragma unroll
-    for (int tj = 0; tj < 2; ++tj)
-#pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        const int row = bm + wr + ti * 16 + lk + 4 * e, col = bn + wc + tj * 16 + lr;
-        if (row < Mr && col < Nc) C[(size_t)col * Mr + row] = acc[ti][tj][e];
-      }
-}
-
 hipError_t launch_fine_geometry(int ns, int p, int pu, const double* coef, const double* glu_t,
                                 const double* glu_w, const double* shp, double* fr, double* fw,
                                 double* rb, hipStream_t st) {
@@ -254,53 +167,108 @@ hipError_t launch_near_list(int n, int M, int kmax, double kappa, const double* 
   return hipGetLastError();
 }
 
+// Fine sources of the bodies listed in `need` (the bodies that are near some body):
+// density zt_c(b) = sum_a U[a][b] z_c(a) (band-limited interpolant; z in body frames when
+// z_is_body, then rotated), X' = c_j + R_j r'_b, q' = w'_b zt, packed like the plain
+// sources.  A 256-thread block covers 32 fine nodes x 8 chunks of the a-sum for kJB
+// listed bodies: short independent load chains, U[a][b] read once per block (coalesced
+// over b) for kJB bodies, partial sums reduced in LDS in a fixed order.
+constexpr int kJB = 4;
 template <typename T>
-hipError_t launch_fine_sources(int n, int M, int Mu, const double* U, const double* z, int z_is_body,
-                               const int* sid, const double* cen, const double* Rm, const double* fr,
-                               const double* fw, double* zt, void* srcf, hipStream_t st) {
-  // zt (Mu x 3n) = U (Mu x M) z (M x 3n): columns are (component, body) pairs
-  dim3 grid((3 * n + 63) / 64, (Mu + 63) / 64);
-  k_gemm_f64<<<grid, 256, 0, st>>>(Mu, M, 3 * n, U, z, zt);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
-  const size_t Nu = (size_t)n * Mu;
-  k_pack_fine<T><<<(unsigned)((Nu + 255) / 256), 256, 0, st>>>(n, Mu, sid, cen, Rm, fr, fw, zt, z_is_body,
-                                                                reinterpret_cast<Src8<T>*>(srcf));
-  return hipGetLastError();
+__global__ __launch_bounds__(256) void k_interp_pack(int n, int M, int Mu, int nneed,
+                                                     const int* __restrict__ need,
+                                                     const double* __restrict__ U,
+                                                     const double* __restrict__ z, int z_is_body,
+                                                     const int* __restrict__ sid,
+                                                     const double* __restrict__ cen,
+                                                     const double* __restrict__ Rm,
+                                                     const double* __restrict__ fr_all,
+                                                     const double* __restrict__ fw_all,
+                                                     Src8<T>* __restrict__ srcf) {
+  __shared__ double part[8][kJB * 3][33];
+  const int bl = threadIdx.x & 31, kc = threadIdx.x >> 5;
+  const int b = blockIdx.x * 32 + bl;
+  const int q0 = blockIdx.y * kJB, jn = min(kJB, nneed - q0);
+  const size_t N = (size_t)n * M;
+  double acc[kJB][3];
+#pragma unroll
+  for (int jj = 0; jj < kJB; ++jj) acc[jj][0] = acc[jj][1] = acc[jj][2] = 0.0;
+  size_t zo[kJB];
+#pragma unroll
+  for (int jj = 0; jj < kJB; ++jj) zo[jj] = (size_t)need[q0 + min(jj, jn - 1)] * M;
+  if (b < Mu) {
+    const int a0 = (M * kc) / 8, a1 = (M * (kc + 1)) / 8;
+#pragma unroll 4
+    for (int a = a0; a < a1; ++a) {
+      const double u = U[(size_t)a * Mu + b];
+#pragma unroll
+      for (int jj = 0; jj < kJB; ++jj) {
+        const size_t g = zo[jj] + a;
+        acc[jj][0] += u * z[g];
+        acc[jj][1] += u * z[N + g];
+        acc[jj][2] += u * z[2 * N + g];
+      }
+    }
+  }
+#pragma unroll
+  for (int jj = 0; jj < kJB; ++jj)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) part[kc][jj * 3 + c][bl] = acc[jj][c];
+  __syncthreads();
+  // 32 nodes x kJB bodies epilogues, one per thread of the first kJB*32 threads
+  const int jj = threadIdx.x >> 5;
+  if (jj >= jn || b >= Mu) return;
+  double v[3];
+  for (int c = 0; c < 3; ++c) {
+    double t = 0.0;
+    for (int k = 0; k < 8; ++k) t += part[k][jj * 3 + c][bl];
+    v[c] = t;
+  }
+  const int j = need[q0 + jj], s = sid[j];
+  const double* R = Rm + 9 * j;
+  if (z_is_body) {
+    const double b0 = R[0] * v[0] + R[1] * v[1] + R[2] * v[2];
+    const double b1 = R[3] * v[0] + R[4] * v[1] + R[5] * v[2];
+    const double b2 = R[6] * v[0] + R[7] * v[1] + R[8] * v[2];
+    v[0] = b0; v[1] = b1; v[2] = b2;
+  }
+  const double* fr = fr_all + (size_t)s * 3 * Mu;
+  const double r0 = fr[b], r1 = fr[Mu + b], r2 = fr[2 * (size_t)Mu + b];
+  const double w = fw_all[(size_t)s * Mu + b];
+  Src8<T> o;
+  o.v[0] = (T)(cen[3 * j] + R[0] * r0 + R[1] * r1 + R[2] * r2);
+  o.v[1] = (T)(cen[3 * j + 1] + R[3] * r0 + R[4] * r1 + R[5] * r2);
+  o.v[2] = (T)(cen[3 * j + 2] + R[6] * r0 + R[7] * r1 + R[8] * r2);
+  o.v[3] = (T)(w * v[0]);
+  o.v[4] = (T)(w * v[1]);
+  o.v[5] = (T)(w * v[2]);
+  o.v[6] = 0;
+  o.v[7] = 0;
+  srcf[(size_t)j * Mu + b] = o;
 }
 
-template hipError_t launch_fine_sources<double>(int, int, int, const double*, const double*, int,
-                                                const int*, const double*, const double*,
-                                                const double*, const double*, double*, void*,
-                                                hipStream_t);
-template hipError_t launch_fine_sources<float>(int, int, int, const double*, const double*, int,
-                                               const int*, const double*, const double*,
-                                               const double*, const double*, double*, void*,
-                                               hipStream_t);
-
-hipError_t launch_gemm_f64_cm(int Mr, int K, int Nc, const double* A, const double* B, double* C,
-                              hipStream_t st) {
-  dim3 grid((Nc + 63) / 64, (Mr + 63) / 64);
-  k_gemm_f64<<<grid, 256, 0, st>>>(Mr, K, Nc, A, B, C);
-  return hipGetLastError();
-}
-
-// Correction of the all-pairs sum for near pairs.  Workgroup (i, s) owns the targets of
-// body i (one per thread) and split s of the concatenated source list of i's near
-// bodies j: for each, the fine sources of j (added) then the plain sources of j
-// (subtracted: the all-pairs sum already counted them).  The list position is uniform
-// over the workgroup, so sources are wave-uniform loads as in the all-pairs kernel.
-// Slot s of out ([S][3][N]) receives the scaled difference for every target of body i,
-// zero when the split is empty, so the slots need no clearing.
+// Correction of the all-pairs sum for near pairs.  The concatenated source list of body
+// i (for each near body j: its M_u fine sources, then its M plain sources with negated
+// strength, since the all-pairs sum already counted them and both kernels are linear in
+// q) is cut into items of ch positions; item t = (body item_body[t], positions
+// [item_pos[t], item_pos[t] + ch) clipped to the list).  The workgroup of item t holds
+// body i's targets (one per thread), stages its positions in LDS (one source per
+// thread, vector loads) and sweeps them as LDS broadcasts; it writes the scaled sums
+// of its targets to slot t ([items][3][M]).
 template <typename T, int KIND>
-__global__ __launch_bounds__(1024) void k_near_corr(int N, int M, int Mu, int kmax,
+__global__ __launch_bounds__(1024) void k_near_corr(int N, int M, int Mu, int kmax, int ch,
+                                                    const int* __restrict__ item_body,
+                                                    const int* __restrict__ item_pos,
                                                     const T* __restrict__ tx, const T* __restrict__ tn,
                                                     const Src8<T>* __restrict__ src,
                                                     const Src8<T>* __restrict__ srcf,
                                                     const int* __restrict__ nbr,
                                                     const int* __restrict__ cnt,
-                                                    double* __restrict__ out) {
-  const int i = blockIdx.x, s = blockIdx.y, S = gridDim.y;
+                                                    double* __restrict__ slots) {
+  extern __shared__ __align__(16) unsigned char lds_raw[];
+  T* sh = reinterpret_cast<T*>(lds_raw);  // [6][blockDim]
+  const int B = blockDim.x;
+  const int t = blockIdx.x, i = item_body[t];
   const int a = threadIdx.x;
   const int g = i * M + min(a, M - 1);
   const T xa = tx[g], ya = tx[N + g], za = tx[2 * (size_t)N + g];
@@ -310,54 +278,117 @@ __global__ __launch_bounds__(1024) void k_near_corr(int N, int M, int Mu, int km
     ny = tn[N + g];
     nz = tn[2 * (size_t)N + g];
   }
-  T px = 0, py = 0, pz = 0, mx = 0, my = 0, mz = 0;
-  const int c = min(cnt[i], kmax);
-  const long seg = (long)Mu + M, L = (long)c * seg;
-  const long lo = L * s / S, hi = L * (s + 1) / S;
-  for (int k = (int)(lo / seg); k < c && (long)k * seg < hi; ++k) {
-    const int j = nbr[(size_t)i * kmax + k];
-    const long base = (long)k * seg;
-    // fine sources of j: list positions [base, base + Mu)
-    const Src8<T>* f = srcf + (size_t)j * Mu;
-    const int f0 = (int)(max(lo, base) - base), f1 = (int)(min(hi, base + Mu) - base);
+  T ax = 0, ay = 0, az = 0;
+  const int seg = Mu + M, L = min(cnt[i], kmax) * seg;
+  const int lo = item_pos[t], hi = min(L, lo + ch);
+  for (int t0 = lo; t0 < hi; t0 += B) {
+    const int m = min(B, hi - t0);
+    __syncthreads();
+    if (a < m) {
+      const int u = t0 + a, k = u / seg, r = u - k * seg;
+      const int j = nbr[(size_t)i * kmax + k];
+      Src8<T> q;
+      T sg = (T)1;
+      if (r < Mu) {
+        q = srcf[(size_t)j * Mu + r];
+      } else {
+        q = src[(size_t)j * M + (r - Mu)];
+        sg = (T)-1;
+      }
+#pragma unroll
+      for (int e = 0; e < 3; ++e) sh[e * B + a] = q.v[e];
+#pragma unroll
+      for (int e = 3; e < 6; ++e) sh[e * B + a] = sg * q.v[e];
+    }
+    __syncthreads();
+    Src8<T> q;
+    q.v[6] = q.v[7] = 0;
 #pragma unroll 4
-    for (int t = f0; t < f1; ++t) Pair<T, KIND>::add(xa, ya, za, nx, ny, nz, f[t], px, py, pz);
-    // plain sources of j: list positions [base + Mu, base + Mu + M)
-    const Src8<T>* q = src + (size_t)j * M;
-    const int c0 = (int)(max(lo, base + Mu) - (base + Mu)), c1 = (int)(min(hi, base + seg) - (base + Mu));
-#pragma unroll 4
-    for (int t = c0; t < c1; ++t) Pair<T, KIND>::add(xa, ya, za, nx, ny, nz, q[t], mx, my, mz);
+    for (int e2 = 0; e2 < m; ++e2) {
+#pragma unroll
+      for (int e = 0; e < 6; ++e) q.v[e] = sh[e * B + e2];
+      Pair<T, KIND>::add(xa, ya, za, nx, ny, nz, q, ax, ay, az);
+    }
   }
   if (a < M) {
     const double scale = KIND == 0 ? -3.0 / (4.0 * RBM_PI) : 1.0 / (8.0 * RBM_PI);
-    double* o = out + (size_t)s * 3 * N;
-    o[g] = scale * ((double)px - (double)mx);
-    o[N + g] = scale * ((double)py - (double)my);
-    o[2 * (size_t)N + g] = scale * ((double)pz - (double)mz);
+    double* o = slots + (size_t)t * 3 * M;
+    o[a] = scale * (double)ax;
+    o[M + a] = scale * (double)ay;
+    o[2 * M + a] = scale * (double)az;
   }
 }
 
+// res[c][i*M + a] = sum over body i's items (item_first[i] .. item_first[i+1]-1, in order)
+// of slot[c][a]; 0 for bodies without near bodies.
+__global__ __launch_bounds__(256) void k_near_reduce(int N, int M, const int* __restrict__ item_first,
+                                                     const double* __restrict__ slots,
+                                                     double* __restrict__ res) {
+  const int i = blockIdx.x;
+  const int e = blockIdx.y * blockDim.x + threadIdx.x;
+  if (e >= 3 * M) return;
+  const int t0 = item_first[i], t1 = item_first[i + 1];
+  double v = 0.0;
+  int t = t0;
+  for (; t + 4 <= t1; t += 4) {
+    const double v0 = slots[(size_t)t * 3 * M + e], v1 = slots[(size_t)(t + 1) * 3 * M + e];
+    const double v2 = slots[(size_t)(t + 2) * 3 * M + e], v3 = slots[(size_t)(t + 3) * 3 * M + e];
+    v += v0;
+    v += v1;
+    v += v2;
+    v += v3;
+  }
+  for (; t < t1; ++t) v += slots[(size_t)t * 3 * M + e];
+  const int comp = e / M, a = e - comp * M;
+  res[(size_t)comp * N + (size_t)i * M + a] = v;
+}
+
 template <typename T>
-hipError_t launch_near_corr(int kind, int n, int M, int Mu, int kmax, int S, const T* tx,
-                            const T* tn, const void* src, const void* srcf, const int* nbr,
-                            const int* cnt, double* out, hipStream_t st) {
+hipError_t launch_near_corr(int kind, int n, int M, int Mu, int kmax, int nneed, const int* need,
+                            int nitems, int ch, const int* item_body, const int* item_pos,
+                            const int* item_first, const T* tx, const T* tn, const void* src,
+                            const double* z, int z_is_body, const double* U, const int* sid,
+                            const double* cen, const double* Rm, const double* fr, const double* fw,
+                            const int* nbr, const int* cnt, void* srcf, double* slots, double* res,
+                            hipStream_t st) {
   const int N = n * M;
-  dim3 grid(n, S);
-  const int bs = ((M + 63) / 64) * 64;
-  const Src8<T>* a = reinterpret_cast<const Src8<T>*>(src);
-  const Src8<T>* b = reinterpret_cast<const Src8<T>*>(srcf);
-  if (kind == 0)
-    k_near_corr<T, 0><<<grid, bs, 0, st>>>(N, M, Mu, kmax, tx, tn, a, b, nbr, cnt, out);
-  else
-    k_near_corr<T, 1><<<grid, bs, 0, st>>>(N, M, Mu, kmax, tx, tn, a, b, nbr, cnt, out);
+  if (nitems > 0 && nneed > 0) {
+    dim3 gi((Mu + 31) / 32, (nneed + kJB - 1) / kJB);
+    k_interp_pack<T><<<gi, 256, 0, st>>>(n, M, Mu, nneed, need, U, z, z_is_body, sid, cen, Rm, fr, fw,
+                                         reinterpret_cast<Src8<T>*>(srcf));
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const int bs = ((M + 63) / 64) * 64;
+    const size_t lds = 6 * (size_t)bs * sizeof(T);
+    const Src8<T>* ps = reinterpret_cast<const Src8<T>*>(src);
+    const Src8<T>* pf = reinterpret_cast<const Src8<T>*>(srcf);
+    if (kind == 0)
+      k_near_corr<T, 0><<<nitems, bs, lds, st>>>(N, M, Mu, kmax, ch, item_body, item_pos, tx, tn, ps, pf,
+                                                 nbr, cnt, slots);
+    else
+      k_near_corr<T, 1><<<nitems, bs, lds, st>>>(N, M, Mu, kmax, ch, item_body, item_pos, tx, tn, ps, pf,
+                                                 nbr, cnt, slots);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  dim3 gr(n, (3 * M + 255) / 256);
+  k_near_reduce<<<gr, 256, 0, st>>>(N, M, item_first, slots, res);
   return hipGetLastError();
 }
 
-template hipError_t launch_near_corr<double>(int, int, int, int, int, int, const double*,
-                                             const double*, const void*, const void*, const int*,
-                                             const int*, double*, hipStream_t);
-template hipError_t launch_near_corr<float>(int, int, int, int, int, int, const float*,
-                                            const float*, const void*, const void*, const int*,
-                                            const int*, double*, hipStream_t);
+template hipError_t launch_near_corr<double>(int, int, int, int, int, int, const int*, int, int,
+                                             const int*, const int*, const int*, const double*,
+                                             const double*, const void*, const double*, int,
+                                             const double*, const int*, const double*,
+                                             const double*, const double*, const double*,
+                                             const int*, const int*, void*, double*, double*,
+                                             hipStream_t);
+template hipError_t launch_near_corr<float>(int, int, int, int, int, int, const int*, int, int,
+                                            const int*, const int*, const int*, const float*,
+                                            const float*, const void*, const double*, int,
+                                            const double*, const int*, const double*,
+                                            const double*, const double*, const double*,
+                                            const int*, const int*, void*, double*, double*,
+                                            hipStream_t);
 
 }  // namespace rbm

@@ -158,18 +158,18 @@ hipError_t launch_interp_matrix(int p, int pu, const double* gl_t, const double*
 // near list per body (increasing j, at most kmax stored) and true counts
 hipError_t launch_near_list(int n, int M, int kmax, double kappa, const double* cen, const int* sid,
                             const double* rb, const double* shp, int* nbr, int* cnt, hipStream_t st);
-// zt = U z (per component and body), then packed fine sources of precision T
+// fine-minus-plain sums for near pairs (kind 0 traction, 1 Stokeslet) of the density z ([3][N],
+// body frames when z_is_body) whose plain sources are packed in src: fine sources of the nneed
+// bodies listed in need (into srcf, n*Mu packed sources), nitems work items of ch list positions
+// (item_body, item_pos) into slots [nitems][3][M], then per body the ordered sum of its items
+// (item_first[i] .. item_first[i+1]-1) into res [3][N] (zero for bodies without near bodies)
 template <typename T>
-hipError_t launch_fine_sources(int n, int M, int Mu, const double* U, const double* z, int z_is_body,
-                               const int* sid, const double* cen, const double* Rm, const double* fr,
-                               const double* fw, double* zt, void* srcf, hipStream_t st);
-// fine-minus-plain sums for near pairs into S slots [S][3][N]; kind 0 traction, 1 Stokeslet
-template <typename T>
-hipError_t launch_near_corr(int kind, int n, int M, int Mu, int kmax, int S, const T* tx,
-                            const T* tn, const void* src, const void* srcf, const int* nbr,
-                            const int* cnt, double* out, hipStream_t st);
-// C (Mr x Nc) = A (Mr x K) B (K x Nc), column-major float64 on MFMA
-hipError_t launch_gemm_f64_cm(int Mr, int K, int Nc, const double* A, const double* B, double* C,
-                              hipStream_t st);
+hipError_t launch_near_corr(int kind, int n, int M, int Mu, int kmax, int nneed, const int* need,
+                            int nitems, int ch, const int* item_body, const int* item_pos,
+                            const int* item_first, const T* tx, const T* tn, const void* src,
+                            const double* z, int z_is_body, const double* U, const int* sid,
+                            const double* cen, const double* Rm, const double* fr, const double* fw,
+                            const int* nbr, const int* cnt, void* srcf, double* slots, double* res,
+                            hipStream_t st);
 
 }  // namespace rbm

@@ -29,13 +29,13 @@ static rbm_status fail(rbm_status s, const std::string& msg) {
       return fail(RBM_E_DEVICE, std::string(#expr) + ": " + hipGetErrorString(e_)); \
   } while (0)
 
-// Near-singular correction: at most kNearMax near bodies per body, the source list of
-// a body split over at most kNearSlotsMax workgroups (and partial-sum slots).
+// Near-singular correction: at most kNearMax near bodies per body.  The concatenated
+// source lists are cut into work items of ch = max(128, ceil(total / kNearWork)) list
+// positions, so that even a few near pairs give enough workgroups and there are at most
+// kNearWork + n items (which bounds the slot scratch).
 constexpr int kMaxPup = 48;
 constexpr int kNearMax = 64;
-constexpr int kNearSlotsMax = 16;
-
-static int near_slots(int n) { return std::max(1, std::min(kNearSlotsMax, (2048 + n - 1) / n)); }
+constexpr int kNearWork = 8192;
 
 struct rbm_ctx {
   rbm_options opt;
@@ -81,10 +81,11 @@ struct rbm_ctx {
   int pu = 0, Mu = 0, near_pairs = 0;
   double kappa = 5.0;
   double *glu_t = nullptr, *glu_w = nullptr, *fr = nullptr, *fw = nullptr, *rb = nullptr,
-         *U = nullptr, *zt = nullptr;
+         *U = nullptr, *nslots = nullptr;
   void* srcf = nullptr;
-  int *nbr = nullptr, *ncnt = nullptr;
-  std::vector<int> ncnt_h;
+  int *nbr = nullptr, *ncnt = nullptr, *nitem = nullptr, *nfirst = nullptr, *nneed = nullptr;
+  int n_items = 0, n_need = 0, item_len = 0;
+  std::vector<int> ncnt_h, nbr_h, items_h, first_h, need_h;
   double* pinned = nullptr;
   // learned warm start
   struct Learned {
@@ -299,16 +300,18 @@ static size_t layout(rbm_ctx* c, int nmax, bool assign) {
   double* srcd = nullptr;
   take(srcd, 8 * N);
   if (assign) c->src = srcd;
-  take(c->part, (size_t)(far_split((int)N) + (c->pu ? kNearSlotsMax : 0)) * N3);
+  take(c->part, (size_t)(far_split((int)N) + (c->pu ? 1 : 0)) * N3);
   if (c->pu) {
-    const size_t Mu = c->Mu, Nu = nm * Mu;
+    const size_t Mu = c->Mu;
     take(c->glu_t, c->pu + 1); take(c->glu_w, c->pu + 1);
     take(c->fr, ns * 3 * Mu); take(c->fw, ns * Mu); take(c->rb, ns);
-    take(c->U, Mu * M); take(c->zt, 3 * Nu);
+    take(c->U, Mu * M);
+    take(c->nslots, (size_t)(kNearWork + nm) * 3 * M);
     double* sf = nullptr;
-    take(sf, 8 * Nu);
+    take(sf, 8 * nm * Mu);
     if (assign) c->srcf = sf;
     take(c->nbr, nm * kNearMax); take(c->ncnt, nm);
+    take(c->nitem, 2 * (kNearWork + nm)); take(c->nfirst, nm + 1); take(c->nneed, nm);
   }
   return off + 256;
 }
@@ -407,14 +410,52 @@ static rbm_status build_near(rbm_ctx* c) {
   if (!c->pu) return RBM_OK;
   HIPCHECK(launch_near_list(c->n, c->M, kNearMax, c->kappa, c->cen, c->sid, c->rb, c->shp, c->nbr,
                             c->ncnt, c->st));
-  c->ncnt_h.resize(c->n);
-  HIPCHECK(hipMemcpyAsync(c->ncnt_h.data(), c->ncnt, c->n * sizeof(int), hipMemcpyDeviceToHost, c->st));
+  const int n = c->n;
+  c->ncnt_h.resize(n);
+  c->nbr_h.resize((size_t)n * kNearMax);
+  HIPCHECK(hipMemcpyAsync(c->ncnt_h.data(), c->ncnt, n * sizeof(int), hipMemcpyDeviceToHost, c->st));
+  HIPCHECK(hipMemcpyAsync(c->nbr_h.data(), c->nbr, (size_t)n * kNearMax * sizeof(int),
+                          hipMemcpyDeviceToHost, c->st));
   HIPCHECK(hipStreamSynchronize(c->st));
   int tot = 0, mx = 0;
   for (int v : c->ncnt_h) { tot += v; mx = std::max(mx, v); }
   if (mx > kNearMax)
     return fail(RBM_E_INVAL, "a body has more than 64 near bodies: lower near_factor");
   c->near_pairs = tot;
+  // work items (body, first list position), per-body item ranges, bodies whose fine
+  // sources are read
+  const long seg = (long)c->Mu + c->M, total = (long)tot * seg;
+  c->item_len = (int)std::max<long>(128, (total + kNearWork - 1) / kNearWork);
+  std::vector<int> body, pos;
+  c->first_h.assign(n + 1, 0);
+  std::vector<char> needed(n, 0);
+  for (int i = 0; i < n; ++i) {
+    c->first_h[i] = (int)body.size();
+    const long L = c->ncnt_h[i] * seg;
+    for (long p0 = 0; p0 < L; p0 += c->item_len) {
+      body.push_back(i);
+      pos.push_back((int)p0);
+    }
+    for (int k = 0; k < c->ncnt_h[i]; ++k) needed[c->nbr_h[(size_t)i * kNearMax + k]] = 1;
+  }
+  c->first_h[n] = (int)body.size();
+  c->n_items = (int)body.size();
+  c->items_h = body;
+  c->items_h.insert(c->items_h.end(), pos.begin(), pos.end());
+  c->need_h.clear();
+  for (int j = 0; j < n; ++j)
+    if (needed[j]) c->need_h.push_back(j);
+  c->n_need = (int)c->need_h.size();
+  if (c->n_items > kNearWork + c->nmax) return fail(RBM_E_INVAL, "near-correction work list overflow");
+  if (c->n_items)
+    HIPCHECK(hipMemcpyAsync(c->nitem, c->items_h.data(), c->items_h.size() * sizeof(int),
+                            hipMemcpyHostToDevice, c->st));
+  HIPCHECK(hipMemcpyAsync(c->nfirst, c->first_h.data(), (n + 1) * sizeof(int), hipMemcpyHostToDevice,
+                          c->st));
+  if (c->n_need)
+    HIPCHECK(hipMemcpyAsync(c->nneed, c->need_h.data(), c->n_need * sizeof(int), hipMemcpyHostToDevice,
+                            c->st));
+  HIPCHECK(hipStreamSynchronize(c->st));
   return RBM_OK;
 }
 
@@ -461,30 +502,31 @@ struct SolveState {
 };
 
 // Partial-sum slots the combine adds for N points: the far sum's split plus, with
-// upsampling, the near-correction slots that follow it.
-static int far_slots(const rbm_ctx* c, int N) {
-  return split_for(c, N) + (c->pu ? near_slots(c->n) : 0);
-}
+// upsampling, the near-correction slot that follows it.
+static int far_slots(const rbm_ctx* c, int N) { return split_for(c, N) + (c->pu ? 1 : 0); }
 
 // Near-singular correction of the far sum of kind (0 traction, 1 Stokeslet) for the
-// density x whose plain sources are already packed in c->src: fine sources of x, then
-// fine-minus-plain sums for the near pairs into the slots after the far split.
+// density x whose plain sources are already packed in c->src: fine sources of the needed
+// bodies, fine-minus-plain sums per work item, reduced per body into the slot after the
+// far split.
 static rbm_status near_correction(rbm_ctx* c, SolveState& S, int kind, const double* x,
                                   int x_is_body, int prec) {
   if (!c->pu) return RBM_OK;
   const int n = c->n, M = c->M, N = n * M;
-  double* out = c->part + (size_t)split_for(c, N) * 3 * N;
+  double* res = c->part + (size_t)split_for(c, N) * 3 * N;
+  const int* ib = c->nitem;
+  const int* ip = c->nitem + c->n_items;
   Timer t(c);
   if (prec == 0) {
-    HIPCHECK(launch_fine_sources<double>(n, M, c->Mu, c->U, x, x_is_body, c->sid, c->cen, c->Rm, c->fr,
-                                         c->fw, c->zt, c->srcf, c->st));
-    HIPCHECK(launch_near_corr<double>(kind, n, M, c->Mu, kNearMax, near_slots(n), c->X, c->Nn, c->src,
-                                      c->srcf, c->nbr, c->ncnt, out, c->st));
+    HIPCHECK(launch_near_corr<double>(kind, n, M, c->Mu, kNearMax, c->n_need, c->nneed, c->n_items,
+                                      c->item_len, ib, ip, c->nfirst, c->X, c->Nn, c->src, x, x_is_body,
+                                      c->U, c->sid, c->cen, c->Rm, c->fr, c->fw, c->nbr, c->ncnt, c->srcf,
+                                      c->nslots, res, c->st));
   } else {
-    HIPCHECK(launch_fine_sources<float>(n, M, c->Mu, c->U, x, x_is_body, c->sid, c->cen, c->Rm, c->fr,
-                                        c->fw, c->zt, c->srcf, c->st));
-    HIPCHECK(launch_near_corr<float>(kind, n, M, c->Mu, kNearMax, near_slots(n), c->Xf, c->Nf, c->src,
-                                     c->srcf, c->nbr, c->ncnt, out, c->st));
+    HIPCHECK(launch_near_corr<float>(kind, n, M, c->Mu, kNearMax, c->n_need, c->nneed, c->n_items,
+                                     c->item_len, ib, ip, c->nfirst, c->Xf, c->Nf, c->src, x, x_is_body,
+                                     c->U, c->sid, c->cen, c->Rm, c->fr, c->fw, c->nbr, c->ncnt, c->srcf,
+                                     c->nslots, res, c->st));
   }
   t.stop();
   if (t.on) S.near_ev.push_back({c->ev_used - 2, c->ev_used - 1});

@@ -147,6 +147,19 @@ def workload(name, seed=None):
     raise KeyError(name)
 
 
+def lattice(n, p):
+    """The paper's scaling workload (§4): a 2 x 2 x n/4 lattice of unit spheres with centre
+    spacing 5, identity orientations, sedimenting under F = (0, 0, -1), T = 0."""
+    if n % 4:
+        raise ValueError("n must be a multiple of 4")
+    nz = n // 4
+    cen = np.array([[5.0 * i, 5.0 * j, 5.0 * k] for k in range(nz) for j in range(2) for i in range(2)])
+    FT = np.zeros((n, 6))
+    FT[:, 2] = -1.0
+    return dict(name=f"lattice{n}_p{p}", p=p, eta=1.0, shapes=[("radial", np.array([math.sqrt(4 * math.pi)]))],
+                shape_id=np.zeros(n, np.int32), centres=cen, quats=np.tile([1.0, 0.0, 0.0, 0.0], (n, 1)), FT=FT)
+
+
 def workload_perturbed(n, p, phi, gap, rng, name="perturbed", lmax=4, amp=0.1):
     """n distinct SH-perturbed spheres (one shape each), volume fraction phi."""
     shapes = [("radial", _radial_perturbed(rng, lmax, amp)) for _ in range(n)]
