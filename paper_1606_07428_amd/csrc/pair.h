@@ -27,7 +27,9 @@ __device__ __forceinline__ double rinv5_t(double r2) {
   const double y2 = y * y;
   const double e = fma(-r2, y2, 1.0);
   const double y5 = y2 * y2 * y;
-  return y5 * fma(e, fma(e, 4.375, 2.5), 1.0);
+  // 1 + 5e/2 + 35e^2/8 = 1 + (5e/2)(1 + 7e/4): every step has at most one constant that
+  // is not an inline operand, so no constant has to be rebuilt in registers per pair
+  return y5 * fma(2.5 * e, fma(e, 1.75, 1.0), 1.0);
 }
 __device__ __forceinline__ float rinv5_t(float r2) {
   const float y = __builtin_amdgcn_rsqf(r2);
