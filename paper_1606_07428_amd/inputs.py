@@ -103,11 +103,12 @@ def workload(name, seed=None):
     'single_sphere', 'random64' (64 SH-perturbed bodies, p = 12),
     'ellipsoids1000' (1000 ellipsoids (1, .8, .6), p = 16), 'sediment512'
     (512 perturbed spheres, F = (0,0,-1)), 'dense4000' (4000 perturbed spheres at
-    volume fraction 20 %, gap 0.1) and 'dense512' (its smaller, separately seeded
-    sibling); ``tiny`` and ``workload_perturbed`` build other sizes.
+    volume fraction 20 %, gap 0.1), 'dense4000_train' (the same generator, another seed)
+    and 'dense512' (a smaller, separately seeded sibling); ``tiny``, ``lattice`` and
+    ``workload_perturbed`` build other configurations.
     """
     cfg_index = {"two_spheres": 0, "single_sphere": 0, "random64": 1, "ellipsoids1000": 2,
-                 "sediment512": 3, "dense4000": 4, "dense512": 5}
+                 "sediment512": 3, "dense4000": 4, "dense512": 5, "dense4000_train": 6}
     if seed is None:
         seed = BASE_SEED + cfg_index.get(name, 99)
     rng = np.random.default_rng(seed)
@@ -129,6 +130,10 @@ def workload(name, seed=None):
         w["FT"][:, 3:] = math.sqrt(0.1) * rng.standard_normal((512, 3))
         return w
     if name == "dense4000":
+        return workload_perturbed(4000, 12, 0.20, 0.1, rng, name)
+    if name == "dense4000_train":
+        # the dense configuration's generator with another seed: time-stepped to train the
+        # warm start that is then evaluated on dense4000
         return workload_perturbed(4000, 12, 0.20, 0.1, rng, name)
     if name == "dense512":
         # a smaller, separately seeded suspension with the dense configuration's statistics
