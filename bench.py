@@ -107,17 +107,21 @@ def _dt_rule(VW):
     return 0.02 / max(np.abs(v - v.mean(axis=0)).max(), 1e-12)
 
 
-def _train_on_trajectory(rbm, torch, w, FT, tol, steps, epochs, lr, precision):
-    s = rbm.solver_for(w, tol=tol, precision=precision, guess=rbm.GUESS_BLOCKDIAG)
+def _train_on_trajectory(rbm, torch, w, FT, tol, steps, epochs, lr, precision, p_up=0, near_factor=5.0):
+    s = rbm.solver_for(w, tol=tol, precision=precision, guess=rbm.GUESS_BLOCKDIAG, p_up=p_up,
+                       near_factor=near_factor)
     s.learned_bind(k_nbr=8, hidden=256, n_hidden=3, capacity=max(4 * steps * s.n, 1),
                    batch_max=1024, seed=7)
     VW = torch.zeros_like(FT)
     s.solve_dev(FT, VW)
     dt = _dt_rule(VW.cpu().numpy())
+    _log(f"training trajectory: dt {dt:.4g}, {steps} RK4 steps")
     s.learned_set_capture(True)
     t0 = time.perf_counter()
-    for _ in range(steps):
+    for k in range(steps):
         s.step_rk4(dt, FT)
+        torch.cuda.synchronize()
+        _log(f"  RK4 step {k + 1}/{steps} done ({time.perf_counter() - t0:.1f} s)")
     torch.cuda.synchronize()
     t_traj = time.perf_counter() - t0
     s.learned_set_capture(False)
@@ -280,6 +284,7 @@ def main_compare(args):
     from paper_1606_07428_amd import inputs, rbm
 
     w = inputs.workload(args.workload)
+    _log(f"workload {args.workload} generated")
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     n = len(w["shape_id"])
@@ -290,9 +295,10 @@ def main_compare(args):
     params = None
     if args.learned_from:
         ws = inputs.workload(args.learned_from)
+        _log(f"training workload {args.learned_from} generated")
         FTs = torch.as_tensor(np.asarray(ws["FT"], dtype=np.float64), device=dev)
         st, _, learned = _train_on_trajectory(rbm, torch, ws, FTs, args.tol, args.train_steps or 25,
-                                              args.epochs, 1e-3, rbm.MIXED_FP32)
+                                              args.epochs, 1e-3, rbm.MIXED_FP32, args.p_up, args.near_factor)
         params = st.learned_params()
         out["learned_transfer"] = dict(learned, trained_on=args.learned_from)
         st.close()
@@ -323,6 +329,7 @@ def main_compare(args):
             s.set_guess_mode(rbm.GUESS_LEARNED)
         torch.cuda.synchronize()
         setup = time.perf_counter() - t0
+        _log(f"{name}: setup {setup:.2f} s")
         dt, infos = _timed(torch, s, FT, VW, args.steps, args.warmup)
         v = VW.cpu().numpy().copy()
         if form_pu == 0 and pu:

@@ -88,6 +88,9 @@ typedef struct {
   double near_factor; /* kappa of the near test |c_i - c_j| < R_i + R_j + kappa h_j (R: largest
                          centroid-to-node distance on the fine grid, h_j = sqrt(|Gamma_j|/M));
                          0 -> 5 */
+  double contact_delta; /* rbm_step_rk4 only: > 0 switches on the contact forces of §3.3 at every
+                           stage (bodies whose closest nodes are within contact_delta, see
+                           rbm_find_contacts / rbm_solve_contacts); 0 = off */
 } rbm_options;
 
 typedef struct {
@@ -236,6 +239,26 @@ rbm_status rbm_get_density(rbm_ctx* ctx, double* mu, double* rho);
  * near pairs when p_up > 0), at the current poses.  d_mu and d_y must not alias.
  * Synchronous on the context stream. */
 rbm_status rbm_apply_dev(rbm_ctx* ctx, const double* d_mu, double* d_y);
+
+/* Contact search (§3.3, contact force algorithm): body pairs a < b whose closest pair of
+ * nodes is less than delta apart, at the current poses; the contact point is the
+ * midpoint of that node pair (ties: smallest node indices).  Writes the first
+ * min(found, max_contacts) pairs ([k][2], increasing a then b) and points ([k][3]) to
+ * host arrays and the number found to *n_found.  Fails with RBM_E_INVAL when more than
+ * 32 n candidate pairs have bounding spheres within delta. */
+rbm_status rbm_find_contacts(rbm_ctx* ctx, double delta, int max_contacts, int* n_found,
+                             int* pairs, double* points);
+
+/* Mobility solve with contact forces (§3.3): for each contact k (bodies a, b touching at
+ * x_k) a force F_k on a and -F_k on b, both at x_k, chosen so that the rigid motions agree
+ * at x_k: (D M C) F_c = -D V_0 with V_0 the velocities for the loads FT, one mobility
+ * solve per unit contact-force component (3 n_contacts solves), the small system solved
+ * on the host by LU with partial pivoting; V = V_0 + M C F_c.  FT, VW: host [n][6];
+ * pairs [n_contacts][2], points [n_contacts][3], Fc [n_contacts][3] (force on body a).
+ * info: the V_0 solve's record with iterations, matvecs and times summed over all
+ * solves.  RBM_E_INVAL for a singular contact system. */
+rbm_status rbm_solve_contacts(rbm_ctx* ctx, const double* FT, int n_contacts, const int* pairs,
+                              const double* points, double* VW, double* Fc, rbm_solve_info* info);
 
 /* Device pointers of internal arrays for inspection (valid until the workspace is
  * rebound).  name: "X","N","W" ([3][N]/[N] lab nodes, normals, weights), "mu",

@@ -391,4 +391,63 @@ template hipError_t launch_near_corr<float>(int, int, int, int, int, int, const 
                                             const int*, const int*, void*, double*, double*,
                                             hipStream_t);
 
+// Contact search (§3.3 contact force algorithm): for candidate body pairs (a, b), the
+// closest pair of nodes, by the smallest (|X_a - X_b|^2, ia * M + ib) so that ties go to
+// the smallest node indices; out[k] = (d^2, index, x* = midpoint).  One workgroup per pair.
+__global__ __launch_bounds__(256) void k_closest_pair(int N, int M, const int* __restrict__ cand,
+                                                      const double* __restrict__ X,
+                                                      double* __restrict__ out) {
+  __shared__ double sd[256];
+  __shared__ long si[256];
+  const int k = blockIdx.x;
+  const int a = cand[2 * k], b = cand[2 * k + 1];
+  double best = 1e300;
+  long bi = 0x7fffffffffffffffL;
+  const long MM = (long)M * M;
+  for (long e = threadIdx.x; e < MM; e += 256) {
+    const int ia = (int)(e / M), ib = (int)(e - (long)ia * M);
+    const size_t ga = (size_t)a * M + ia, gb = (size_t)b * M + ib;
+    const double dx = X[ga] - X[gb], dy = X[N + ga] - X[N + gb], dz = X[2 * (size_t)N + ga] - X[2 * (size_t)N + gb];
+    const double d2 = dx * dx + dy * dy + dz * dz;
+    if (d2 < best || (d2 == best && e < bi)) {
+      best = d2;
+      bi = e;
+    }
+  }
+  sd[threadIdx.x] = best;
+  si[threadIdx.x] = bi;
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if (threadIdx.x < h) {
+      const double d = sd[threadIdx.x + h];
+      const long i = si[threadIdx.x + h];
+      if (d < sd[threadIdx.x] || (d == sd[threadIdx.x] && i < si[threadIdx.x])) {
+        sd[threadIdx.x] = d;
+        si[threadIdx.x] = i;
+      }
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    const long e = si[0];
+    const int ia = (int)(e / M), ib = (int)(e - (long)ia * M);
+    const size_t ga = (size_t)a * M + ia, gb = (size_t)b * M + ib;
+    out[5 * k] = sd[0];
+    out[5 * k + 1] = (double)e;
+    for (int c = 0; c < 3; ++c) out[5 * k + 2 + c] = 0.5 * (X[(size_t)c * N + ga] + X[(size_t)c * N + gb]);
+  }
+}
+
+hipError_t launch_closest_pairs(int ncand, int N, int M, const int* cand, const double* X, double* out,
+                                hipStream_t st) {
+  if (ncand < 1) return hipSuccess;
+  k_closest_pair<<<ncand, 256, 0, st>>>(N, M, cand, X, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_bound_radius(int ns, int M, const double* r, double* rb, hipStream_t st) {
+  k_bound_radius<<<ns, 256, 0, st>>>(M, r, rb);
+  return hipGetLastError();
+}
+
 }  // namespace rbm

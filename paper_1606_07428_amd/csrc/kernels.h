@@ -172,4 +172,11 @@ hipError_t launch_near_corr(int kind, int n, int M, int Mu, int kmax, int nneed,
                             const int* nbr, const int* cnt, void* srcf, double* slots, double* res,
                             hipStream_t st);
 
+// contact search: closest node pair of each candidate body pair (cand [k][2]): out [k][5] =
+// (distance^2, node-pair index ia*M + ib, midpoint x*)
+hipError_t launch_closest_pairs(int ncand, int N, int M, const int* cand, const double* X, double* out,
+                                hipStream_t st);
+// rb[s] = max_a |r_a| over the M points r [ns][3][M]
+hipError_t launch_bound_radius(int ns, int M, const double* r, double* rb, hipStream_t st);
+
 }  // namespace rbm

@@ -36,6 +36,8 @@ static rbm_status fail(rbm_status s, const std::string& msg) {
 constexpr int kMaxPup = 48;
 constexpr int kNearMax = 64;
 constexpr int kNearWork = 8192;
+// contact search: at most kContactCand candidate pairs per body (bounding spheres within delta)
+constexpr int kContactCand = 32;
 
 struct rbm_ctx {
   rbm_options opt;
@@ -86,6 +88,10 @@ struct rbm_ctx {
   int *nbr = nullptr, *ncnt = nullptr, *nitem = nullptr, *nfirst = nullptr, *nneed = nullptr;
   int n_items = 0, n_need = 0, item_len = 0;
   std::vector<int> ncnt_h, nbr_h, items_h, first_h, need_h;
+  // contact search: coarse bounding radius per shape (device and host), candidate pairs
+  double *rbc = nullptr, *cres = nullptr;
+  int* ccand = nullptr;
+  std::vector<double> rbc_h;
   double* pinned = nullptr;
   // learned warm start
   struct Learned {
@@ -123,6 +129,7 @@ extern "C" void rbm_default_options(rbm_options* o) {
   o->stream = nullptr;
   o->p_up = 0;
   o->near_factor = 5.0;
+  o->contact_delta = 0.0;
 }
 
 extern "C" const char* rbm_last_error(void) { return g_err.c_str(); }
@@ -142,6 +149,8 @@ extern "C" rbm_status rbm_create(const rbm_options* opt, rbm_ctx** out) {
     return fail(RBM_E_INVAL, "p_up must be 0 or in [p+1, 48]");
   if (!(opt->near_factor >= 0.0) || !std::isfinite(opt->near_factor))
     return fail(RBM_E_INVAL, "near_factor must be >= 0");
+  if (!(opt->contact_delta >= 0.0) || !std::isfinite(opt->contact_delta))
+    return fail(RBM_E_INVAL, "contact_delta must be >= 0");
   rbm_ctx* c = new rbm_ctx();
   c->opt = *opt;
   if (!(c->opt.inner_tol > 0.0)) c->opt.inner_tol = 1e-4;
@@ -273,6 +282,7 @@ static size_t layout(rbm_ctx* c, int nmax, bool assign) {
   take(c->rcbuf, c->shape_data.size() + 1);
   take(c->gx, ns * 3 * M); take(c->gn, ns * 3 * M); take(c->gr, ns * 3 * M); take(c->gw, ns * M);
   take(c->shp, ns * 32);
+  take(c->rbc, ns);
   take(c->A0, ns * M3 * M3); take(c->P0, ns * M3 * M3); take(c->V0, ns * 6 * M3);
   take(c->piv, ns * M3);
   if (c->opt.precision == RBM_MIXED_FP32) take(c->P0f, ns * M3 * M3); else if (assign) c->P0f = nullptr;
@@ -301,6 +311,7 @@ static size_t layout(rbm_ctx* c, int nmax, bool assign) {
   take(srcd, 8 * N);
   if (assign) c->src = srcd;
   take(c->part, (size_t)(far_split((int)N) + (c->pu ? 1 : 0)) * N3);
+  take(c->ccand, 2 * (size_t)kContactCand * nm); take(c->cres, 5 * (size_t)kContactCand * nm);
   if (c->pu) {
     const size_t Mu = c->Mu;
     take(c->glu_t, c->pu + 1); take(c->glu_w, c->pu + 1);
@@ -389,6 +400,9 @@ extern "C" rbm_status rbm_setup(rbm_ctx* c) {
   HIPCHECK(launch_gauss_jordan(c->ns, M3, c->P0, c->piv, st));
   if (c->P0f) HIPCHECK(launch_cast_f32((size_t)c->ns * M3 * M3, c->P0, c->P0f, st));
   if (c->P0h) HIPCHECK(launch_cast_bf16((size_t)c->ns * M3 * M3, c->P0, c->P0h, st));
+  HIPCHECK(launch_bound_radius(c->ns, M, c->gr, c->rbc, st));
+  c->rbc_h.resize(c->ns);
+  HIPCHECK(hipMemcpyAsync(c->rbc_h.data(), c->rbc, c->ns * sizeof(double), hipMemcpyDeviceToHost, st));
   if (c->pu) {
     HIPCHECK(launch_gauss_legendre(c->pu + 1, c->glu_t, c->glu_w, st));
     HIPCHECK(launch_fine_geometry(c->ns, p, c->pu, c->coef, c->glu_t, c->glu_w, c->shp, c->fr, c->fw,
@@ -897,6 +911,170 @@ extern "C" rbm_status rbm_apply_dev(rbm_ctx* c, const double* d_mu, double* d_y)
   return RBM_OK;
 }
 
+extern "C" rbm_status rbm_find_contacts(rbm_ctx* c, double delta, int max_contacts, int* n_found,
+                                        int* pairs, double* points) {
+  if (!c || !n_found) return fail(RBM_E_INVAL, "null argument");
+  if (max_contacts < 0 || (max_contacts > 0 && (!pairs || !points)))
+    return fail(RBM_E_INVAL, "max_contacts >= 0 with pairs and points for max_contacts > 0");
+  if (!(delta > 0.0) || !std::isfinite(delta)) return fail(RBM_E_INVAL, "delta must be > 0");
+  if (!c->ws) return fail(RBM_E_NOMEM, "bind a workspace first");
+  if (!c->setup_done) return fail(RBM_E_STATE, "call rbm_setup first");
+  if (c->n < 1) return fail(RBM_E_STATE, "set bodies first");
+  rbm_status s;
+  if ((s = upload_bodies(c)) != RBM_OK) return s;
+  const int n = c->n, M = c->M;
+  // candidates: bounding spheres (largest centroid-to-node distance) within delta
+  std::vector<int> cand;
+  for (int a = 0; a < n; ++a)
+    for (int b = a + 1; b < n; ++b) {
+      const double* ca = &c->cen_h[3 * a];
+      const double* cb = &c->cen_h[3 * b];
+      const double dx = ca[0] - cb[0], dy = ca[1] - cb[1], dz = ca[2] - cb[2];
+      if (std::sqrt(dx * dx + dy * dy + dz * dz) < c->rbc_h[c->sid_h[a]] + c->rbc_h[c->sid_h[b]] + delta) {
+        cand.push_back(a);
+        cand.push_back(b);
+      }
+    }
+  const int ncand = (int)cand.size() / 2;
+  if ((size_t)ncand > (size_t)kContactCand * c->nmax)
+    return fail(RBM_E_INVAL, "too many contact candidates: lower delta");
+  std::vector<double> res(5 * (size_t)ncand);
+  if (ncand) {
+    HIPCHECK(hipMemcpyAsync(c->ccand, cand.data(), cand.size() * sizeof(int), hipMemcpyHostToDevice, c->st));
+    HIPCHECK(launch_closest_pairs(ncand, n * M, M, c->ccand, c->X, c->cres, c->st));
+    HIPCHECK(hipMemcpyAsync(res.data(), c->cres, res.size() * sizeof(double), hipMemcpyDeviceToHost, c->st));
+  }
+  HIPCHECK(hipStreamSynchronize(c->st));
+  int found = 0;
+  for (int k = 0; k < ncand; ++k) {
+    if (!(std::sqrt(res[5 * k]) < delta)) continue;
+    if (found < max_contacts) {
+      pairs[2 * found] = cand[2 * k];
+      pairs[2 * found + 1] = cand[2 * k + 1];
+      for (int e = 0; e < 3; ++e) points[3 * found + e] = res[5 * k + 2 + e];
+    }
+    ++found;
+  }
+  *n_found = found;
+  return RBM_OK;
+}
+
+// LU with partial pivoting of the small dense system A x = b (A row-major n x n,
+// overwritten); false if a pivot vanishes.
+static bool small_solve(int n, std::vector<double>& A, std::vector<double>& b) {
+  for (int k = 0; k < n; ++k) {
+    int piv = k;
+    for (int i = k + 1; i < n; ++i)
+      if (std::fabs(A[(size_t)i * n + k]) > std::fabs(A[(size_t)piv * n + k])) piv = i;
+    if (!(std::fabs(A[(size_t)piv * n + k]) > 0.0)) return false;
+    if (piv != k) {
+      for (int j = 0; j < n; ++j) std::swap(A[(size_t)k * n + j], A[(size_t)piv * n + j]);
+      std::swap(b[k], b[piv]);
+    }
+    for (int i = k + 1; i < n; ++i) {
+      const double f = A[(size_t)i * n + k] / A[(size_t)k * n + k];
+      for (int j = k; j < n; ++j) A[(size_t)i * n + j] -= f * A[(size_t)k * n + j];
+      b[i] -= f * b[k];
+    }
+  }
+  for (int k = n - 1; k >= 0; --k) {
+    double v = b[k];
+    for (int j = k + 1; j < n; ++j) v -= A[(size_t)k * n + j] * b[j];
+    b[k] = v / A[(size_t)k * n + k];
+  }
+  return true;
+}
+
+extern "C" rbm_status rbm_solve_contacts(rbm_ctx* c, const double* FT, int n_contacts,
+                                         const int* pairs, const double* points, double* VW,
+                                         double* Fc, rbm_solve_info* info) {
+  if (!c || !FT || !VW) return fail(RBM_E_INVAL, "null argument");
+  if (n_contacts < 0 || (n_contacts > 0 && (!pairs || !points || !Fc)))
+    return fail(RBM_E_INVAL, "n_contacts >= 0 with pairs, points and Fc for n_contacts > 0");
+  const int n = c->n;
+  for (int k = 0; k < n_contacts; ++k) {
+    const int a = pairs[2 * k], b = pairs[2 * k + 1];
+    if (a < 0 || b < 0 || a >= n || b >= n || a == b) return fail(RBM_E_INVAL, "bad contact pair");
+    if (!all_finite(points + 3 * k, 3)) return fail(RBM_E_INVAL, "non-finite contact point");
+  }
+  rbm_solve_info i0, ik;
+  std::vector<double> V0(6 * (size_t)n);
+  rbm_status s = rbm_solve(c, FT, V0.data(), &i0);
+  if (s != RBM_OK) return s;
+  const int m = 3 * n_contacts;
+  std::vector<double> Vc((size_t)m * 6 * n), load(6 * (size_t)n);
+  // column (k, e) of M C: the solve for a unit force along e at x_k on body a, its
+  // opposite on body b, torques about the centroids
+  for (int k = 0; k < n_contacts; ++k) {
+    const int a = pairs[2 * k], b = pairs[2 * k + 1];
+    const double* xs = points + 3 * k;
+    double ra[3], rb[3];
+    for (int d = 0; d < 3; ++d) {
+      ra[d] = xs[d] - c->cen_h[3 * a + d];
+      rb[d] = xs[d] - c->cen_h[3 * b + d];
+    }
+    for (int e = 0; e < 3; ++e) {
+      std::fill(load.begin(), load.end(), 0.0);
+      double f[3] = {0, 0, 0};
+      f[e] = 1.0;
+      const double ta[3] = {ra[1] * f[2] - ra[2] * f[1], ra[2] * f[0] - ra[0] * f[2], ra[0] * f[1] - ra[1] * f[0]};
+      const double tb[3] = {rb[1] * f[2] - rb[2] * f[1], rb[2] * f[0] - rb[0] * f[2], rb[0] * f[1] - rb[1] * f[0]};
+      for (int d = 0; d < 3; ++d) {
+        load[6 * a + d] += f[d];
+        load[6 * a + 3 + d] += ta[d];
+        load[6 * b + d] -= f[d];
+        load[6 * b + 3 + d] -= tb[d];
+      }
+      s = rbm_solve(c, load.data(), &Vc[(size_t)(3 * k + e) * 6 * n], &ik);
+      if (s != RBM_OK) return s;
+      i0.iters += ik.iters;
+      i0.matvecs += ik.matvecs;
+      i0.ms_total += ik.ms_total;
+      i0.ms_far += ik.ms_far;
+      i0.ms_self += ik.ms_self;
+      i0.far_pairs += ik.far_pairs;
+    }
+  }
+  // velocity differences at the contact points: D V
+  auto dvel = [&](const double* V, int k, double* out) {
+    const int a = pairs[2 * k], b = pairs[2 * k + 1];
+    const double* xs = points + 3 * k;
+    double ra[3], rb[3];
+    for (int d = 0; d < 3; ++d) {
+      ra[d] = xs[d] - c->cen_h[3 * a + d];
+      rb[d] = xs[d] - c->cen_h[3 * b + d];
+    }
+    const double* va = V + 6 * a;
+    const double* vb = V + 6 * b;
+    const double ua[3] = {va[0] + va[4] * ra[2] - va[5] * ra[1], va[1] + va[5] * ra[0] - va[3] * ra[2],
+                          va[2] + va[3] * ra[1] - va[4] * ra[0]};
+    const double ub[3] = {vb[0] + vb[4] * rb[2] - vb[5] * rb[1], vb[1] + vb[5] * rb[0] - vb[3] * rb[2],
+                          vb[2] + vb[3] * rb[1] - vb[4] * rb[0]};
+    for (int d = 0; d < 3; ++d) out[d] = ua[d] - ub[d];
+  };
+  std::vector<double> A((size_t)m * m), rhs(m);
+  for (int col = 0; col < m; ++col)
+    for (int k = 0; k < n_contacts; ++k) {
+      double d[3];
+      dvel(&Vc[(size_t)col * 6 * n], k, d);
+      for (int e = 0; e < 3; ++e) A[(size_t)(3 * k + e) * m + col] = d[e];
+    }
+  for (int k = 0; k < n_contacts; ++k) {
+    double d[3];
+    dvel(V0.data(), k, d);
+    for (int e = 0; e < 3; ++e) rhs[3 * k + e] = -d[e];
+  }
+  if (m > 0 && !small_solve(m, A, rhs)) return fail(RBM_E_INVAL, "singular contact system");
+  for (size_t i = 0; i < V0.size(); ++i) {
+    double v = V0[i];
+    for (int col = 0; col < m; ++col) v += rhs[col] * Vc[(size_t)col * 6 * n + i];
+    VW[i] = v;
+  }
+  for (int col = 0; col < m; ++col) Fc[col] = rhs[col];
+  if (info) *info = i0;
+  return RBM_OK;
+}
+
 extern "C" const void* rbm_debug_ptr(rbm_ctx* c, const char* name) {
   if (!c || !name || !c->ws) return nullptr;
   const std::string s(name);
@@ -1008,10 +1186,36 @@ extern "C" rbm_status rbm_step_rk4(rbm_ctx* c, double dt, const double* d_FT,
   HIPCHECK(hipMemcpyAsync(c->quat0, c->quat, 4 * n * sizeof(double), hipMemcpyDeviceToDevice, st));
   const double a[4] = {0.0, 0.5, 0.5, 1.0}, wgt[4] = {1.0, 2.0, 2.0, 1.0};
   rbm_status worst = RBM_OK;
+  std::vector<double> FT_h;
+  if (c->opt.contact_delta > 0.0) {
+    FT_h.resize(6 * (size_t)n);
+    HIPCHECK(hipMemcpyAsync(FT_h.data(), d_FT, FT_h.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+    HIPCHECK(hipStreamSynchronize(st));
+  }
   for (int k = 0; k < 4; ++k) {
     HIPCHECK(launch_rk_stage(n, c->cen0, c->quat0, c->kst, a[k], dt, c->cen, c->quat, st));
     if ((s = refresh_nodes(c)) != RBM_OK) return s;
     c->bodies_dirty = false;
+    if (c->opt.contact_delta > 0.0) {
+      // stage poses to the host for the contact search, then the contact-corrected solve
+      HIPCHECK(hipMemcpyAsync(c->cen_h.data(), c->cen, 3 * n * sizeof(double), hipMemcpyDeviceToHost, st));
+      HIPCHECK(hipMemcpyAsync(c->quat_h.data(), c->quat, 4 * n * sizeof(double), hipMemcpyDeviceToHost, st));
+      HIPCHECK(hipStreamSynchronize(st));
+      int nf = 0;
+      if ((s = rbm_find_contacts(c, c->opt.contact_delta, 0, &nf, nullptr, nullptr)) != RBM_OK) return s;
+      if (nf > 0) {
+        std::vector<int> cp(2 * (size_t)nf);
+        std::vector<double> cx(3 * (size_t)nf), fc(3 * (size_t)nf), vw(6 * (size_t)n);
+        if ((s = rbm_find_contacts(c, c->opt.contact_delta, nf, &nf, cp.data(), cx.data())) != RBM_OK) return s;
+        s = rbm_solve_contacts(c, FT_h.data(), nf, cp.data(), cx.data(), vw.data(), fc.data(),
+                               stage_info ? stage_info + k : nullptr);
+        if (s != RBM_OK) return s;
+        HIPCHECK(hipMemcpyAsync(c->VW, vw.data(), vw.size() * sizeof(double), hipMemcpyHostToDevice, st));
+        HIPCHECK(launch_rk_deriv(n, c->VW, c->quat, c->kst, c->kacc, wgt[k], k == 0, st));
+        HIPCHECK(hipStreamSynchronize(st));
+        continue;
+      }
+    }
     s = solve_impl(c, d_FT, c->VW, stage_info ? stage_info + k : nullptr);
     if (s == RBM_E_NOCONV) worst = s;
     else if (s != RBM_OK) return s;

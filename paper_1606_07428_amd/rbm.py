@@ -26,7 +26,7 @@ EXPORTED = [
     "rbm_learned_capture", "rbm_learned_set_capture", "rbm_learned_train", "rbm_learned_info",
     "rbm_learned_get_params", "rbm_learned_set_params", "rbm_learned_forward_dev",
     "rbm_learned_loss_grad_dev", "rbm_learned_features_dev", "rbm_learned_guess_dev", "rbm_set_guess",
-    "rbm_apply_dev",
+    "rbm_apply_dev", "rbm_find_contacts", "rbm_solve_contacts",
 ]
 
 
@@ -34,7 +34,8 @@ class Options(ctypes.Structure):
     _fields_ = [("p", ctypes.c_int), ("p_sing", ctypes.c_int), ("eta", ctypes.c_double),
                 ("tol", ctypes.c_double), ("max_iter", ctypes.c_int), ("max_restart", ctypes.c_int),
                 ("precision", ctypes.c_int), ("guess", ctypes.c_int), ("inner_tol", ctypes.c_double),
-                ("stream", ctypes.c_void_p), ("p_up", ctypes.c_int), ("near_factor", ctypes.c_double)]
+                ("stream", ctypes.c_void_p), ("p_up", ctypes.c_int), ("near_factor", ctypes.c_double),
+                ("contact_delta", ctypes.c_double)]
 
 
 class SolveInfo(ctypes.Structure):
@@ -104,6 +105,8 @@ def load():
         "rbm_learned_guess_dev": (I, [P, P, P]),
         "rbm_set_guess": (I, [P, I]),
         "rbm_apply_dev": (I, [P, P, P]),
+        "rbm_find_contacts": (I, [P, D, I, P, P, P]),
+        "rbm_solve_contacts": (I, [P, P, I, P, P, P, P, P]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -141,7 +144,8 @@ class Solver:
 
     def __init__(self, p, shapes, shape_id, centres, quats, eta=1.0, p_sing=0, tol=1e-12,
                  max_iter=100, max_restart=4, precision=FP64, guess=GUESS_BLOCKDIAG,
-                 inner_tol=1e-4, n_max=None, stream=None, device="cuda", p_up=0, near_factor=5.0):
+                 inner_tol=1e-4, n_max=None, stream=None, device="cuda", p_up=0, near_factor=5.0,
+                 contact_delta=0.0):
         import torch
         lib = load()
         self.torch = torch
@@ -151,7 +155,7 @@ class Solver:
         opt.p, opt.p_sing, opt.eta, opt.tol = p, p_sing, eta, tol
         opt.max_iter, opt.max_restart, opt.precision, opt.guess = max_iter, max_restart, precision, guess
         opt.inner_tol = inner_tol
-        opt.p_up, opt.near_factor = p_up, near_factor
+        opt.p_up, opt.near_factor, opt.contact_delta = p_up, near_factor, contact_delta
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
         opt.stream = ctypes.c_void_p(self.stream.cuda_stream)
         self.opt = opt
@@ -229,6 +233,28 @@ class Solver:
         _check(load().rbm_apply_dev(self.ctx, ctypes.c_void_p(mu_dev.data_ptr()),
                                     ctypes.c_void_p(y.data_ptr())))
         return y
+
+    def find_contacts(self, delta, max_contacts=4096):
+        """Body pairs whose closest nodes are within delta: (pairs (k, 2), points (k, 3))."""
+        pairs = np.zeros((max_contacts, 2), dtype=np.int32)
+        pts = np.zeros((max_contacts, 3))
+        nf = ctypes.c_int()
+        _check(load().rbm_find_contacts(self.ctx, float(delta), max_contacts, ctypes.byref(nf),
+                                        _ptr(pairs), _ptr(pts)))
+        k = min(nf.value, max_contacts)
+        return pairs[:k].copy(), pts[:k].copy()
+
+    def solve_contacts(self, FT, pairs, points):
+        """Velocities with contact forces: (VW (n, 6), Fc (k, 3), info)."""
+        FT = _f64(FT, (self.n, 6))
+        pairs = np.ascontiguousarray(pairs, dtype=np.int32).reshape(-1, 2)
+        points = _f64(points, (-1, 3))
+        VW = np.zeros((self.n, 6))
+        Fc = np.zeros((max(len(pairs), 1), 3))
+        info = SolveInfo()
+        _check(load().rbm_solve_contacts(self.ctx, _ptr(FT), len(pairs), _ptr(pairs), _ptr(points),
+                                         _ptr(VW), _ptr(Fc), ctypes.byref(info)))
+        return VW, Fc[:len(pairs)], info.as_dict()
 
     def step_rk4(self, dt, FT_dev):
         """One RK4 step with loads FT_dev (float64 (n, 6) CUDA tensor); returns the
