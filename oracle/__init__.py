@@ -19,6 +19,7 @@ nearfield  upsampled smooth rule for near body pairs (§3)
 system     incident density, augmented second-kind system, solves, velocities (§2.2-§3.3)
 timestep   quaternion RK4 evolution of centres and orientations (§3.3)
 contact    contact forces between touching bodies (§3.3 contact force algorithm)
+magnetic   magnetostatic potential, field and Maxwell traction of permeable bodies (§4)
 mlp        FP64 reference of the warm-start network (forward, backward, Adam)
 
 Every floating-point quantity is computed in float64.

@@ -255,6 +255,16 @@ def solve_dense(prob, FT):
     return rho, mu, prob.velocities(rho, mu)
 
 
+def solve_dense_density(prob, rho):
+    """As ``solve_dense`` for a given incident density rho (N, 3) (e.g. a Maxwell traction,
+    §4) in place of F/|Gamma| + tau^{-1} T x (x - x^c)."""
+    rho = np.asarray(rho, dtype=np.float64).reshape(prob.N, 3)
+    b = prob.rhs(rho).reshape(-1)
+    mu = np.zeros_like(rho) if np.linalg.norm(b) == 0.0 else \
+        np.linalg.solve(prob.dense_matrix(), b).reshape(prob.N, 3)
+    return mu, prob.velocities(rho, mu)
+
+
 def gmres(apply, b, tol, maxit=500, x0=None):
     """Unrestarted GMRES with modified Gram-Schmidt Arnoldi and Givens rotations;
     stops when the true residual ||b - A x|| <= tol ||b||.  Returns x, iterations."""
