@@ -91,6 +91,8 @@ typedef struct {
   double contact_delta; /* rbm_step_rk4 only: > 0 switches on the contact forces of §3.3 at every
                            stage (bodies whose closest nodes are within contact_delta, see
                            rbm_find_contacts / rbm_solve_contacts); 0 = off */
+  int magnetic;         /* 1: set up the Laplace operators of the magnetostatic problem (§4) for
+                           rbm_magnetic_traction_dev (two M x M operators per shape); 0 = off */
 } rbm_options;
 
 typedef struct {
@@ -259,6 +261,22 @@ rbm_status rbm_find_contacts(rbm_ctx* ctx, double delta, int max_contacts, int* 
  * solves.  RBM_E_INVAL for a singular contact system. */
 rbm_status rbm_solve_contacts(rbm_ctx* ctx, const double* FT, int n_contacts, const int* pairs,
                               const double* points, double* VW, double* Fc, rbm_solve_info* info);
+
+/* Magnetostatics of permeable bodies (§4, magnetorheological flows), float64, current poses:
+ * bodies of permeability mu_ratio * mu0 in a fluid of permeability mu0 and the uniform field
+ * H0 (host [3]).  Solves (1/2 I + eta K^L) q = eta H0 . n, eta = (mu_ratio - 1)/(mu_ratio + 1),
+ * by unpreconditioned GMRES to ||residual|| <= tol ||rhs|| (iterations to *iters, may be NULL),
+ * with phi = -H0 . x + S^L[q]; writes the Maxwell traction of the fluid side
+ * mu0 [(H . n) H - |H|^2 n / 2], H = -grad phi (exterior limit), to d_rho ([3][N], device) and,
+ * if d_FT is not NULL, the net force and torque (about the centroid) per body ([n][6],
+ * device).  Needs options.magnetic = 1.  RBM_E_NOCONV if GMRES stops short of tol. */
+rbm_status rbm_magnetic_traction_dev(rbm_ctx* ctx, const double* H0, double mu_ratio, double mu0,
+                                     double tol, double* d_rho, double* d_FT, int* iters);
+
+/* Mobility solve with a given incident density rho ([3][N], device; e.g. the Maxwell
+ * traction above) in place of F/|Gamma| + tau^{-1} T x (x - x^c) (§2.2, §4); velocities
+ * to d_VW ([n][6], device).  The learned guess is not used here (block-diagonal instead). */
+rbm_status rbm_solve_density_dev(rbm_ctx* ctx, const double* d_rho, double* d_VW, rbm_solve_info* info);
 
 /* Device pointers of internal arrays for inspection (valid until the workspace is
  * rebound).  name: "X","N","W" ([3][N]/[N] lab nodes, normals, weights), "mu",

@@ -21,6 +21,13 @@
 
 namespace rbm {
 
+// Constant factor of each kernel's sum: traction -3/(4pi), Stokeslet 1/(8pi) (the 1/eta
+// is applied by the caller), Laplace normal derivative -1/(4pi), Laplace single layer 1/(4pi).
+__host__ __device__ constexpr double kind_scale(int kind) {
+  return kind == 0 ? -3.0 / (4.0 * RBM_PI)
+                   : kind == 1 ? 1.0 / (8.0 * RBM_PI) : kind == 2 ? -1.0 / (4.0 * RBM_PI) : 1.0 / (4.0 * RBM_PI);
+}
+
 template <typename T, int KIND, int TPL>
 __global__ __launch_bounds__(256) void k_far(int N, int M, const T* __restrict__ tx,
                                              const T* __restrict__ tn,
@@ -37,7 +44,7 @@ __global__ __launch_bounds__(256) void k_far(int N, int M, const T* __restrict__
     xa[u] = tx[a];
     ya[u] = tx[N + a];
     za[u] = tx[2 * N + a];
-    if (KIND == 0) {
+    if (KIND == 0 || KIND == 2) {
       nx[u] = tn[a];
       ny[u] = tn[N + a];
       nz[u] = tn[2 * N + a];
@@ -112,7 +119,7 @@ __global__ __launch_bounds__(256) void k_far(int N, int M, const T* __restrict__
   }
   // fast segment after the block's bodies
   fast(max(b0, bhi), b1);
-  const double scale = KIND == 0 ? -3.0 / (4.0 * RBM_PI) : 1.0 / (8.0 * RBM_PI);
+  const double scale = kind_scale(KIND);
 #pragma unroll
   for (int u = 0; u < TPL; ++u) {
     const int a = base + u * 256 + (int)threadIdx.x;
@@ -142,7 +149,7 @@ __global__ __launch_bounds__(256) void k_far_lds(int N, int M, const T* __restri
   const int a = min(base + (int)threadIdx.x, N - 1);
   const T xa = tx[a], ya = tx[N + a], za = tx[2 * N + a];
   T nx = 0, ny = 0, nz = 0;
-  if (KIND == 0) {
+  if (KIND == 0 || KIND == 2) {
     nx = tn[a];
     ny = tn[N + a];
     nz = tn[2 * N + a];
@@ -182,7 +189,7 @@ __global__ __launch_bounds__(256) void k_far_lds(int N, int M, const T* __restri
       }
     }
   }
-  const double scale = KIND == 0 ? -3.0 / (4.0 * RBM_PI) : 1.0 / (8.0 * RBM_PI);
+  const double scale = kind_scale(KIND);
   if (base + (int)threadIdx.x < N) {
     double* o = part + (size_t)split * 3 * N;
     o[a] = scale * (double)ax;
@@ -201,6 +208,17 @@ hipError_t launch_far(int kind, int N, int M, const T* tx, const T* nrm, const v
   dim3 grid((N + 256 * kTPL - 1) / (256 * kTPL), nsplit);
   const Src8<T>* s = reinterpret_cast<const Src8<T>*>(src);
   constexpr int TS = sizeof(T) == 8 ? 512 : 256;
+  if (kind >= 2) {
+    // the scalar Laplace sums of the magnetostatic problem (float64 only)
+    if constexpr (sizeof(T) == 8) {
+      if (kind == 2)
+        k_far<T, 2, kTPL><<<grid, 256, 0, st>>>(N, M, tx, nrm, s, part, chunk);
+      else
+        k_far<T, 3, kTPL><<<grid, 256, 0, st>>>(N, M, tx, nrm, s, part, chunk);
+      return hipGetLastError();
+    }
+    return hipErrorInvalidValue;
+  }
   if (N <= kLdsMaxN) {
     if (kind == 0)
       k_far_lds<T, 0, TS><<<grid, 256, 0, st>>>(N, M, tx, nrm, s, part, chunk);

@@ -179,4 +179,31 @@ hipError_t launch_closest_pairs(int ncand, int N, int M, const int* cand, const 
 // rb[s] = max_a |r_a| over the M points r [ns][3][M]
 hipError_t launch_bound_radius(int ns, int M, const double* r, double* rb, hipStream_t st);
 
+// ---- magnetostatics (k_magnetic.hip) -------------------------------------------------
+// Laplace self operators S^L, K^L per shape, column-major [ns][M][M] (singular rule)
+hipError_t launch_singular_laplace(int ns, int p, int ps, const double* coef, const double* gx,
+                                   const double* gn, const double* node_th, const double* node_ph,
+                                   const double* rnodes, const double* rW, const double* Fttab,
+                                   double* SL, double* KL, hipStream_t st);
+// spectral derivative matrices Dt, Dp (column-major M x M) and shape tangents [ns][6][M]
+hipError_t launch_magnetic_tables(int p, int ns, const double* coef, const double* Yttab,
+                                  const double* Ypstab, const double* Ftab, double* Dt, double* Dp,
+                                  double* tang, hipStream_t st);
+// y = A_{s(i)} x per body, scalar node vectors
+hipError_t launch_scalar_self(int n, int M, const int* sid, const double* A, const double* x, double* y,
+                              hipStream_t st);
+hipError_t launch_pack_scalar(int N, const double* X, const double* W, const double* q, void* src,
+                              hipStream_t st);
+// out = cv v + cs self + cp sum of the split slots' first component (v, self may be NULL)
+hipError_t launch_scalar_combine(int N, int nsplit, const double* part, double cp, const double* self,
+                                 double cs, const double* v, double cv, double* out, hipStream_t st);
+// out = (accumulate ? out : 0) + scale (h . V_g), V [3][N]
+hipError_t launch_hdot(int N, const double* V, double h0, double h1, double h2, double scale,
+                       int accumulate, double* out, hipStream_t st);
+// exterior field and Maxwell traction rho [3][N] from phi and the exterior normal derivative dn
+hipError_t launch_magnetic_traction(int n, int M, const int* sid, const double* Rm, const double* Nn,
+                                    const double* tang, const double* Dt, const double* Dp,
+                                    const double* phi, const double* dn, double mu0, double* rho,
+                                    hipStream_t st);
+
 }  // namespace rbm

@@ -1,5 +1,6 @@
-// Pair arithmetic of the smooth-rule sums between bodies (§2.1, §3): the packed
-// source record and the traction / Stokeslet contribution of one source to one target,
+// Pair arithmetic of the smooth-rule sums between bodies (§2.1, §3, §4): the packed
+// source record and the contribution of one source to one target for the traction (kind
+// 0), Stokeslet (1), Laplace normal-derivative (2) and Laplace single-layer (3) kernels,
 // shared by the all-pairs sum (k_far.hip) and the near-singular correction (k_near.hip).
 #pragma once
 #include "common.h"
@@ -50,12 +51,19 @@ struct Pair {
       ax += f * dx;
       ay += f * dy;
       az += f * dz;
-    } else {
+    } else if (KIND == 1) {
       const T ri = rsqrt_t(r2);
       const T f = dq * (ri * ri * ri);
       ax += s.v[3] * ri + f * dx;
       ay += s.v[4] * ri + f * dy;
       az += s.v[5] * ri + f * dz;
+    } else if (KIND == 2) {
+      // Laplace, normal derivative at the target of the single layer: (d.N_a) q_b / |d|^3
+      const T ri = rsqrt_t(r2);
+      ax += (dx * nx + dy * ny + dz * nz) * s.v[3] * (ri * ri * ri);
+    } else {
+      // Laplace single layer: q_b / |d|
+      ax += s.v[3] * rsqrt_t(r2);
     }
   }
 };

@@ -88,6 +88,10 @@ struct rbm_ctx {
   int *nbr = nullptr, *ncnt = nullptr, *nitem = nullptr, *nfirst = nullptr, *nneed = nullptr;
   int n_items = 0, n_need = 0, item_len = 0;
   std::vector<int> ncnt_h, nbr_h, items_h, first_h, need_h;
+  // magnetostatics (option magnetic): Laplace self operators, derivative matrices, tangents,
+  // scalar work vectors
+  double *SL0 = nullptr, *KL0 = nullptr, *Dth = nullptr, *Dph = nullptr, *tang = nullptr,
+         *mq = nullptr, *mphi = nullptr, *mdn = nullptr, *mtmp = nullptr, *mb = nullptr;
   // contact search: coarse bounding radius per shape (device and host), candidate pairs
   double *rbc = nullptr, *cres = nullptr;
   int* ccand = nullptr;
@@ -130,6 +134,7 @@ extern "C" void rbm_default_options(rbm_options* o) {
   o->p_up = 0;
   o->near_factor = 5.0;
   o->contact_delta = 0.0;
+  o->magnetic = 0;
 }
 
 extern "C" const char* rbm_last_error(void) { return g_err.c_str(); }
@@ -312,6 +317,11 @@ static size_t layout(rbm_ctx* c, int nmax, bool assign) {
   if (assign) c->src = srcd;
   take(c->part, (size_t)(far_split((int)N) + (c->pu ? 1 : 0)) * N3);
   take(c->ccand, 2 * (size_t)kContactCand * nm); take(c->cres, 5 * (size_t)kContactCand * nm);
+  if (c->opt.magnetic) {
+    take(c->SL0, ns * M * M); take(c->KL0, ns * M * M);
+    take(c->Dth, (size_t)M * M); take(c->Dph, (size_t)M * M); take(c->tang, ns * 6 * M);
+    take(c->mq, N); take(c->mphi, N); take(c->mdn, N); take(c->mtmp, N); take(c->mb, N);
+  }
   if (c->pu) {
     const size_t Mu = c->Mu;
     take(c->glu_t, c->pu + 1); take(c->glu_w, c->pu + 1);
@@ -400,6 +410,12 @@ extern "C" rbm_status rbm_setup(rbm_ctx* c) {
   HIPCHECK(launch_gauss_jordan(c->ns, M3, c->P0, c->piv, st));
   if (c->P0f) HIPCHECK(launch_cast_f32((size_t)c->ns * M3 * M3, c->P0, c->P0f, st));
   if (c->P0h) HIPCHECK(launch_cast_bf16((size_t)c->ns * M3 * M3, c->P0, c->P0h, st));
+  if (c->opt.magnetic) {
+    HIPCHECK(launch_singular_laplace(c->ns, p, c->ps, c->coef, c->gx, c->gn, c->nth, c->nph, c->rnodes,
+                                     c->rW, c->Fttab, c->SL0, c->KL0, st));
+    HIPCHECK(launch_magnetic_tables(p, c->ns, c->coef, c->Yttab, c->Ypstab, c->Ftab, c->Dth, c->Dph,
+                                    c->tang, st));
+  }
   HIPCHECK(launch_bound_radius(c->ns, M, c->gr, c->rbc, st));
   c->rbc_h.resize(c->ns);
   HIPCHECK(hipMemcpyAsync(c->rbc_h.data(), c->rbc, c->ns * sizeof(double), hipMemcpyDeviceToHost, st));
@@ -627,8 +643,9 @@ static rbm_status dot_into(rbm_ctx* c, int kk, const double* Vb, size_t ldv, con
   return RBM_OK;
 }
 
-static rbm_status norm_into(rbm_ctx* c, const double* w, double* out) {
-  const size_t len = 3 * (size_t)c->n * c->M;
+// 2-norm of w[0, len) into out; len = 0 means a traction-sized vector (3 n M).
+static rbm_status norm_into(rbm_ctx* c, const double* w, double* out, size_t len = 0) {
+  if (len == 0) len = 3 * (size_t)c->n * c->M;
   HIPCHECK(launch_dots(1, len, w, len, w, c->partial, c->nblk, c->st));
   HIPCHECK(launch_dots_final_sqrt(c->nblk, c->partial, out, c->st));
   return RBM_OK;
@@ -688,11 +705,15 @@ static rbm_status learned_correction(rbm_ctx* c, const double* dFT);
 static rbm_status learned_capture(rbm_ctx* c, const double* dFT);
 
 // Incident density (§2.2) and right-hand side b = -(A_self rho - L rho + K_far rho).
-static rbm_status build_rhs(rbm_ctx* c, SolveState& S, const double* dFT, double* bnorm) {
+static rbm_status build_rhs(rbm_ctx* c, SolveState& S, const double* dFT, const double* d_rho,
+                            double* bnorm) {
   hipStream_t st = c->st;
   const int n = c->n, M = c->M, N = n * M;
   rbm_status s;
-  HIPCHECK(launch_rho(n, M, dFT, c->cen, c->X, c->tauinv, c->area_b, c->rho, st));
+  if (d_rho)
+    HIPCHECK(hipMemcpyAsync(c->rho, d_rho, 3 * (size_t)N * sizeof(double), hipMemcpyDeviceToDevice, st));
+  else
+    HIPCHECK(launch_rho(n, M, dFT, c->cen, c->X, c->tauinv, c->area_b, c->rho, st));
   if ((s = self_apply(c, S, 0, 0, c->rho, c->yb)) != RBM_OK) return s;
   if ((s = far_traction(c, S, c->rho, 0, 0)) != RBM_OK) return s;
   HIPCHECK(launch_combine(N, M, far_slots(c, N), c->part, -1.0, nullptr, 0.0, c->yb, c->Rm, -1.0, c->b, st));
@@ -705,7 +726,8 @@ static rbm_status build_rhs(rbm_ctx* c, SolveState& S, const double* dFT, double
   return RBM_OK;
 }
 
-static rbm_status solve_impl(rbm_ctx* c, const double* dFT, double* dVW, rbm_solve_info* info) {
+static rbm_status solve_impl(rbm_ctx* c, const double* dFT, double* dVW, rbm_solve_info* info,
+                             const double* d_rho = nullptr) {
   if (!c->ws) return fail(RBM_E_NOMEM, "bind a workspace first");
   if (!c->setup_done) return fail(RBM_E_STATE, "call rbm_setup first");
   if (c->n < 1) return fail(RBM_E_STATE, "set bodies first");
@@ -718,7 +740,7 @@ static rbm_status solve_impl(rbm_ctx* c, const double* dFT, double* dVW, rbm_sol
   c->ev_used = 0;
   Timer total(c);
   double bnorm;
-  if ((s = build_rhs(c, S, dFT, &bnorm)) != RBM_OK) return s;
+  if ((s = build_rhs(c, S, dFT, d_rho, &bnorm)) != RBM_OK) return s;
   const double abs_tol = c->opt.tol * bnorm;
   const int prec = c->opt.precision;
   // initial guess
@@ -732,7 +754,7 @@ static rbm_status solve_impl(rbm_ctx* c, const double* dFT, double* dVW, rbm_sol
     // block-diagonal (isolated-particle) guess mu_BD = P^{-1} b (§3.2 preconditioner)
     if ((s = self_apply(c, S, 1, prec, c->b, c->yb)) != RBM_OK) return s;
     HIPCHECK(launch_combine(N, M, 0, nullptr, 0.0, nullptr, 0.0, c->yb, c->Rm, 1.0, c->mu, st));
-    if (c->opt.guess == RBM_GUESS_LEARNED && c->L.bound && c->L.stats_ready) {
+    if (c->opt.guess == RBM_GUESS_LEARNED && c->L.bound && c->L.stats_ready && !d_rho) {
       HIPCHECK(hipMemcpyAsync(c->t2, c->mu, len * sizeof(double), hipMemcpyDeviceToDevice, st));
       if ((s = learned_correction(c, dFT)) != RBM_OK) return s;
       learned_active = true;
@@ -814,7 +836,7 @@ static rbm_status solve_impl(rbm_ctx* c, const double* dFT, double* dVW, rbm_sol
   total.stop();
   HIPCHECK(hipStreamSynchronize(st));
   c->have_solution = true;
-  if (c->L.bound && c->L.capture_on)
+  if (c->L.bound && c->L.capture_on && !d_rho)
     if ((s = learned_capture(c, dFT)) != RBM_OK) return s;
   if (info) {
     std::memset(info, 0, sizeof(*info));
@@ -1075,6 +1097,125 @@ extern "C" rbm_status rbm_solve_contacts(rbm_ctx* c, const double* FT, int n_con
   return RBM_OK;
 }
 
+extern "C" rbm_status rbm_solve_density_dev(rbm_ctx* c, const double* d_rho, double* d_VW,
+                                           rbm_solve_info* info) {
+  if (!c || !d_rho || !d_VW) return fail(RBM_E_INVAL, "null argument");
+  return solve_impl(c, nullptr, d_VW, info, d_rho);
+}
+
+// w = 1/2 v + eta (K^L_self v + K^L_far v) on scalar node vectors (float64).
+static rbm_status magnetic_apply(rbm_ctx* c, double eta, const double* v, double* w) {
+  const int n = c->n, M = c->M, N = n * M;
+  const int nsp = split_for(c, N);
+  HIPCHECK(launch_scalar_self(n, M, c->sid, c->KL0, v, c->mtmp, c->st));
+  HIPCHECK(launch_pack_scalar(N, c->X, c->W, v, c->src, c->st));
+  HIPCHECK(launch_far<double>(2, N, M, c->X, c->Nn, c->src, c->part, nsp, c->st));
+  HIPCHECK(launch_scalar_combine(N, nsp, c->part, eta, c->mtmp, eta, v, 0.5, w, c->st));
+  return RBM_OK;
+}
+
+// Unpreconditioned restarted GMRES (CGS2) for (1/2 I + eta K^L) x = b, x starting at 0;
+// the operator is second kind with |eta| < 1.
+static rbm_status magnetic_gmres(rbm_ctx* c, double eta, const double* b, double* x, double tol,
+                                 int* iters) {
+  const size_t len = (size_t)c->n * c->M;
+  const int m = c->opt.max_iter, ldh = m + 1;
+  rbm_status s;
+  double bn;
+  if ((s = norm_into(c, b, c->scal + 4, len)) != RBM_OK) return s;
+  if ((s = read_scalar(c, c->scal + 4, &bn)) != RBM_OK) return s;
+  HIPCHECK(hipMemsetAsync(x, 0, len * sizeof(double), c->st));
+  *iters = 0;
+  if (bn == 0.0) return RBM_OK;
+  double* r = c->mb;  // residual
+  HIPCHECK(hipMemcpyAsync(r, b, len * sizeof(double), hipMemcpyDeviceToDevice, c->st));
+  double rn = bn;
+  for (int cycle = 0; cycle <= c->opt.max_restart; ++cycle) {
+    HIPCHECK(hipMemsetAsync(c->g, 0, (m + 2) * sizeof(double), c->st));
+    HIPCHECK(hipMemsetAsync(c->H, 0, (size_t)(m + 1) * (m + 1) * sizeof(double), c->st));
+    c->pinned[1] = rn;
+    HIPCHECK(hipMemcpyAsync(c->g, c->pinned + 1, sizeof(double), hipMemcpyHostToDevice, c->st));
+    HIPCHECK(launch_scale_copy(len, r, c->g, 1, c->V, c->st));
+    int k;
+    for (k = 0; k < m; ++k) {
+      double* vk = c->V + (size_t)k * len;
+      double* w = c->V + (size_t)(k + 1) * len;
+      if ((s = magnetic_apply(c, eta, vk, w)) != RBM_OK) return s;
+      double* hcol = c->H + (size_t)k * ldh;
+      HIPCHECK(launch_dots(k + 1, len, c->V, len, w, c->partial, c->nblk, c->st));
+      HIPCHECK(launch_dots_final(k + 1, c->nblk, c->partial, hcol, nullptr, c->st));
+      HIPCHECK(launch_vupdate(k + 1, len, c->V, len, hcol, w, 0, c->st));
+      HIPCHECK(launch_dots(k + 1, len, c->V, len, w, c->partial, c->nblk, c->st));
+      HIPCHECK(launch_dots_final(k + 1, c->nblk, c->partial, c->htmp, hcol, c->st));
+      HIPCHECK(launch_vupdate(k + 1, len, c->V, len, c->htmp, w, 0, c->st));
+      HIPCHECK(launch_dots(1, len, w, len, w, c->partial, c->nblk, c->st));
+      HIPCHECK(launch_dots_final_sqrt(c->nblk, c->partial, hcol + k + 1, c->st));
+      HIPCHECK(launch_scale_copy(len, w, hcol + k + 1, 1, w, c->st));
+      HIPCHECK(launch_givens(k, ldh, c->H, c->cs, c->sn, c->g, nullptr, nullptr, c->scal, c->st));
+      double res;
+      if ((s = read_scalar(c, c->scal, &res)) != RBM_OK) return s;
+      if (!std::isfinite(res)) return fail(RBM_E_DEVICE, "non-finite GMRES residual");
+      ++*iters;
+      if (res <= tol * bn) { ++k; break; }
+    }
+    if (k > m) k = m;
+    HIPCHECK(launch_backsolve(k, ldh, c->H, c->g, c->y, c->st));
+    HIPCHECK(launch_vupdate(k, len, c->V, len, c->y, c->mtmp, 1, c->st));
+    HIPCHECK(launch_axpby(len, 1.0, x, 1.0, c->mtmp, x, c->st));
+    // true residual r = b - A x
+    if ((s = magnetic_apply(c, eta, x, c->mphi)) != RBM_OK) return s;
+    HIPCHECK(launch_axpby(len, 1.0, b, -1.0, c->mphi, r, c->st));
+    if ((s = norm_into(c, r, c->scal + 4, len)) != RBM_OK) return s;
+    if ((s = read_scalar(c, c->scal + 4, &rn)) != RBM_OK) return s;
+    if (rn <= tol * bn) return RBM_OK;
+  }
+  return fail(RBM_E_NOCONV, "magnetic GMRES did not reach tol");
+}
+
+extern "C" rbm_status rbm_magnetic_traction_dev(rbm_ctx* c, const double* H0, double mu_ratio,
+                                               double mu0, double tol, double* d_rho, double* d_FT,
+                                               int* iters) {
+  if (!c || !H0 || !d_rho) return fail(RBM_E_INVAL, "null argument");
+  if (!c->opt.magnetic) return fail(RBM_E_STATE, "create the context with options.magnetic = 1");
+  if (!(mu_ratio > 0.0) || !std::isfinite(mu_ratio) || !(mu0 > 0.0) || !std::isfinite(mu0) ||
+      !(tol > 0.0) || !all_finite(H0, 3))
+    return fail(RBM_E_INVAL, "mu_ratio, mu0, tol must be > 0 and H0 finite");
+  if (!c->ws) return fail(RBM_E_NOMEM, "bind a workspace first");
+  if (!c->setup_done) return fail(RBM_E_STATE, "call rbm_setup first");
+  if (c->n < 1) return fail(RBM_E_STATE, "set bodies first");
+  rbm_status s;
+  if ((s = upload_bodies(c)) != RBM_OK) return s;
+  const int n = c->n, M = c->M, N = n * M;
+  const int nsp = split_for(c, N);
+  const double eta = (mu_ratio - 1.0) / (mu_ratio + 1.0);
+  hipStream_t st = c->st;
+  // q from (1/2 I + eta K^L) q = eta H0 . n
+  HIPCHECK(launch_hdot(N, c->Nn, H0[0], H0[1], H0[2], eta, 0, c->mdn, st));
+  int it = 0;
+  if ((s = magnetic_gmres(c, eta, c->mdn, c->mq, tol, &it)) != RBM_OK) return s;
+  if (iters) *iters = it;
+  // phi = -H0 . X + S^L q
+  HIPCHECK(launch_scalar_self(n, M, c->sid, c->SL0, c->mq, c->mtmp, st));
+  HIPCHECK(launch_pack_scalar(N, c->X, c->W, c->mq, c->src, st));
+  HIPCHECK(launch_far<double>(3, N, M, c->X, c->Nn, c->src, c->part, nsp, st));
+  HIPCHECK(launch_scalar_combine(N, nsp, c->part, 1.0, c->mtmp, 1.0, nullptr, 0.0, c->mphi, st));
+  HIPCHECK(launch_hdot(N, c->X, H0[0], H0[1], H0[2], -1.0, 1, c->mphi, st));
+  // exterior normal derivative dn = -H0 . n - q/2 + K^L q
+  HIPCHECK(launch_scalar_self(n, M, c->sid, c->KL0, c->mq, c->mtmp, st));
+  HIPCHECK(launch_far<double>(2, N, M, c->X, c->Nn, c->src, c->part, nsp, st));
+  HIPCHECK(launch_scalar_combine(N, nsp, c->part, 1.0, c->mtmp, 1.0, c->mq, -0.5, c->mdn, st));
+  HIPCHECK(launch_hdot(N, c->Nn, H0[0], H0[1], H0[2], -1.0, 1, c->mdn, st));
+  // field and Maxwell traction
+  HIPCHECK(launch_magnetic_traction(n, M, c->sid, c->Rm, c->Nn, c->tang, c->Dth, c->Dph, c->mphi, c->mdn,
+                                    mu0, d_rho, st));
+  if (d_FT) {
+    HIPCHECK(launch_moments(n, M, d_rho, c->X, c->W, c->cen, c->mom, st));
+    HIPCHECK(hipMemcpyAsync(d_FT, c->mom, 6 * (size_t)n * sizeof(double), hipMemcpyDeviceToDevice, st));
+  }
+  HIPCHECK(hipStreamSynchronize(st));
+  return RBM_OK;
+}
+
 extern "C" const void* rbm_debug_ptr(rbm_ctx* c, const char* name) {
   if (!c || !name || !c->ws) return nullptr;
   const std::string s(name);
@@ -1096,6 +1237,11 @@ extern "C" const void* rbm_debug_ptr(rbm_ctx* c, const char* name) {
   if (s == "Rm") return c->Rm;
   if (s == "Ftab") return c->Ftab;
   if (s == "Ytab") return c->Ytab;
+  if (s == "mag_q") return c->mq;
+  if (s == "mag_phi") return c->mphi;
+  if (s == "mag_dn") return c->mdn;
+  if (s == "SL0") return c->SL0;
+  if (s == "KL0") return c->KL0;
   if (s == "U") return c->U;
   if (s == "fr") return c->fr;
   if (s == "fw") return c->fw;
@@ -1598,7 +1744,7 @@ extern "C" rbm_status rbm_learned_guess_dev(rbm_ctx* c, const double* d_FT, doub
   SolveState S;
   c->ev_used = 0;
   double bnorm;
-  if ((s = build_rhs(c, S, d_FT, &bnorm)) != RBM_OK) return s;
+  if ((s = build_rhs(c, S, d_FT, nullptr, &bnorm)) != RBM_OK) return s;
   if ((s = self_apply(c, S, 1, 0, c->b, c->yb)) != RBM_OK) return s;
   HIPCHECK(launch_combine(N, c->M, 0, nullptr, 0.0, nullptr, 0.0, c->yb, c->Rm, 1.0, c->mu, c->st));
   if ((s = learned_correction(c, d_FT)) != RBM_OK) return s;

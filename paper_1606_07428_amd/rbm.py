@@ -26,7 +26,8 @@ EXPORTED = [
     "rbm_learned_capture", "rbm_learned_set_capture", "rbm_learned_train", "rbm_learned_info",
     "rbm_learned_get_params", "rbm_learned_set_params", "rbm_learned_forward_dev",
     "rbm_learned_loss_grad_dev", "rbm_learned_features_dev", "rbm_learned_guess_dev", "rbm_set_guess",
-    "rbm_apply_dev", "rbm_find_contacts", "rbm_solve_contacts",
+    "rbm_apply_dev", "rbm_find_contacts", "rbm_solve_contacts", "rbm_magnetic_traction_dev",
+    "rbm_solve_density_dev",
 ]
 
 
@@ -35,7 +36,7 @@ class Options(ctypes.Structure):
                 ("tol", ctypes.c_double), ("max_iter", ctypes.c_int), ("max_restart", ctypes.c_int),
                 ("precision", ctypes.c_int), ("guess", ctypes.c_int), ("inner_tol", ctypes.c_double),
                 ("stream", ctypes.c_void_p), ("p_up", ctypes.c_int), ("near_factor", ctypes.c_double),
-                ("contact_delta", ctypes.c_double)]
+                ("contact_delta", ctypes.c_double), ("magnetic", ctypes.c_int)]
 
 
 class SolveInfo(ctypes.Structure):
@@ -107,6 +108,8 @@ def load():
         "rbm_apply_dev": (I, [P, P, P]),
         "rbm_find_contacts": (I, [P, D, I, P, P, P]),
         "rbm_solve_contacts": (I, [P, P, I, P, P, P, P, P]),
+        "rbm_magnetic_traction_dev": (I, [P, P, D, D, D, P, P, P]),
+        "rbm_solve_density_dev": (I, [P, P, P, P]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -145,7 +148,7 @@ class Solver:
     def __init__(self, p, shapes, shape_id, centres, quats, eta=1.0, p_sing=0, tol=1e-12,
                  max_iter=100, max_restart=4, precision=FP64, guess=GUESS_BLOCKDIAG,
                  inner_tol=1e-4, n_max=None, stream=None, device="cuda", p_up=0, near_factor=5.0,
-                 contact_delta=0.0):
+                 contact_delta=0.0, magnetic=0):
         import torch
         lib = load()
         self.torch = torch
@@ -156,6 +159,7 @@ class Solver:
         opt.max_iter, opt.max_restart, opt.precision, opt.guess = max_iter, max_restart, precision, guess
         opt.inner_tol = inner_tol
         opt.p_up, opt.near_factor, opt.contact_delta = p_up, near_factor, contact_delta
+        opt.magnetic = magnetic
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
         opt.stream = ctypes.c_void_p(self.stream.cuda_stream)
         self.opt = opt
@@ -233,6 +237,26 @@ class Solver:
         _check(load().rbm_apply_dev(self.ctx, ctypes.c_void_p(mu_dev.data_ptr()),
                                     ctypes.c_void_p(y.data_ptr())))
         return y
+
+    def magnetic_traction(self, H0, mu_ratio, mu0=1.0, tol=1e-12):
+        """Maxwell traction (3, N) CUDA tensor, net loads (n, 6) CUDA tensor, GMRES iterations."""
+        rho = self.torch.empty((3, self.N), dtype=self.torch.float64, device=self.device)
+        FT = self.torch.empty((self.n, 6), dtype=self.torch.float64, device=self.device)
+        h = _f64(H0, (3,))
+        it = ctypes.c_int()
+        _check(load().rbm_magnetic_traction_dev(self.ctx, _ptr(h), float(mu_ratio), float(mu0), float(tol),
+                                                ctypes.c_void_p(rho.data_ptr()), ctypes.c_void_p(FT.data_ptr()),
+                                                ctypes.byref(it)))
+        return rho, FT, it.value
+
+    def solve_density_dev(self, rho_dev, VW_dev):
+        """Mobility solve with incident density rho_dev (3, N) CUDA tensor into VW_dev (n, 6)."""
+        info = SolveInfo()
+        st = _check(load().rbm_solve_density_dev(self.ctx, ctypes.c_void_p(rho_dev.data_ptr()),
+                                                 ctypes.c_void_p(VW_dev.data_ptr()), ctypes.byref(info)),
+                    allow=(RBM_E_NOCONV,))
+        self.last_status = st
+        return info.as_dict()
 
     def find_contacts(self, delta, max_contacts=4096):
         """Body pairs whose closest nodes are within delta: (pairs (k, 2), points (k, 3))."""
