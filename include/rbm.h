@@ -92,7 +92,8 @@ typedef struct {
                            stage (bodies whose closest nodes are within contact_delta, see
                            rbm_find_contacts / rbm_solve_contacts); 0 = off */
   int magnetic;         /* 1: set up the Laplace operators of the magnetostatic problem (§4) for
-                           rbm_magnetic_traction_dev (two M x M operators per shape); 0 = off */
+                           rbm_magnetic_traction_dev and rbm_step_rk4_magnetic (two M x M
+                           operators per shape); 0 = off */
 } rbm_options;
 
 typedef struct {
@@ -277,6 +278,17 @@ rbm_status rbm_magnetic_traction_dev(rbm_ctx* ctx, const double* H0, double mu_r
  * traction above) in place of F/|Gamma| + tau^{-1} T x (x - x^c) (§2.2, §4); velocities
  * to d_VW ([n][6], device).  The learned guess is not used here (block-diagonal instead). */
 rbm_status rbm_solve_density_dev(rbm_ctx* ctx, const double* d_rho, double* d_VW, rbm_solve_info* info);
+
+/* One RK4 step of a magnetorheological suspension (§4): at each of the four stages the
+ * magnetostatic problem of rbm_magnetic_traction_dev is solved at the stage poses (H0 host
+ * [3], mu_ratio, mu0, GMRES tolerance tol_mag) and its Maxwell traction drives that stage's
+ * mobility solve (rbm_solve_density_dev); stage updates as in rbm_step_rk4, including the
+ * contact correction when options.contact_delta > 0.  Needs options.magnetic = 1.
+ * stage_info[4] may be NULL.  RBM_E_NOCONV if a mobility solve missed its tolerance (the
+ * step is still taken); an error of a magnetostatic solve ends the call with the poses of
+ * the stage it was solving. */
+rbm_status rbm_step_rk4_magnetic(rbm_ctx* ctx, double dt, const double* H0, double mu_ratio,
+                                 double mu0, double tol_mag, rbm_solve_info* stage_info);
 
 /* Device pointers of internal arrays for inspection (valid until the workspace is
  * rebound).  name: "X","N","W" ([3][N]/[N] lab nodes, normals, weights), "mu",

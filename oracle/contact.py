@@ -63,11 +63,13 @@ def contact_maps(prob, contacts):
     return C, D
 
 
-def solve_with_contacts(prob, FT, contacts, mobility_solve):
+def solve_with_contacts(prob, FT, contacts, mobility_solve, V0=None):
     """(V_0, F_c, V): mobility_solve(FT (n, 6)) -> VW (n, 6) is the mobility problem on
-    this configuration (e.g. a dense oracle solve)."""
-    FT = np.asarray(FT, dtype=np.float64).reshape(prob.n, 6)
-    V0 = mobility_solve(FT)
+    this configuration (e.g. a dense oracle solve).  V0, if given, replaces the solve
+    with the loads FT (e.g. velocities driven by a magnetic traction, §4)."""
+    if V0 is None:
+        V0 = mobility_solve(np.asarray(FT, dtype=np.float64).reshape(prob.n, 6))
+    V0 = np.asarray(V0, dtype=np.float64).reshape(prob.n, 6)
     if not contacts:
         return V0, np.zeros((0, 3)), V0
     C, D = contact_maps(prob, contacts)

@@ -91,7 +91,8 @@ struct rbm_ctx {
   // magnetostatics (option magnetic): Laplace self operators, derivative matrices, tangents,
   // scalar work vectors
   double *SL0 = nullptr, *KL0 = nullptr, *Dth = nullptr, *Dph = nullptr, *tang = nullptr,
-         *mq = nullptr, *mphi = nullptr, *mdn = nullptr, *mtmp = nullptr, *mb = nullptr;
+         *mq = nullptr, *mphi = nullptr, *mdn = nullptr, *mtmp = nullptr, *mb = nullptr,
+         *mrho = nullptr;
   // contact search: coarse bounding radius per shape (device and host), candidate pairs
   double *rbc = nullptr, *cres = nullptr;
   int* ccand = nullptr;
@@ -321,6 +322,7 @@ static size_t layout(rbm_ctx* c, int nmax, bool assign) {
     take(c->SL0, ns * M * M); take(c->KL0, ns * M * M);
     take(c->Dth, (size_t)M * M); take(c->Dph, (size_t)M * M); take(c->tang, ns * 6 * M);
     take(c->mq, N); take(c->mphi, N); take(c->mdn, N); take(c->mtmp, N); take(c->mb, N);
+    take(c->mrho, N3);
   }
   if (c->pu) {
     const size_t Mu = c->Mu;
@@ -1007,6 +1009,10 @@ static bool small_solve(int n, std::vector<double>& A, std::vector<double>& b) {
   return true;
 }
 
+static rbm_status contact_correct(rbm_ctx* c, const std::vector<double>& V0, rbm_solve_info i0,
+                                  int n_contacts, const int* pairs, const double* points, double* VW,
+                                  double* Fc, rbm_solve_info* info);
+
 extern "C" rbm_status rbm_solve_contacts(rbm_ctx* c, const double* FT, int n_contacts,
                                          const int* pairs, const double* points, double* VW,
                                          double* Fc, rbm_solve_info* info) {
@@ -1019,10 +1025,22 @@ extern "C" rbm_status rbm_solve_contacts(rbm_ctx* c, const double* FT, int n_con
     if (a < 0 || b < 0 || a >= n || b >= n || a == b) return fail(RBM_E_INVAL, "bad contact pair");
     if (!all_finite(points + 3 * k, 3)) return fail(RBM_E_INVAL, "non-finite contact point");
   }
-  rbm_solve_info i0, ik;
+  rbm_solve_info i0;
   std::vector<double> V0(6 * (size_t)n);
   rbm_status s = rbm_solve(c, FT, V0.data(), &i0);
   if (s != RBM_OK) return s;
+  return contact_correct(c, V0, i0, n_contacts, pairs, points, VW, Fc, info);
+}
+
+// Given the velocities V0 without contact forces (host, [n][6]) and the validated
+// contact list: the mobility solves of the unit contact forces, (D M C) F_c = -D V0 and
+// VW = V0 + M C F_c.  i0 carries V0's solve statistics and accumulates the rest.
+static rbm_status contact_correct(rbm_ctx* c, const std::vector<double>& V0, rbm_solve_info i0,
+                                  int n_contacts, const int* pairs, const double* points, double* VW,
+                                  double* Fc, rbm_solve_info* info) {
+  const int n = c->n;
+  rbm_solve_info ik;
+  rbm_status s;
   const int m = 3 * n_contacts;
   std::vector<double> Vc((size_t)m * 6 * n), load(6 * (size_t)n);
   // column (k, e) of M C: the solve for a unit force along e at x_k on body a, its
@@ -1172,6 +1190,9 @@ static rbm_status magnetic_gmres(rbm_ctx* c, double eta, const double* b, double
   return fail(RBM_E_NOCONV, "magnetic GMRES did not reach tol");
 }
 
+static rbm_status magnetic_traction_impl(rbm_ctx* c, const double* H0, double mu_ratio, double mu0,
+                                         double tol, double* d_rho, double* d_FT, int* iters);
+
 extern "C" rbm_status rbm_magnetic_traction_dev(rbm_ctx* c, const double* H0, double mu_ratio,
                                                double mu0, double tol, double* d_rho, double* d_FT,
                                                int* iters) {
@@ -1185,6 +1206,14 @@ extern "C" rbm_status rbm_magnetic_traction_dev(rbm_ctx* c, const double* H0, do
   if (c->n < 1) return fail(RBM_E_STATE, "set bodies first");
   rbm_status s;
   if ((s = upload_bodies(c)) != RBM_OK) return s;
+  return magnetic_traction_impl(c, H0, mu_ratio, mu0, tol, d_rho, d_FT, iters);
+}
+
+// Density q, potential, exterior normal derivative, field and Maxwell traction at the
+// current poses (arguments validated by the caller).
+static rbm_status magnetic_traction_impl(rbm_ctx* c, const double* H0, double mu_ratio, double mu0,
+                                         double tol, double* d_rho, double* d_FT, int* iters) {
+  rbm_status s;
   const int n = c->n, M = c->M, N = n * M;
   const int nsp = split_for(c, N);
   const double eta = (mu_ratio - 1.0) / (mu_ratio + 1.0);
@@ -1366,6 +1395,73 @@ extern "C" rbm_status rbm_step_rk4(rbm_ctx* c, double dt, const double* d_FT,
     if (s == RBM_E_NOCONV) worst = s;
     else if (s != RBM_OK) return s;
     HIPCHECK(launch_rk_deriv(n, c->VW, c->quat, c->kst, c->kacc, wgt[k], k == 0, st));
+  }
+  HIPCHECK(launch_rk_final(n, c->cen0, c->quat0, c->kacc, dt, c->cen, c->quat, st));
+  if ((s = refresh_nodes(c)) != RBM_OK) return s;
+  HIPCHECK(hipMemcpyAsync(c->cen_h.data(), c->cen, 3 * n * sizeof(double), hipMemcpyDeviceToHost, st));
+  HIPCHECK(hipMemcpyAsync(c->quat_h.data(), c->quat, 4 * n * sizeof(double), hipMemcpyDeviceToHost, st));
+  HIPCHECK(hipStreamSynchronize(st));
+  c->bodies_dirty = false;
+  c->have_solution = true;
+  if (worst != RBM_OK) return fail(worst, "a stage solve did not reach tol");
+  return RBM_OK;
+}
+
+// RK4 step of a magnetorheological suspension (§4): at every stage the magnetostatic
+// problem at the stage poses gives the Maxwell traction, which is the incident density of
+// that stage's mobility solve; contacts (contact_delta > 0) correct the stage velocities
+// as in rbm_step_rk4.
+extern "C" rbm_status rbm_step_rk4_magnetic(rbm_ctx* c, double dt, const double* H0, double mu_ratio,
+                                            double mu0, double tol_mag, rbm_solve_info* stage_info) {
+  if (!c || !H0) return fail(RBM_E_INVAL, "null argument");
+  if (!(dt > 0.0) || !std::isfinite(dt)) return fail(RBM_E_INVAL, "dt must be > 0");
+  if (!c->opt.magnetic) return fail(RBM_E_STATE, "create the context with options.magnetic = 1");
+  if (!(mu_ratio > 0.0) || !std::isfinite(mu_ratio) || !(mu0 > 0.0) || !std::isfinite(mu0) ||
+      !(tol_mag > 0.0) || !all_finite(H0, 3))
+    return fail(RBM_E_INVAL, "mu_ratio, mu0, tol_mag must be > 0 and H0 finite");
+  if (!c->ws) return fail(RBM_E_NOMEM, "bind a workspace first");
+  if (!c->setup_done) return fail(RBM_E_STATE, "call rbm_setup first");
+  if (c->n < 1) return fail(RBM_E_STATE, "set bodies first");
+  rbm_status s;
+  if ((s = upload_bodies(c)) != RBM_OK) return s;
+  const int n = c->n;
+  hipStream_t st = c->st;
+  HIPCHECK(hipMemcpyAsync(c->cen0, c->cen, 3 * n * sizeof(double), hipMemcpyDeviceToDevice, st));
+  HIPCHECK(hipMemcpyAsync(c->quat0, c->quat, 4 * n * sizeof(double), hipMemcpyDeviceToDevice, st));
+  const double a[4] = {0.0, 0.5, 0.5, 1.0}, wgt[4] = {1.0, 2.0, 2.0, 1.0};
+  rbm_status worst = RBM_OK;
+  for (int k = 0; k < 4; ++k) {
+    HIPCHECK(launch_rk_stage(n, c->cen0, c->quat0, c->kst, a[k], dt, c->cen, c->quat, st));
+    if ((s = refresh_nodes(c)) != RBM_OK) return s;
+    c->bodies_dirty = false;
+    int it = 0;
+    if ((s = magnetic_traction_impl(c, H0, mu_ratio, mu0, tol_mag, c->mrho, nullptr, &it)) != RBM_OK) return s;
+    rbm_solve_info i0;
+    std::memset(&i0, 0, sizeof(i0));
+    s = solve_impl(c, nullptr, c->VW, &i0, c->mrho);
+    if (s == RBM_E_NOCONV) worst = s;
+    else if (s != RBM_OK) return s;
+    if (stage_info) stage_info[k] = i0;
+    if (c->opt.contact_delta > 0.0) {
+      HIPCHECK(hipMemcpyAsync(c->cen_h.data(), c->cen, 3 * n * sizeof(double), hipMemcpyDeviceToHost, st));
+      HIPCHECK(hipMemcpyAsync(c->quat_h.data(), c->quat, 4 * n * sizeof(double), hipMemcpyDeviceToHost, st));
+      HIPCHECK(hipStreamSynchronize(st));
+      int nf = 0;
+      if ((s = rbm_find_contacts(c, c->opt.contact_delta, 0, &nf, nullptr, nullptr)) != RBM_OK) return s;
+      if (nf > 0) {
+        std::vector<int> cp(2 * (size_t)nf);
+        std::vector<double> cx(3 * (size_t)nf), fc(3 * (size_t)nf), vw(6 * (size_t)n), V0(6 * (size_t)n);
+        if ((s = rbm_find_contacts(c, c->opt.contact_delta, nf, &nf, cp.data(), cx.data())) != RBM_OK) return s;
+        HIPCHECK(hipMemcpyAsync(V0.data(), c->VW, V0.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+        HIPCHECK(hipStreamSynchronize(st));
+        s = contact_correct(c, V0, i0, nf, cp.data(), cx.data(), vw.data(), fc.data(),
+                            stage_info ? stage_info + k : nullptr);
+        if (s != RBM_OK) return s;
+        HIPCHECK(hipMemcpyAsync(c->VW, vw.data(), vw.size() * sizeof(double), hipMemcpyHostToDevice, st));
+      }
+    }
+    HIPCHECK(launch_rk_deriv(n, c->VW, c->quat, c->kst, c->kacc, wgt[k], k == 0, st));
+    HIPCHECK(hipStreamSynchronize(st));
   }
   HIPCHECK(launch_rk_final(n, c->cen0, c->quat0, c->kacc, dt, c->cen, c->quat, st));
   if ((s = refresh_nodes(c)) != RBM_OK) return s;

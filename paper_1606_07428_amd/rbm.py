@@ -27,7 +27,7 @@ EXPORTED = [
     "rbm_learned_get_params", "rbm_learned_set_params", "rbm_learned_forward_dev",
     "rbm_learned_loss_grad_dev", "rbm_learned_features_dev", "rbm_learned_guess_dev", "rbm_set_guess",
     "rbm_apply_dev", "rbm_find_contacts", "rbm_solve_contacts", "rbm_magnetic_traction_dev",
-    "rbm_solve_density_dev",
+    "rbm_solve_density_dev", "rbm_step_rk4_magnetic",
 ]
 
 
@@ -110,6 +110,7 @@ def load():
         "rbm_solve_contacts": (I, [P, P, I, P, P, P, P, P]),
         "rbm_magnetic_traction_dev": (I, [P, P, D, D, D, P, P, P]),
         "rbm_solve_density_dev": (I, [P, P, P, P]),
+        "rbm_step_rk4_magnetic": (I, [P, D, P, D, D, D, P]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -285,6 +286,17 @@ class Solver:
         four stage infos."""
         infos = (SolveInfo * 4)()
         st = _check(load().rbm_step_rk4(self.ctx, float(dt), ctypes.c_void_p(FT_dev.data_ptr()), infos),
+                    allow=(RBM_E_NOCONV,))
+        self.last_status = st
+        return [i.as_dict() for i in infos]
+
+    def step_rk4_magnetic(self, dt, H0, mu_ratio, mu0=1.0, tol_mag=1e-12):
+        """One RK4 step driven by the Maxwell traction of the field H0 (§4); returns the
+        four stage infos."""
+        infos = (SolveInfo * 4)()
+        h = _f64(H0, (3,))
+        st = _check(load().rbm_step_rk4_magnetic(self.ctx, float(dt), _ptr(h), float(mu_ratio), float(mu0),
+                                                 float(tol_mag), infos),
                     allow=(RBM_E_NOCONV,))
         self.last_status = st
         return [i.as_dict() for i in infos]

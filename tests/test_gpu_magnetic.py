@@ -97,3 +97,64 @@ def test_two_spheres_dipole_force_on_gpu():
         assert abs(F[1, 0] / ref - 1) < 0.05
         assert np.abs(F[0, :3] + F[1, :3]).max() < 1e-8 * abs(ref)
     s.close()
+
+
+def _oracle_mhd_velocity(w, H0, mu_r, delta=0.0):
+    from oracle import contact as ct
+    shapes = oracle_problem(w).shapes
+
+    def vel(c, q):
+        prob = sy.Problem(shapes, w["shape_id"], c, q)
+        mag = mg.Magnetic(prob, mu_r, H0)
+        rho = mag.traction(mag.field(mag.density()))
+        V0 = sy.solve_dense_density(prob, rho)[1]
+        contacts = ct.find_contacts(prob, delta) if delta > 0 else []
+        if not contacts:
+            return V0
+        return ct.solve_with_contacts(prob, None, contacts, lambda FT: sy.solve_dense(prob, FT)[2], V0=V0)[2]
+    return vel
+
+
+def _compare_poses(s, c, q, tol):
+    c_g, q_g = s.bodies()
+    assert np.abs(c_g - c).max() < tol
+    Rg = np.array([sy.quat_to_rot(x) for x in q_g])
+    Ro = np.array([sy.quat_to_rot(x) for x in q])
+    assert np.abs(Rg - Ro).max() < tol
+
+
+@pytest.mark.parametrize("n,p,seed,dt", [(3, 5, 41, 0.5)])
+def test_magnetic_rk4_step_matches_oracle(n, p, seed, dt):
+    from oracle import timestep as ts
+    _case(f"magnetic rk4 n={n} p={p} seed={seed} dt={dt}")
+    w = inputs.tiny(n, p, seed=seed)
+    H0, mu_r = 3.0 * np.array([1.0, -1.0, -1.0]) / math.sqrt(3.0), 2.0
+    s = rbm.solver_for(w, tol=1e-13, magnetic=1)
+    infos = s.step_rk4_magnetic(dt, H0, mu_r, tol_mag=1e-13)
+    assert all(i["rel_residual"] < 1e-13 for i in infos)
+    c, q = np.asarray(w["centres"], float), ts.normalize(np.asarray(w["quats"], float))
+    c1, q1 = ts.rk4_step(_oracle_mhd_velocity(w, H0, mu_r), c, q, dt)
+    assert np.abs(c1 - c).max() > 1e-4          # the bodies did move
+    _compare_poses(s, c1, q1, 1e-11)
+    s.close()
+
+
+def test_magnetic_rk4_step_with_contacts_matches_oracle():
+    """Two spheres touching along the field attract; the contact forces of §3.3 hold them."""
+    from oracle import timestep as ts
+    _case("magnetic rk4 with contacts: two spheres along H0, gap 0.03, delta 0.05")
+    w = _pair(2.03, p=6)
+    H0, mu_r, dt, delta = np.array([4.0, 0.0, 0.0]), 2.0, 0.2, 0.05
+    s = rbm.solver_for(w, tol=1e-13, magnetic=1, contact_delta=delta)
+    s.step_rk4_magnetic(dt, H0, mu_r, tol_mag=1e-13)
+    c, q = np.asarray(w["centres"], float), np.asarray(w["quats"], float)
+    c1, q1 = ts.rk4_step(_oracle_mhd_velocity(w, H0, mu_r, delta), c, q, dt)
+    _compare_poses(s, c1, q1, 1e-11)
+    # without the contact forces the pair closes the gap
+    s2 = rbm.solver_for(w, tol=1e-13, magnetic=1)
+    s2.step_rk4_magnetic(dt, H0, mu_r, tol_mag=1e-13)
+    gap_free = s2.bodies()[0][1, 0] - s2.bodies()[0][0, 0]
+    gap_held = s.bodies()[0][1, 0] - s.bodies()[0][0, 0]
+    assert gap_free < 2.03 - 1e-4 and abs(gap_held - 2.03) < 1e-3 * (2.03 - gap_free)
+    s.close()
+    s2.close()
