@@ -165,6 +165,21 @@ def lattice(n, p):
                 shape_id=np.zeros(n, np.int32), centres=cen, quats=np.tile([1.0, 0.0, 0.0, 0.0], (n, 1)), FT=FT)
 
 
+def mhd_lattice(side=8, p=8, spacing=3.0, jitter=0.0, seed=0):
+    """The magnetorheological workload of §4 (Fig. 1): side^3 unit spheres on a cubic lattice
+    (centre spacing `spacing`, optionally jittered uniformly by +-jitter per coordinate),
+    identity orientations, no external loads; the field is applied separately."""
+    rng = np.random.default_rng(160607428 + 50 + seed)
+    g = np.arange(side) * spacing
+    cen = np.array([[x, y, z] for z in g for y in g for x in g])
+    if jitter > 0:
+        cen = cen + rng.uniform(-jitter, jitter, cen.shape)
+    n = len(cen)
+    return dict(name=f"mhd{n}_p{p}", p=p, eta=1.0, shapes=[("radial", np.array([math.sqrt(4 * math.pi)]))],
+                shape_id=np.zeros(n, np.int32), centres=cen, quats=np.tile([1.0, 0.0, 0.0, 0.0], (n, 1)),
+                FT=np.zeros((n, 6)))
+
+
 def workload_perturbed(n, p, phi, gap, rng, name="perturbed", lmax=4, amp=0.1):
     """n distinct SH-perturbed spheres (one shape each), volume fraction phi."""
     shapes = [("radial", _radial_perturbed(rng, lmax, amp)) for _ in range(n)]
