@@ -20,6 +20,7 @@ system     incident density, augmented second-kind system, solves, velocities (ย
 timestep   quaternion RK4 evolution of centres and orientations (ยง3.3)
 contact    contact forces between touching bodies (ยง3.3 contact force algorithm)
 magnetic   magnetostatic potential, field and Maxwell traction of permeable bodies (ยง4)
+fmm        fast multipole approximation of the off-body traction sum (the O(N) far field of ยง3.1)
 mlp        FP64 reference of the warm-start network (forward, backward, Adam)
 
 Every floating-point quantity is computed in float64.
