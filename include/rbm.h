@@ -94,6 +94,13 @@ typedef struct {
   int magnetic;         /* 1: set up the Laplace operators of the magnetostatic problem (§4) for
                            rbm_magnetic_traction_dev and rbm_step_rk4_magnetic (two M x M
                            operators per shape); 0 = off */
+  int fmm_order;        /* > 0: order P in [2, 16] of the fast multipole far field (the O(N)
+                           equivalent of the FMM of §3.1) used by the inner GMRES of the
+                           precision form (precision FP32/BF16) in place of the direct float32
+                           sum; outer residuals stay direct float64, so the solve still meets
+                           tol.  0 = off (direct sums everywhere) */
+  int fmm_max_level;    /* deepest octree level the FMM may use, in [2, 6] (workspace grows as
+                           8^level); 0 -> 5 */
 } rbm_options;
 
 typedef struct {
@@ -117,6 +124,8 @@ typedef struct {
   double init_rel_residual; /* ||b - A mu_0|| / ||b|| */
   int near_pairs;     /* ordered near body pairs of the upsampled rule (0 when off) */
   double ms_near;     /* device time of the near-singular corrections (interpolation, sums) */
+  int fmm_level;      /* leaf level of the fast multipole tree of this solve (-1: not used) */
+  int fmm_applies;    /* far sums evaluated by the fast multipole method */
 } rbm_solve_info;
 
 /* Default options: p = 8, p_sing = 0, eta = 1, tol = 1e-12, max_iter = 100,
@@ -324,6 +333,18 @@ rbm_status rbm_far_traction(rbm_ctx* ctx, int n_points, int M, const double* X,
  * (1/(8 pi eta)) [q_b/|d| + d (d.q_b)/|d|^3]  (Stokeslet of §2.1). */
 rbm_status rbm_far_stokeslet(rbm_ctx* ctx, int n_points, int M, const double* X,
                              const double* q, double* u, int precision);
+
+/* rbm_far_traction_fmm: the sum of rbm_far_traction (add = NULL) approximated by the fast
+ *   multipole method of order options.fmm_order (the O(N) far field, §3.1): Stokes through
+ *   four harmonic potentials, complex solid-harmonic expansions on a uniform octree whose
+ *   leaves are at least d_max wide (d_max >= the largest body diameter, so that every
+ *   same-body pair falls in the direct near field), leaf level at most
+ *   options.fmm_max_level (to *level, may be NULL).  Error: geometric in the order
+ *   (about 5e-4 relative at order 10 for suspensions of spheres).  precision 0 = float64,
+ *   1 = float32 arithmetic.  Needs options.fmm_order > 0; RBM_E_INVAL if a leaf would
+ *   hold more than 4096 points.  Synchronous. */
+rbm_status rbm_far_traction_fmm(rbm_ctx* ctx, int n_points, int M, const double* X, const double* Nrm,
+                                const double* q, double d_max, double* y, int precision, int* level);
 
 const char* rbm_last_error(void);
 

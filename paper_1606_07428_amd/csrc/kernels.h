@@ -179,6 +179,24 @@ hipError_t launch_closest_pairs(int ncand, int N, int M, const int* cand, const 
 // rb[s] = max_a |r_a| over the M points r [ns][3][M]
 hipError_t launch_bound_radius(int ns, int M, const double* r, double* rb, hipStream_t st);
 
+// Fast multipole far field (k_fmm.hip).  Expansion orders up to kFmmMaxOrder; a tree is
+// usable when no leaf holds more than kFmmLeafCap points.
+constexpr int kFmmMaxOrder = 16;
+constexpr int kFmmLeafCap = 4096;
+hipError_t launch_fmm_bounds(int N, const double* X, double* out6, hipStream_t st);
+hipError_t launch_fmm_sort_points(int N, int M, const double* X, const double* Nn, const double* lo, double w,
+                                  int nb, int* leaf, int* cnt, int* start, int* fill, int* perm, int* maxcnt,
+                                  double4* Xs, double4* Ns, hipStream_t st);
+hipError_t launch_fmm_finish_tree(int N, int M, int L, const double* X, const double* Nn, const int* start,
+                                  int* perm, double4* Xs, double4* Ns, int* const* cnt_lev, hipStream_t st);
+template <typename T>
+hipError_t launch_fmm_tables(int P, int L, double D, void* tabR, void* tabI, hipStream_t st);
+template <typename T>
+hipError_t launch_fmm_apply(int P, int L, const double* lo, double D, int N, const int* start, const int* perm,
+                            const double4* Xs, const double4* Ns, int* const* cnt_lev, const size_t* lev_off,
+                            const void* tabR, const void* tabI, const void* src, void* Mexp, void* Lexp,
+                            double* out, hipStream_t st);
+
 // ---- magnetostatics (k_magnetic.hip) -------------------------------------------------
 // Laplace self operators S^L, K^L per shape, column-major [ns][M][M] (singular rule)
 hipError_t launch_singular_laplace(int ns, int p, int ps, const double* coef, const double* gx,

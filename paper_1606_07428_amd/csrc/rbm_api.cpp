@@ -93,6 +93,19 @@ struct rbm_ctx {
   double *SL0 = nullptr, *KL0 = nullptr, *Dth = nullptr, *Dph = nullptr, *tang = nullptr,
          *mq = nullptr, *mphi = nullptr, *mdn = nullptr, *mtmp = nullptr, *mb = nullptr,
          *mrho = nullptr;
+  // fast multipole far field (option fmm_order): tree over the current points, sorted
+  // geometry, counts per box and level, translation tables and expansions
+  int *fleaf = nullptr, *fperm = nullptr, *fstart = nullptr, *ffill = nullptr, *fcnt = nullptr,
+      *fmax = nullptr;
+  double4 *fXs = nullptr, *fNs = nullptr;
+  double* fbounds = nullptr;
+  void *ftabR = nullptr, *ftabI = nullptr, *fM = nullptr, *fL = nullptr;
+  bool fmm_ready = false;
+  int fmm_level = 0, fmm_npts = 0;
+  double fmm_lo[3] = {0, 0, 0}, fmm_D = 1.0;
+  size_t fmm_off[8] = {0};
+  int* fmm_cnt[8] = {nullptr};
+  int far_nslots = 0, far_base = 0;  // partial-sum slots of the last far sum, near slot index
   // contact search: coarse bounding radius per shape (device and host), candidate pairs
   double *rbc = nullptr, *cres = nullptr;
   int* ccand = nullptr;
@@ -136,6 +149,8 @@ extern "C" void rbm_default_options(rbm_options* o) {
   o->near_factor = 5.0;
   o->contact_delta = 0.0;
   o->magnetic = 0;
+  o->fmm_order = 0;
+  o->fmm_max_level = 5;
 }
 
 extern "C" const char* rbm_last_error(void) { return g_err.c_str(); }
@@ -157,8 +172,13 @@ extern "C" rbm_status rbm_create(const rbm_options* opt, rbm_ctx** out) {
     return fail(RBM_E_INVAL, "near_factor must be >= 0");
   if (!(opt->contact_delta >= 0.0) || !std::isfinite(opt->contact_delta))
     return fail(RBM_E_INVAL, "contact_delta must be >= 0");
+  if (opt->fmm_order != 0 && (opt->fmm_order < 2 || opt->fmm_order > kFmmMaxOrder))
+    return fail(RBM_E_INVAL, "fmm_order must be 0 or in [2, 16]");
+  if (opt->fmm_order != 0 && opt->fmm_max_level != 0 && (opt->fmm_max_level < 2 || opt->fmm_max_level > 6))
+    return fail(RBM_E_INVAL, "fmm_max_level must be 0 or in [2, 6]");
   rbm_ctx* c = new rbm_ctx();
   c->opt = *opt;
+  if (c->opt.fmm_max_level == 0) c->opt.fmm_max_level = 5;
   if (!(c->opt.inner_tol > 0.0)) c->opt.inner_tol = 1e-4;
   c->p = opt->p;
   c->ps = ps;
@@ -323,6 +343,25 @@ static size_t layout(rbm_ctx* c, int nmax, bool assign) {
     take(c->Dth, (size_t)M * M); take(c->Dph, (size_t)M * M); take(c->tang, ns * 6 * M);
     take(c->mq, N); take(c->mphi, N); take(c->mdn, N); take(c->mtmp, N); take(c->mb, N);
     take(c->mrho, N3);
+  }
+  if (c->opt.fmm_order > 0) {
+    const int Lm = c->opt.fmm_max_level, P = c->opt.fmm_order;
+    const size_t nleaf = (size_t)1 << (3 * Lm);
+    size_t btot = 0;
+    for (int l = 2; l <= Lm; ++l) btot += (size_t)1 << (3 * l);
+    const size_t kc = (size_t)(P + 1) * (P + 2) / 2, kc2 = (size_t)(2 * P + 1) * (2 * P + 2) / 2;
+    take(c->fleaf, N); take(c->fperm, N); take(c->fstart, nleaf + 1); take(c->ffill, nleaf);
+    take(c->fcnt, std::max(btot, nleaf)); take(c->fmax, 64);
+    take(c->fXs, N); take(c->fNs, N); take(c->fbounds, 64);
+    double *tr = nullptr, *ti = nullptr, *me = nullptr, *le = nullptr;
+    take(tr, 2 * (size_t)(Lm - 1) * 8 * kc); take(ti, 2 * (size_t)(Lm - 1) * 343 * kc2);
+    take(me, 2 * btot * 4 * kc); take(le, 2 * btot * 4 * kc);
+    if (assign) {
+      c->ftabR = tr;
+      c->ftabI = ti;
+      c->fM = me;
+      c->fL = le;
+    }
   }
   if (c->pu) {
     const size_t Mu = c->Mu;
@@ -531,6 +570,7 @@ struct SolveState {
   std::vector<std::pair<int, int>> trac_ev, stok_ev, self_ev, near_ev;  // event index pairs
   double far_pairs = 0.0;
   int matvecs = 0;
+  int fmm_applies = 0;
 };
 
 // Partial-sum slots the combine adds for N points: the far sum's split plus, with
@@ -545,7 +585,7 @@ static rbm_status near_correction(rbm_ctx* c, SolveState& S, int kind, const dou
                                   int x_is_body, int prec) {
   if (!c->pu) return RBM_OK;
   const int n = c->n, M = c->M, N = n * M;
-  double* res = c->part + (size_t)split_for(c, N) * 3 * N;
+  double* res = c->part + (size_t)c->far_base * 3 * N;
   const int* ib = c->nitem;
   const int* ip = c->nitem + c->n_items;
   Timer t(c);
@@ -565,12 +605,100 @@ static rbm_status near_correction(rbm_ctx* c, SolveState& S, int kind, const dou
   return RBM_OK;
 }
 
+// Octree of the fast multipole far field over the points X, N ([3][npts], float64) with
+// bodies of M consecutive points and largest body diameter d_max: leaf level = finest level
+// whose width is >= d_max (at most fmm_max_level), points sorted by leaf.  Leaves the
+// context without a tree (fmm_ready false) when some leaf would hold more than kFmmLeafCap
+// points; the far sums are then direct.
+static rbm_status fmm_build(rbm_ctx* c, int npts, int M, const double* X, const double* Nn, double d_max) {
+  c->fmm_ready = false;
+  hipStream_t st = c->st;
+  HIPCHECK(launch_fmm_bounds(npts, X, c->fbounds, st));
+  HIPCHECK(hipMemcpyAsync(c->pinned, c->fbounds, 6 * sizeof(double), hipMemcpyDeviceToHost, st));
+  HIPCHECK(hipStreamSynchronize(st));
+  double e = 0.0;
+  for (int d = 0; d < 3; ++d) {
+    c->fmm_lo[d] = c->pinned[d];
+    e = std::max(e, c->pinned[3 + d] - c->pinned[d]);
+  }
+  c->fmm_D = e > 0.0 ? e * (1.0 + std::ldexp(1.0, -20)) : 1.0;
+  int L = 0;
+  while (L < c->opt.fmm_max_level && std::ldexp(c->fmm_D, -(L + 1)) >= d_max) ++L;
+  c->fmm_level = L;
+  const int nb = 1 << L;
+  // per-level counts: levels 2..L consecutive (or the single leaf level when L < 2)
+  size_t off = 0;
+  for (int l = 0; l < 8; ++l) c->fmm_cnt[l] = nullptr;
+  if (L >= 2) {
+    for (int l = 2; l <= L; ++l) {
+      c->fmm_off[l] = off;
+      c->fmm_cnt[l] = c->fcnt + off;
+      off += (size_t)1 << (3 * l);
+    }
+  } else {
+    c->fmm_off[L] = 0;
+    c->fmm_cnt[L] = c->fcnt;
+  }
+  HIPCHECK(launch_fmm_sort_points(npts, M, X, Nn, c->fmm_lo, std::ldexp(c->fmm_D, -L), nb, c->fleaf,
+                                  c->fmm_cnt[L], c->fstart, c->ffill, c->fperm, c->fmax, c->fXs, c->fNs, st));
+  int maxcnt = 0;
+  HIPCHECK(hipMemcpyAsync(c->pinned, c->fmax, sizeof(int), hipMemcpyDeviceToHost, st));
+  HIPCHECK(hipStreamSynchronize(st));
+  std::memcpy(&maxcnt, c->pinned, sizeof(int));
+  if (maxcnt > kFmmLeafCap) return RBM_OK;
+  HIPCHECK(launch_fmm_finish_tree(npts, M, L, X, Nn, c->fstart, c->fperm, c->fXs, c->fNs, c->fmm_cnt, st));
+  c->fmm_npts = npts;
+  c->fmm_ready = true;
+  return RBM_OK;
+}
+
+// Largest body diameter bound of the current shapes: twice the largest centroid-to-node
+// distance.
+static double fmm_dmax(const rbm_ctx* c) {
+  double r = 0.0;
+  for (double v : c->rbc_h) r = std::max(r, v);
+  return 2.0 * r;
+}
+
+// FMM traction sums of the packed sources c->src (precision prec) into out[3][npts].
+static rbm_status fmm_apply(rbm_ctx* c, int prec, double* out) {
+  const int P = c->opt.fmm_order, L = c->fmm_level;
+  if (prec == 0) {
+    if (L >= 2) HIPCHECK(launch_fmm_tables<double>(P, L, c->fmm_D, c->ftabR, c->ftabI, c->st));
+    HIPCHECK(launch_fmm_apply<double>(P, L, c->fmm_lo, c->fmm_D, c->fmm_npts, c->fstart, c->fperm, c->fXs,
+                                      c->fNs, c->fmm_cnt, c->fmm_off, c->ftabR, c->ftabI, c->src, c->fM, c->fL,
+                                      out, c->st));
+  } else {
+    if (L >= 2) HIPCHECK(launch_fmm_tables<float>(P, L, c->fmm_D, c->ftabR, c->ftabI, c->st));
+    HIPCHECK(launch_fmm_apply<float>(P, L, c->fmm_lo, c->fmm_D, c->fmm_npts, c->fstart, c->fperm, c->fXs,
+                                     c->fNs, c->fmm_cnt, c->fmm_off, c->ftabR, c->ftabI, c->src, c->fM, c->fL,
+                                     out, c->st));
+  }
+  return RBM_OK;
+}
+
 // Far traction of x (lab [3][N] or body frame), precision prec: part sums in c->part
-// (far_slots() of them, the near correction included).
+// (c->far_nslots of them, the near correction included).  prec 0: direct float64; prec 1:
+// float32, by the FMM when the context has a tree for the current poses (inner iterations
+// of the precision form), else direct.
 static rbm_status far_traction(rbm_ctx* c, SolveState& S, const double* x, int x_is_body,
                                int prec) {
   const int N = c->n * c->M;
   const int nsp = split_for(c, N);
+  if (prec != 0 && c->fmm_ready && c->fmm_npts == N) {
+    HIPCHECK(launch_pack_sources<float>(N, c->M, c->X, c->W, c->Rm, x, x_is_body, nullptr, c->src, c->st));
+    Timer t(c);
+    rbm_status s = fmm_apply(c, 1, c->part);
+    if (s != RBM_OK) return s;
+    t.stop();
+    if (t.on) S.trac_ev.push_back({c->ev_used - 2, c->ev_used - 1});
+    c->far_base = 1;
+    c->far_nslots = 1 + (c->pu ? 1 : 0);
+    S.fmm_applies++;
+    return near_correction(c, S, 0, x, x_is_body, 1);
+  }
+  c->far_base = nsp;
+  c->far_nslots = nsp + (c->pu ? 1 : 0);
   if (prec == 0) {
     HIPCHECK(launch_pack_sources<double>(N, c->M, c->X, c->W, c->Rm, x, x_is_body, nullptr, c->src, c->st));
     Timer t(c);
@@ -621,7 +749,7 @@ static rbm_status apply_A(rbm_ctx* c, SolveState& S, const double* x, double* ou
   rbm_status s;
   if ((s = self_apply(c, S, 0, 0, x, c->yb)) != RBM_OK) return s;
   if ((s = far_traction(c, S, x, 0, 0)) != RBM_OK) return s;
-  HIPCHECK(launch_combine(N, c->M, far_slots(c, N), c->part, 1.0, nullptr, 0.0, c->yb, c->Rm, 1.0, out, c->st));
+  HIPCHECK(launch_combine(N, c->M, c->far_nslots, c->part, 1.0, nullptr, 0.0, c->yb, c->Rm, 1.0, out, c->st));
   S.matvecs++;
   return RBM_OK;
 }
@@ -632,7 +760,7 @@ static rbm_status apply_AP(rbm_ctx* c, SolveState& S, int prec, const double* v,
   rbm_status s;
   if ((s = self_apply(c, S, 1, prec, v, c->yb)) != RBM_OK) return s;
   if ((s = far_traction(c, S, c->yb, 1, prec == 0 ? 0 : 1)) != RBM_OK) return s;
-  HIPCHECK(launch_combine(N, c->M, far_slots(c, N), c->part, 1.0, v, 1.0, nullptr, nullptr, 0.0, out, c->st));
+  HIPCHECK(launch_combine(N, c->M, c->far_nslots, c->part, 1.0, v, 1.0, nullptr, nullptr, 0.0, out, c->st));
   S.matvecs++;
   return RBM_OK;
 }
@@ -718,7 +846,7 @@ static rbm_status build_rhs(rbm_ctx* c, SolveState& S, const double* dFT, const 
     HIPCHECK(launch_rho(n, M, dFT, c->cen, c->X, c->tauinv, c->area_b, c->rho, st));
   if ((s = self_apply(c, S, 0, 0, c->rho, c->yb)) != RBM_OK) return s;
   if ((s = far_traction(c, S, c->rho, 0, 0)) != RBM_OK) return s;
-  HIPCHECK(launch_combine(N, M, far_slots(c, N), c->part, -1.0, nullptr, 0.0, c->yb, c->Rm, -1.0, c->b, st));
+  HIPCHECK(launch_combine(N, M, c->far_nslots, c->part, -1.0, nullptr, 0.0, c->yb, c->Rm, -1.0, c->b, st));
   HIPCHECK(launch_moments(n, M, c->rho, c->X, c->W, c->cen, c->mom, st));
   HIPCHECK(launch_add_rigid(n, M, c->mom, c->X, c->cen, 1.0, c->b, st));
   S.matvecs++;
@@ -741,6 +869,12 @@ static rbm_status solve_impl(rbm_ctx* c, const double* dFT, double* dVW, rbm_sol
   SolveState S;
   c->ev_used = 0;
   Timer total(c);
+  // tree of the fast multipole far field for the inner iterations at these poses
+  if (c->opt.fmm_order > 0 && c->opt.precision != RBM_FP64) {
+    if ((s = fmm_build(c, N, M, c->X, c->Nn, fmm_dmax(c))) != RBM_OK) return s;
+  } else {
+    c->fmm_ready = false;
+  }
   double bnorm;
   if ((s = build_rhs(c, S, dFT, d_rho, &bnorm)) != RBM_OK) return s;
   const double abs_tol = c->opt.tol * bnorm;
@@ -828,6 +962,7 @@ static rbm_status solve_impl(rbm_ctx* c, const double* dFT, double* dVW, rbm_sol
     t.stop();
     if (t.on) S.stok_ev.push_back({c->ev_used - 2, c->ev_used - 1});
     S.far_pairs += (double)N * N - (double)n * M * M;
+    c->far_base = split_for(c, N);
     if ((s = near_correction(c, S, 1, c->t2, 0, 0)) != RBM_OK) return s;
   }
   HIPCHECK(launch_combine(N, M, far_slots(c, N), c->part, 1.0 / c->opt.eta, nullptr, 0.0, nullptr, nullptr,
@@ -856,6 +991,8 @@ static rbm_status solve_impl(rbm_ctx* c, const double* dFT, double* dVW, rbm_sol
     info->n_stokeslet = (int)S.stok_ev.size();
     info->pairs_per_launch = (double)N * N - (double)n * M * M;
     info->near_pairs = c->pu ? c->near_pairs : 0;
+    info->fmm_level = c->fmm_ready ? c->fmm_level : -1;
+    info->fmm_applies = S.fmm_applies;
     if (total.on) {
       float ms = 0;
       (void)hipEventElapsedTime(&ms, total.a, total.b);
@@ -1306,6 +1443,30 @@ extern "C" rbm_status rbm_far_traction(rbm_ctx* c, int n_points, int M, const do
   return RBM_OK;
 }
 
+extern "C" rbm_status rbm_far_traction_fmm(rbm_ctx* c, int n_points, int M, const double* X,
+                                           const double* Nrm, const double* q, double d_max, double* y,
+                                           int precision, int* level) {
+  if (!c || !X || !Nrm || !q || !y) return fail(RBM_E_INVAL, "null argument");
+  if (!c->ws) return fail(RBM_E_NOMEM, "bind a workspace first");
+  if (c->opt.fmm_order <= 0) return fail(RBM_E_STATE, "create the context with options.fmm_order > 0");
+  if (n_points < 1 || M < 1) return fail(RBM_E_INVAL, "sizes must be >= 1");
+  if (n_points > c->nmax * c->M) return fail(RBM_E_NOMEM, "more points than the workspace holds");
+  if (!(d_max > 0.0) || !std::isfinite(d_max)) return fail(RBM_E_INVAL, "d_max must be > 0");
+  rbm_status s;
+  if ((s = fmm_build(c, n_points, M, X, Nrm, d_max)) != RBM_OK) return s;
+  if (!c->fmm_ready) return fail(RBM_E_INVAL, "a leaf box would hold more than 4096 points");
+  if (level) *level = c->fmm_level;
+  if (precision == 0)
+    HIPCHECK(launch_pack_sources<double>(n_points, M, X, nullptr, nullptr, q, 0, nullptr, c->src, c->st));
+  else
+    HIPCHECK(launch_pack_sources<float>(n_points, M, X, nullptr, nullptr, q, 0, nullptr, c->src, c->st));
+  s = fmm_apply(c, precision == 0 ? 0 : 1, y);
+  c->fmm_ready = false;  // the tree belongs to these points, not to the bodies
+  if (s != RBM_OK) return s;
+  HIPCHECK(hipStreamSynchronize(c->st));
+  return RBM_OK;
+}
+
 extern "C" rbm_status rbm_far_stokeslet(rbm_ctx* c, int n_points, int M, const double* X,
                                         const double* q, double* u, int precision) {
   if (!c || !X || !q || !u) return fail(RBM_E_INVAL, "null argument");
@@ -1340,6 +1501,7 @@ extern "C" rbm_status rbm_debug_read(rbm_ctx* c, const char* name, size_t offset
 }
 
 static rbm_status refresh_nodes(rbm_ctx* c) {
+  c->fmm_ready = false;
   HIPCHECK(launch_body_prep(c->n, c->quat, c->sid, c->shp, c->Rm, c->tauinv, c->area_b, c->st));
   HIPCHECK(launch_nodes(c->n, c->M, c->sid, c->cen, c->Rm, c->gr, c->gn, c->gw, c->X, c->Nn, c->W,
                         c->Xf, c->Nf, c->st));

@@ -27,7 +27,7 @@ EXPORTED = [
     "rbm_learned_get_params", "rbm_learned_set_params", "rbm_learned_forward_dev",
     "rbm_learned_loss_grad_dev", "rbm_learned_features_dev", "rbm_learned_guess_dev", "rbm_set_guess",
     "rbm_apply_dev", "rbm_find_contacts", "rbm_solve_contacts", "rbm_magnetic_traction_dev",
-    "rbm_solve_density_dev", "rbm_step_rk4_magnetic",
+    "rbm_solve_density_dev", "rbm_step_rk4_magnetic", "rbm_far_traction_fmm",
 ]
 
 
@@ -36,7 +36,8 @@ class Options(ctypes.Structure):
                 ("tol", ctypes.c_double), ("max_iter", ctypes.c_int), ("max_restart", ctypes.c_int),
                 ("precision", ctypes.c_int), ("guess", ctypes.c_int), ("inner_tol", ctypes.c_double),
                 ("stream", ctypes.c_void_p), ("p_up", ctypes.c_int), ("near_factor", ctypes.c_double),
-                ("contact_delta", ctypes.c_double), ("magnetic", ctypes.c_int)]
+                ("contact_delta", ctypes.c_double), ("magnetic", ctypes.c_int),
+                ("fmm_order", ctypes.c_int), ("fmm_max_level", ctypes.c_int)]
 
 
 class SolveInfo(ctypes.Structure):
@@ -48,7 +49,8 @@ class SolveInfo(ctypes.Structure):
                 ("ms_stokeslet", ctypes.c_double), ("pairs_per_launch", ctypes.c_double),
                 ("guess_used", ctypes.c_int), ("fallback_used", ctypes.c_int),
                 ("init_rel_residual", ctypes.c_double), ("near_pairs", ctypes.c_int),
-                ("ms_near", ctypes.c_double)]
+                ("ms_near", ctypes.c_double), ("fmm_level", ctypes.c_int),
+                ("fmm_applies", ctypes.c_int)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -111,6 +113,7 @@ def load():
         "rbm_magnetic_traction_dev": (I, [P, P, D, D, D, P, P, P]),
         "rbm_solve_density_dev": (I, [P, P, P, P]),
         "rbm_step_rk4_magnetic": (I, [P, D, P, D, D, D, P]),
+        "rbm_far_traction_fmm": (I, [P, I, I, P, P, P, D, P, I, P]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -149,7 +152,7 @@ class Solver:
     def __init__(self, p, shapes, shape_id, centres, quats, eta=1.0, p_sing=0, tol=1e-12,
                  max_iter=100, max_restart=4, precision=FP64, guess=GUESS_BLOCKDIAG,
                  inner_tol=1e-4, n_max=None, stream=None, device="cuda", p_up=0, near_factor=5.0,
-                 contact_delta=0.0, magnetic=0):
+                 contact_delta=0.0, magnetic=0, fmm_order=0, fmm_max_level=5):
         import torch
         lib = load()
         self.torch = torch
@@ -161,6 +164,7 @@ class Solver:
         opt.inner_tol = inner_tol
         opt.p_up, opt.near_factor, opt.contact_delta = p_up, near_factor, contact_delta
         opt.magnetic = magnetic
+        opt.fmm_order, opt.fmm_max_level = fmm_order, fmm_max_level
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
         opt.stream = ctypes.c_void_p(self.stream.cuda_stream)
         self.opt = opt
@@ -397,6 +401,17 @@ class Solver:
                                        ctypes.c_void_p(Nrm.data_ptr()), ctypes.c_void_p(q.data_ptr()),
                                        a, ctypes.c_void_p(y.data_ptr()), precision))
         return y
+
+    def far_traction_fmm(self, X, Nrm, q, M, d_max, precision=0):
+        """Fast multipole approximation of far_traction (add = None): ((3, n) tensor, leaf level)."""
+        n = X.shape[1]
+        y = self.torch.empty_like(X)
+        lev = ctypes.c_int()
+        _check(load().rbm_far_traction_fmm(self.ctx, n, M, ctypes.c_void_p(X.data_ptr()),
+                                           ctypes.c_void_p(Nrm.data_ptr()), ctypes.c_void_p(q.data_ptr()),
+                                           float(d_max), ctypes.c_void_p(y.data_ptr()), precision,
+                                           ctypes.byref(lev)))
+        return y, lev.value
 
     def far_stokeslet(self, X, q, M, precision=0):
         torch = self.torch
