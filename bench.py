@@ -306,23 +306,27 @@ def main_compare(args):
         torch.cuda.empty_cache()
         _log(f"trained on {args.learned_from}: {learned}")
     pu = args.p_up
-    forms = [("fp64", rbm.FP64, False, pu), ("mixed_fp32", rbm.MIXED_FP32, False, pu),
-             ("mixed_bf16", rbm.MIXED_BF16, False, pu)]
+    forms = [("fp64", rbm.FP64, False, pu, 0), ("mixed_fp32", rbm.MIXED_FP32, False, pu, 0),
+             ("mixed_bf16", rbm.MIXED_BF16, False, pu, 0)]
     if params is not None:
-        forms.append(("mixed_fp32_learned", rbm.MIXED_FP32, True, pu))
+        forms.append(("mixed_fp32_learned", rbm.MIXED_FP32, True, pu, 0))
+    if args.fmm:
+        forms += [("mixed_fp32_fmm", rbm.MIXED_FP32, False, pu, args.fmm),
+                  ("mixed_bf16_fmm", rbm.MIXED_BF16, False, pu, args.fmm)]
+        out["fmm_order"] = args.fmm
     if args.forms:
         keep = set(args.forms.split(","))
         forms = [f for f in forms if f[0] in keep]
     if pu:
         # the plain smooth rule first: the upsampled float64 solve is then the reference
-        forms.insert(0, ("fp64_plain", rbm.FP64, False, 0))
+        forms.insert(0, ("fp64_plain", rbm.FP64, False, 0, 0))
         out["p_up"], out["near_factor"] = pu, args.near_factor
     ref = None
     plain = None
-    for name, prec, use_net, form_pu in forms:
+    for name, prec, use_net, form_pu, fmm_order in forms:
         t0 = time.perf_counter()
         s = rbm.solver_for(w, tol=args.tol, precision=prec, guess=rbm.GUESS_BLOCKDIAG, p_up=form_pu,
-                           near_factor=args.near_factor)
+                           near_factor=args.near_factor, fmm_order=fmm_order)
         if use_net:
             s.learned_bind(k_nbr=8, hidden=256, n_hidden=3, capacity=1, batch_max=1024, seed=7)
             s.learned_set_params(params)
@@ -346,6 +350,7 @@ def main_compare(args):
             "velocity_rel_err_vs_fp64": float(np.abs(v - ref).max() / np.abs(ref).max()) if ref is not None else 0.0,
             "init_rel_residual": i["init_rel_residual"], "fallback": i["fallback_used"],
             "near_pairs": i["near_pairs"], "near_ms": i["ms_near"],
+            "fmm_level": i["fmm_level"], "fmm_applies": i["fmm_applies"],
             "workspace_GB": s.workspace_bytes / 1e9}
         if plain is not None and form_pu:
             out["forms"][name]["velocity_change_vs_plain_rule"] = float(np.abs(v - plain).max() / np.abs(plain).max())
@@ -486,6 +491,9 @@ def main():
                          "float64 reference solve")
     ap.add_argument("--near-factor", type=float, default=5.0,
                     help="compare mode: kappa of the near test (mean node spacings)")
+    ap.add_argument("--fmm", type=int, default=0,
+                    help="compare mode: add mixed forms whose inner iterations use the fast multipole "
+                         "far field of this order")
     ap.add_argument("--lattice", action="store_true",
                     help="per-matvec and per-solve times on the paper's sphere lattice (Table 2)")
     ap.add_argument("--mhd", action="store_true",

@@ -273,7 +273,8 @@ __device__ __forceinline__ void tri_inv(int c, int& n, int& m) {
 constexpr int kP2mChunk = 16;
 
 // Leaf multipoles: M_d[c] = sum_p charge_d(p) conj(R_c(y_p - centre)), charges
-// (q_x, q_y, q_z, (y - centre).q).  One workgroup per leaf, 4 Kc threads (one output each).
+// (q_x, q_y, q_z, (y - centre).q), sources in leaf order.  One workgroup per leaf, 4 Kc
+// threads (one output each).
 template <typename T>
 __global__ void __launch_bounds__(1024) k_fmm_p2m(int P, int nb, double lox, double loy, double loz, double w,
                                                   const int* __restrict__ start, const int* __restrict__ perm,
@@ -294,7 +295,7 @@ __global__ void __launch_bounds__(1024) k_fmm_p2m(int P, int nb, double lox, dou
     if (o < cnt) {
       const int p = s0 + base + o;
       const double4 x = Xs[p];
-      const Src8<T> s = src[perm[p]];
+      const Src8<T> s = src[p];
       const T sx = (T)(x.x - cx), sy = (T)(x.y - cy), sz = (T)(x.z - cz);
       ch[o][0] = s.v[3];
       ch[o][1] = s.v[4];
@@ -353,17 +354,19 @@ __global__ void __launch_bounds__(1024) k_fmm_m2m(int P, int nc, double wc, cons
 }
 
 // Locals of level lev (side nl, width w): L2L from the parent (lev > 2) plus M2L from the
-// interaction list.  Boxes without points are skipped.
+// interaction list.  Boxes without points are skipped.  The M2L operands are expanded in
+// LDS to all m (n^2 + n + m indexing), so the inner sum has no sign cases.
 template <typename T>
 __global__ void __launch_bounds__(1024) k_fmm_m2l(int P, int nl, double w, const int* __restrict__ cnt,
                                                   const Cx<T>* __restrict__ tabR, const Cx<T>* __restrict__ tabI,
                                                   const Cx<T>* __restrict__ Mlev, const Cx<T>* __restrict__ Lpar,
                                                   Cx<T>* __restrict__ Llev) {
-  __shared__ Cx<T> Ms[4][kFmmKc];
-  __shared__ Cx<T> It[kFmmKc2];
+  constexpr int kFull = (kFmmPMax + 1) * (kFmmPMax + 1), kFull2 = (2 * kFmmPMax + 1) * (2 * kFmmPMax + 1);
+  __shared__ Cx<T> Ms[4][kFull];
+  __shared__ Cx<T> It[kFull2];
   const int b = blockIdx.x;
   if (cnt[b] == 0) return;
-  const int Kc = tri(P + 1, 0), Kc2 = tri(2 * P + 1, 0);
+  const int Kc = tri(P + 1, 0), F = (P + 1) * (P + 1), F2 = (2 * P + 1) * (2 * P + 1);
   const int i = b % nl, j = (b / nl) % nl, k = b / (nl * nl);
   const int o = threadIdx.x, d = o / Kc, c = o % Kc;
   int kk = 0, ll = 0;
@@ -401,20 +404,45 @@ __global__ void __launch_bounds__(1024) k_fmm_m2l(int P, int nl, double w, const
         // psi moves from the source centre to the target's: + (c_s - c_t) . phi = - a . phi
         const T ax = (T)(vx * w), ay = (T)(vy * w), az = (T)(vz * w);
         const Cx<T>* src = Mlev + (size_t)sb * 4 * Kc;
-        for (int q = threadIdx.x; q < Kc; q += blockDim.x) {
-          const Cx<T> a = src[q], bb = src[Kc + q], cc = src[2 * Kc + q], dd = src[3 * Kc + q];
+        for (int q = threadIdx.x; q < F; q += blockDim.x) {
+          int n = 0, m = 0;
+          n = (int)sqrtf((float)q);
+          while (n * n > q) --n;
+          while ((n + 1) * (n + 1) <= q) ++n;
+          m = q - n * n - n;
+          const int h = tri(n, m < 0 ? -m : m);
+          Cx<T> a = src[h], bb = src[Kc + h], cc = src[2 * Kc + h], dd = src[3 * Kc + h];
+          Cx<T> dpsi{dd.re - ax * a.re - ay * bb.re - az * cc.re, dd.im - ax * a.im - ay * bb.im - az * cc.im};
+          if (m < 0) {
+            // X_n^{-m} = (-1)^m conj(X_n^m)
+            const T sg = (m & 1) ? T(-1) : T(1);
+            a = Cx<T>{sg * a.re, -sg * a.im};
+            bb = Cx<T>{sg * bb.re, -sg * bb.im};
+            cc = Cx<T>{sg * cc.re, -sg * cc.im};
+            dpsi = Cx<T>{sg * dpsi.re, -sg * dpsi.im};
+          }
           Ms[0][q] = a;
           Ms[1][q] = bb;
           Ms[2][q] = cc;
-          Ms[3][q] = Cx<T>{dd.re - ax * a.re - ay * bb.re - az * cc.re, dd.im - ax * a.im - ay * bb.im - az * cc.im};
+          Ms[3][q] = dpsi;
         }
-        const Cx<T>* tv = tabI + (size_t)(((vz + 3) * 7 + (vy + 3)) * 7 + (vx + 3)) * Kc2;
-        for (int q = threadIdx.x; q < Kc2; q += blockDim.x) It[q] = tv[q];
+        const Cx<T>* tv = tabI + (size_t)(((vz + 3) * 7 + (vy + 3)) * 7 + (vx + 3)) * tri(2 * P + 1, 0);
+        for (int q = threadIdx.x; q < F2; q += blockDim.x) {
+          int n = (int)sqrtf((float)q);
+          while (n * n > q) --n;
+          while ((n + 1) * (n + 1) <= q) ++n;
+          const int m = q - n * n - n;
+          It[q] = cget(tv, n, m);
+        }
         __syncthreads();
         if (d < 4) {
           Cx<T> part{0, 0};
-          for (int n = 0; n <= P; ++n)
-            for (int m = -n; m <= n; ++m) cfma(part, cget(Ms[d], n, m), cget(It, n + kk, m + ll));
+          const Cx<T>* md = Ms[d];
+          for (int n = 0; n <= P; ++n) {
+            const int bm = n * n + n, nk = n + kk;
+            const int bi = nk * nk + nk + ll;
+            for (int m = -n; m <= n; ++m) cfma(part, md[bm + m], It[bi + m]);
+          }
           if (kk & 1) {
             acc.re -= part.re;
             acc.im -= part.im;
@@ -428,152 +456,144 @@ __global__ void __launch_bounds__(1024) k_fmm_m2l(int P, int nl, double w, const
   if (d < 4) Llev[((size_t)b * 4 + d) * Kc + c] = acc;
 }
 
-constexpr int kEvalThreads = 256;
-constexpr int kEvalTile = 512;
+// Work items of the leaf kernel: (leaf, first target) for every 64 targets of a leaf.
+__global__ void k_fmm_task_count(int nbox, const int* __restrict__ cnt, int* __restrict__ tcnt) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b < nbox) tcnt[b] = (cnt[b] + 63) / 64;
+}
 
-// Leaf evaluation: far field from the leaf's local expansions, plus the direct traction
-// sum over the points of the 27 adjacent leaves that belong to other bodies.  Writes
-// -(3/4pi)-scaled traction sums to out[3][N] at the points' original indices.
+__global__ void k_fmm_task_fill(int nbox, const int* __restrict__ tcnt, const int* __restrict__ toff,
+                                int2* __restrict__ task) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= nbox) return;
+  for (int j = 0; j < tcnt[b]; ++j) task[toff[b] + j] = make_int2(b, 64 * j);
+}
+
+// Sources in leaf order: srt[p] = src[perm[p]] with the body index in v[6].
 template <typename T>
-__global__ void __launch_bounds__(kEvalThreads) k_fmm_eval(int P, int nb, double lox, double loy, double loz,
-                                                           double w, int N, const int* __restrict__ start,
-                                                           const int* __restrict__ perm,
-                                                           const double4* __restrict__ Xs,
-                                                           const double4* __restrict__ Ns,
-                                                           const Src8<T>* __restrict__ src,
-                                                           const Cx<T>* __restrict__ Lleaf, int far_on,
-                                                           double* __restrict__ out) {
-  __shared__ Cx<T> Lb[4][kFmmKc];
-  __shared__ T sx[kEvalTile], sy[kEvalTile], sz[kEvalTile], qx[kEvalTile], qy[kEvalTile], qz[kEvalTile];
-  __shared__ int sbody[kEvalTile];
-  const int b = blockIdx.x;
+__global__ void k_fmm_pack_sorted(int N, const int* __restrict__ perm, const double4* __restrict__ Xs,
+                                  const Src8<T>* __restrict__ src, Src8<T>* __restrict__ srt) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= N) return;
+  Src8<T> s = src[perm[p]];
+  s.v[6] = (T)Xs[p].w;
+  s.v[7] = 0;
+  srt[p] = s;
+}
+
+// Leaf evaluation, one wave per work item (64 targets of one leaf, one per lane): far field
+// from the leaf's local expansions, plus the direct traction sum over the points of the 27
+// adjacent leaves that belong to other bodies.  The leaf is wave-uniform, so its expansion
+// coefficients and the sources (9 contiguous ranges of the leaf-ordered points) are read
+// with scalar loads.  Writes -(3/4pi)-scaled sums to out[3][N] at the original indices.
+template <typename T>
+__global__ void __launch_bounds__(256) k_fmm_leaf(int P, int nb, double lox, double loy, double loz, double w,
+                                                  int N, int ntask, const int2* __restrict__ task,
+                                                  const int* __restrict__ start, const int* __restrict__ perm,
+                                                  const double4* __restrict__ Xs, const double4* __restrict__ Ns,
+                                                  const Src8<T>* __restrict__ srt, const Cx<T>* __restrict__ Lleaf,
+                                                  int far_on, double* __restrict__ out) {
+  const int wv = __builtin_amdgcn_readfirstlane(blockIdx.x * 4 + (threadIdx.x >> 6));
+  if (wv >= ntask) return;
+  const int lane = threadIdx.x & 63;
+  const int2 tk = task[wv];
+  const int b = __builtin_amdgcn_readfirstlane(tk.x), t0 = __builtin_amdgcn_readfirstlane(tk.y);
   const int s0 = start[b], nt = start[b + 1] - s0;
-  if (nt == 0) return;
+  const int t = t0 + lane;
+  const bool live = t < nt;
   const int Kc = tri(P + 1, 0);
   const int i = b % nb, j = (b / nb) % nb, k = b / (nb * nb);
   const double cx = lox + (i + 0.5) * w, cy = loy + (j + 0.5) * w, cz = loz + (k + 0.5) * w;
-  if (far_on)
-    for (int q = threadIdx.x; q < 4 * Kc; q += blockDim.x) Lb[q / Kc][q % Kc] = Lleaf[(size_t)b * 4 * Kc + q];
-  __syncthreads();
-  for (int tb = 0; tb < nt; tb += kEvalThreads) {
-    const int t = tb + threadIdx.x;
-    const bool live = t < nt;
-    double4 xt = make_double4(0, 0, 0, -1), nn = make_double4(0, 0, 0, 0);
-    if (live) {
-      xt = Xs[s0 + t];
-      nn = Ns[s0 + t];
-    }
-    const T xa = (T)xt.x, ya = (T)xt.y, za = (T)xt.z, nx = (T)nn.x, ny = (T)nn.y, nz = (T)nn.z;
-    const int bt = (int)xt.w;
-    T fx = 0, fy = 0, fz = 0;
-    if (live && far_on) {
-      // local expansions: gradient sums (d/dx + i d/dy) phi_0, phi_1 and d/dz phi_2, and for all
-      // four densities A = (d/dx + i d/dy)^2, B = d/dz (d/dx + i d/dy), C = d^2/dz^2
-      const T ssx = (T)(xt.x - cx), ssy = (T)(xt.y - cy), ssz = (T)(xt.z - cz);
-      const T r2 = ssx * ssx + ssy * ssy + ssz * ssz;
-      Cx<T> g0{0, 0}, g1{0, 0}, g2{0, 0}, A[4], B[4], C[4];
-      for (int dd = 0; dd < 4; ++dd) A[dd] = B[dd] = C[dd] = Cx<T>{0, 0};
-      // one term: value v = conj(R_kk^l(s)) at order (kk, l), l of either sign
-      auto term = [&](int kk, int l, Cx<T> v) {
-        if (kk <= P - 1) {
-          cfma(g0, cget(Lb[0], kk + 1, l + 1), v);
-          cfma(g1, cget(Lb[1], kk + 1, l + 1), v);
-          cfma(g2, cget(Lb[2], kk + 1, l), v);
-        }
-        if (kk <= P - 2)
-          for (int dd = 0; dd < 4; ++dd) {
-            cfma(A[dd], cget(Lb[dd], kk + 2, l + 2), v);
-            cfma(B[dd], cget(Lb[dd], kk + 2, l + 1), v);
-            cfma(C[dd], cget(Lb[dd], kk + 2, l), v);
-          }
-      };
-      // R_kk^l(s) column by column (m = l >= 0); conj(R^l) for +l and (-1)^l R^l for -l
-      T dre = 1, dim = 0;
-      for (int l = 0; l <= P - 1; ++l) {
-        if (l > 0) {
-          const T inv = T(1) / T(2 * l);
-          const T nre = (dre * ssx - dim * ssy) * inv, nim = (dre * ssy + dim * ssx) * inv;
-          dre = nre;
-          dim = nim;
-        }
-        T are = 0, aim = 0, bre = dre, bim = dim;
-        for (int kk = l; kk <= P - 1; ++kk) {
-          if (kk > l) {
-            T vre, vim;
-            if (kk == l + 1) {
-              vre = ssz * bre;
-              vim = ssz * bim;
-            } else {
-              const T c1 = T(2 * kk - 1), inv = T(1) / T((kk - l) * (kk + l));
-              vre = (c1 * ssz * bre - r2 * are) * inv;
-              vim = (c1 * ssz * bim - r2 * aim) * inv;
-            }
-            are = bre; aim = bim;
-            bre = vre; bim = vim;
-          }
-          term(kk, l, Cx<T>{bre, -bim});
-          if (l > 0) term(kk, -l, (l & 1) ? Cx<T>{-bre, -bim} : Cx<T>{bre, bim});
-        }
+  const double4 xt = Xs[s0 + (live ? t : 0)], nn = Ns[s0 + (live ? t : 0)];
+  const T xa = (T)xt.x, ya = (T)xt.y, za = (T)xt.z, nx = (T)nn.x, ny = (T)nn.y, nz = (T)nn.z;
+  const T bt = (T)xt.w;
+  T fx = 0, fy = 0, fz = 0;
+  if (far_on) {
+    const Cx<T>* Lb = Lleaf + (size_t)b * 4 * Kc;
+    const T ssx = (T)(xt.x - cx), ssy = (T)(xt.y - cy), ssz = (T)(xt.z - cz);
+    const T r2 = ssx * ssx + ssy * ssy + ssz * ssz;
+    // gradient sums (d/dx + i d/dy) phi_0, phi_1 and d/dz phi_2; for all four densities
+    // A = (d/dx + i d/dy)^2, B = d/dz (d/dx + i d/dy), C = d^2/dz^2
+    Cx<T> g0{0, 0}, g1{0, 0}, g2{0, 0}, A[4], B[4], C[4];
+    for (int dd = 0; dd < 4; ++dd) A[dd] = B[dd] = C[dd] = Cx<T>{0, 0};
+    auto term = [&](int kk, int l, Cx<T> v) {
+      if (kk <= P - 1) {
+        cfma(g0, cget(Lb, kk + 1, l + 1), v);
+        cfma(g1, cget(Lb + Kc, kk + 1, l + 1), v);
+        cfma(g2, cget(Lb + 2 * Kc, kk + 1, l), v);
       }
-      const T div = g0.re + g1.im + g2.re;
-      T H[4][6];  // xx, yy, zz, xy, xz, yz
-      for (int dd = 0; dd < 4; ++dd) {
-        H[dd][0] = T(0.5) * (A[dd].re - C[dd].re);
-        H[dd][1] = T(0.5) * (-A[dd].re - C[dd].re);
-        H[dd][2] = C[dd].re;
-        H[dd][3] = T(0.5) * A[dd].im;
-        H[dd][4] = B[dd].re;
-        H[dd][5] = B[dd].im;
-      }
-      T Hs[6];
-      for (int e = 0; e < 6; ++e) Hs[e] = H[3][e] - ssx * H[0][e] - ssy * H[1][e] - ssz * H[2][e];
-      // the direct sum is kept in units of -(3/4pi): scale the far part by -(1/3)
-      const T sc = T(-1.0 / 3.0);
-      fx = sc * (div * nx + Hs[0] * nx + Hs[3] * ny + Hs[4] * nz);
-      fy = sc * (div * ny + Hs[3] * nx + Hs[1] * ny + Hs[5] * nz);
-      fz = sc * (div * nz + Hs[4] * nx + Hs[5] * ny + Hs[2] * nz);
-    }
-    // near field over the adjacent leaves, other bodies only
-    for (int nk = max(0, k - 1); nk <= min(nb - 1, k + 1); ++nk)
-      for (int nj = max(0, j - 1); nj <= min(nb - 1, j + 1); ++nj)
-        for (int ni = max(0, i - 1); ni <= min(nb - 1, i + 1); ++ni) {
-          const int sbx = (nk * nb + nj) * nb + ni;
-          const int a0 = start[sbx], a1 = start[sbx + 1];
-          for (int base = a0; base < a1; base += kEvalTile) {
-            const int cntt = min(kEvalTile, a1 - base);
-            __syncthreads();
-            for (int q = threadIdx.x; q < cntt; q += blockDim.x) {
-              const Src8<T> s = src[perm[base + q]];
-              sx[q] = s.v[0];
-              sy[q] = s.v[1];
-              sz[q] = s.v[2];
-              qx[q] = s.v[3];
-              qy[q] = s.v[4];
-              qz[q] = s.v[5];
-              sbody[q] = (int)Xs[base + q].w;
-            }
-            __syncthreads();
-            if (live)
-              for (int q = 0; q < cntt; ++q) {
-                const T dx = xa - sx[q], dy = ya - sy[q], dz = za - sz[q];
-                const bool same = sbody[q] == bt;
-                const T r2 = same ? T(1) : dx * dx + dy * dy + dz * dz;
-                const T dn = dx * nx + dy * ny + dz * nz;
-                const T dq = dx * qx[q] + dy * qy[q] + dz * qz[q];
-                const T f = same ? T(0) : (dn * dq) * rinv5_t(r2);
-                fx += f * dx;
-                fy += f * dy;
-                fz += f * dz;
-              }
-          }
+      if (kk <= P - 2)
+        for (int dd = 0; dd < 4; ++dd) {
+          cfma(A[dd], cget(Lb + dd * Kc, kk + 2, l + 2), v);
+          cfma(B[dd], cget(Lb + dd * Kc, kk + 2, l + 1), v);
+          cfma(C[dd], cget(Lb + dd * Kc, kk + 2, l), v);
         }
-    if (live) {
-      const int g = perm[s0 + t];
-      const double sc = -3.0 / (4.0 * RBM_PI);
-      out[g] = sc * (double)fx;
-      out[(size_t)N + g] = sc * (double)fy;
-      out[2 * (size_t)N + g] = sc * (double)fz;
+    };
+    // R_kk^l(s) column by column (l >= 0): conj(R^l) for +l and (-1)^l R^l for -l
+    T dre = 1, dim = 0;
+    for (int l = 0; l <= P - 1; ++l) {
+      if (l > 0) {
+        const T inv = T(1) / T(2 * l);
+        const T nre = (dre * ssx - dim * ssy) * inv, nim = (dre * ssy + dim * ssx) * inv;
+        dre = nre;
+        dim = nim;
+      }
+      T are = 0, aim = 0, bre = dre, bim = dim;
+      for (int kk = l; kk <= P - 1; ++kk) {
+        if (kk > l) {
+          const T c1 = T(2 * kk - 1), inv = T(1) / T((kk - l) * (kk + l));
+          const T vre = (c1 * ssz * bre - r2 * are) * inv, vim = (c1 * ssz * bim - r2 * aim) * inv;
+          are = bre; aim = bim;
+          bre = vre; bim = vim;
+        }
+        term(kk, l, Cx<T>{bre, -bim});
+        if (l > 0) term(kk, -l, (l & 1) ? Cx<T>{-bre, -bim} : Cx<T>{bre, bim});
+      }
     }
+    const T div = g0.re + g1.im + g2.re;
+    T H[4][6];  // xx, yy, zz, xy, xz, yz
+    for (int dd = 0; dd < 4; ++dd) {
+      H[dd][0] = T(0.5) * (A[dd].re - C[dd].re);
+      H[dd][1] = T(0.5) * (-A[dd].re - C[dd].re);
+      H[dd][2] = C[dd].re;
+      H[dd][3] = T(0.5) * A[dd].im;
+      H[dd][4] = B[dd].re;
+      H[dd][5] = B[dd].im;
+    }
+    T Hs[6];
+    for (int e = 0; e < 6; ++e) Hs[e] = H[3][e] - ssx * H[0][e] - ssy * H[1][e] - ssz * H[2][e];
+    // the direct sum is kept in units of -(3/4pi): scale the far part by -(1/3)
+    const T sc = T(-1.0 / 3.0);
+    fx = sc * (div * nx + Hs[0] * nx + Hs[3] * ny + Hs[4] * nz);
+    fy = sc * (div * ny + Hs[3] * nx + Hs[1] * ny + Hs[5] * nz);
+    fz = sc * (div * nz + Hs[4] * nx + Hs[5] * ny + Hs[2] * nz);
+  }
+  // near field: for each (nk, nj) the leaves ni - 1 .. ni + 1 are consecutive in leaf order
+  const int i0 = max(0, i - 1), i1 = min(nb - 1, i + 1);
+  for (int nk = max(0, k - 1); nk <= min(nb - 1, k + 1); ++nk)
+    for (int nj = max(0, j - 1); nj <= min(nb - 1, j + 1); ++nj) {
+      const int row = (nk * nb + nj) * nb;
+      const int a0 = __builtin_amdgcn_readfirstlane(start[row + i0]);
+      const int a1 = __builtin_amdgcn_readfirstlane(start[row + i1 + 1]);
+      for (int q = a0; q < a1; ++q) {
+        const Src8<T> s = srt[q];
+        const T dx = xa - s.v[0], dy = ya - s.v[1], dz = za - s.v[2];
+        const bool same = s.v[6] == bt;
+        const T r2 = same ? T(1) : dx * dx + dy * dy + dz * dz;
+        const T dn = dx * nx + dy * ny + dz * nz;
+        const T dq = dx * s.v[3] + dy * s.v[4] + dz * s.v[5];
+        const T f = same ? T(0) : (dn * dq) * rinv5_t(r2);
+        fx += f * dx;
+        fy += f * dy;
+        fz += f * dz;
+      }
+    }
+  if (live) {
+    const int g = perm[s0 + t];
+    const double sc = -3.0 / (4.0 * RBM_PI);
+    out[g] = sc * (double)fx;
+    out[(size_t)N + g] = sc * (double)fy;
+    out[2 * (size_t)N + g] = sc * (double)fz;
   }
 }
 
@@ -599,14 +619,18 @@ hipError_t launch_fmm_sort_points(int N, int M, const double* X, const double* N
 }
 
 hipError_t launch_fmm_finish_tree(int N, int M, int L, const double* X, const double* Nn, const int* start,
-                                  int* perm, double4* Xs, double4* Ns, int* const* cnt_lev, hipStream_t st) {
-  const int nb = 1 << L;
-  k_fmm_sort<<<nb * nb * nb, 256, 0, st>>>(start, perm);
+                                  int* perm, double4* Xs, double4* Ns, int* const* cnt_lev, int* tcnt, int* toff,
+                                  int2* task, int* scratch, hipStream_t st) {
+  const int nb = 1 << L, nbox = nb * nb * nb;
+  k_fmm_sort<<<nbox, 256, 0, st>>>(start, perm);
   k_fmm_gather<<<(N + 255) / 256, 256, 0, st>>>(N, M, perm, X, Nn, Xs, Ns);
   for (int lev = L - 1; lev >= 2; --lev) {
     const int np = 1 << lev;
     k_fmm_level_count<<<(np * np * np + 255) / 256, 256, 0, st>>>(np, cnt_lev[lev + 1], cnt_lev[lev]);
   }
+  k_fmm_task_count<<<(nbox + 255) / 256, 256, 0, st>>>(nbox, cnt_lev[L], tcnt);
+  k_fmm_scan<<<1, 1024, 0, st>>>(nbox, tcnt, toff, scratch);
+  k_fmm_task_fill<<<(nbox + 255) / 256, 256, 0, st>>>(nbox, tcnt, toff, task);
   return hipGetLastError();
 }
 
@@ -629,20 +653,21 @@ hipError_t launch_fmm_tables(int P, int L, double D, void* tabR, void* tabI, hip
 template <typename T>
 hipError_t launch_fmm_apply(int P, int L, const double* lo, double D, int N, const int* start, const int* perm,
                             const double4* Xs, const double4* Ns, int* const* cnt_lev, const size_t* lev_off,
-                            const void* tabR, const void* tabI, const void* src, void* Mexp, void* Lexp,
-                            double* out, hipStream_t st) {
+                            int ntask, const int2* task, const void* tabR, const void* tabI, const void* src,
+                            void* srt, void* Mexp, void* Lexp, double* out, hipStream_t st) {
   if (P < 2 || P > kFmmPMax || L < 0) return hipErrorInvalidValue;
   const int nb = 1 << L, Kc = tri(P + 1, 0), Kc2 = tri(2 * P + 1, 0);
   const double w = ldexp(D, -L);
-  const Src8<T>* s = static_cast<const Src8<T>*>(src);
+  Src8<T>* so = static_cast<Src8<T>*>(srt);
   Cx<T>* Mx = static_cast<Cx<T>*>(Mexp);
   Cx<T>* Lx = static_cast<Cx<T>*>(Lexp);
   const Cx<T>* tR = static_cast<const Cx<T>*>(tabR);
   const Cx<T>* tI = static_cast<const Cx<T>*>(tabI);
   const int th = fmm_threads(P);
   const bool far_on = L >= 2;
+  k_fmm_pack_sorted<T><<<(N + 255) / 256, 256, 0, st>>>(N, perm, Xs, static_cast<const Src8<T>*>(src), so);
   if (far_on) {
-    k_fmm_p2m<T><<<nb * nb * nb, th, 0, st>>>(P, nb, lo[0], lo[1], lo[2], w, start, perm, Xs, s,
+    k_fmm_p2m<T><<<nb * nb * nb, th, 0, st>>>(P, nb, lo[0], lo[1], lo[2], w, start, perm, Xs, so,
                                               Mx + lev_off[L] * 4 * Kc);
     for (int lev = L; lev > 2; --lev) {
       const int nc = 1 << lev, np = nc / 2;
@@ -660,21 +685,22 @@ hipError_t launch_fmm_apply(int P, int L, const double* lo, double D, int N, con
                                                 Lx + lev_off[lev] * 4 * Kc);
     }
   }
-  k_fmm_eval<T><<<nb * nb * nb, kEvalThreads, 0, st>>>(P, nb, lo[0], lo[1], lo[2], w, N, start, perm, Xs, Ns, s,
-                                                       far_on ? Lx + lev_off[L] * 4 * Kc : nullptr,
-                                                       far_on ? 1 : 0, out);
+  if (ntask > 0)
+    k_fmm_leaf<T><<<(ntask + 3) / 4, 256, 0, st>>>(P, nb, lo[0], lo[1], lo[2], w, N, ntask, task, start, perm, Xs,
+                                                   Ns, so, far_on ? Lx + lev_off[L] * 4 * Kc : nullptr,
+                                                   far_on ? 1 : 0, out);
   return hipGetLastError();
 }
 
 template hipError_t launch_fmm_tables<double>(int, int, double, void*, void*, hipStream_t);
 template hipError_t launch_fmm_tables<float>(int, int, double, void*, void*, hipStream_t);
 template hipError_t launch_fmm_apply<double>(int, int, const double*, double, int, const int*, const int*,
-                                             const double4*, const double4*, int* const*, const size_t*,
-                                             const void*, const void*, const void*, void*, void*, double*,
-                                             hipStream_t);
+                                             const double4*, const double4*, int* const*, const size_t*, int,
+                                             const int2*, const void*, const void*, const void*, void*, void*,
+                                             void*, double*, hipStream_t);
 template hipError_t launch_fmm_apply<float>(int, int, const double*, double, int, const int*, const int*,
-                                            const double4*, const double4*, int* const*, const size_t*,
-                                            const void*, const void*, const void*, void*, void*, double*,
-                                            hipStream_t);
+                                            const double4*, const double4*, int* const*, const size_t*, int,
+                                            const int2*, const void*, const void*, const void*, void*, void*,
+                                            void*, double*, hipStream_t);
 
 }  // namespace rbm

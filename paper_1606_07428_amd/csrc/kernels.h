@@ -188,14 +188,15 @@ hipError_t launch_fmm_sort_points(int N, int M, const double* X, const double* N
                                   int nb, int* leaf, int* cnt, int* start, int* fill, int* perm, int* maxcnt,
                                   double4* Xs, double4* Ns, hipStream_t st);
 hipError_t launch_fmm_finish_tree(int N, int M, int L, const double* X, const double* Nn, const int* start,
-                                  int* perm, double4* Xs, double4* Ns, int* const* cnt_lev, hipStream_t st);
+                                  int* perm, double4* Xs, double4* Ns, int* const* cnt_lev, int* tcnt, int* toff,
+                                  int2* task, int* scratch, hipStream_t st);
 template <typename T>
 hipError_t launch_fmm_tables(int P, int L, double D, void* tabR, void* tabI, hipStream_t st);
 template <typename T>
 hipError_t launch_fmm_apply(int P, int L, const double* lo, double D, int N, const int* start, const int* perm,
                             const double4* Xs, const double4* Ns, int* const* cnt_lev, const size_t* lev_off,
-                            const void* tabR, const void* tabI, const void* src, void* Mexp, void* Lexp,
-                            double* out, hipStream_t st);
+                            int ntask, const int2* task, const void* tabR, const void* tabI, const void* src,
+                            void* srt, void* Mexp, void* Lexp, double* out, hipStream_t st);
 
 // ---- magnetostatics (k_magnetic.hip) -------------------------------------------------
 // Laplace self operators S^L, K^L per shape, column-major [ns][M][M] (singular rule)

@@ -96,7 +96,10 @@ struct rbm_ctx {
   // fast multipole far field (option fmm_order): tree over the current points, sorted
   // geometry, counts per box and level, translation tables and expansions
   int *fleaf = nullptr, *fperm = nullptr, *fstart = nullptr, *ffill = nullptr, *fcnt = nullptr,
-      *fmax = nullptr;
+      *fmax = nullptr, *ftcnt = nullptr, *ftoff = nullptr;
+  int2* ftask = nullptr;
+  double* fsrt = nullptr;
+  int fmm_ntask = 0;
   double4 *fXs = nullptr, *fNs = nullptr;
   double* fbounds = nullptr;
   void *ftabR = nullptr, *ftabI = nullptr, *fM = nullptr, *fL = nullptr;
@@ -353,6 +356,8 @@ static size_t layout(rbm_ctx* c, int nmax, bool assign) {
     take(c->fleaf, N); take(c->fperm, N); take(c->fstart, nleaf + 1); take(c->ffill, nleaf);
     take(c->fcnt, std::max(btot, nleaf)); take(c->fmax, 64);
     take(c->fXs, N); take(c->fNs, N); take(c->fbounds, 64);
+    take(c->ftcnt, nleaf); take(c->ftoff, nleaf + 1); take(c->ftask, N / 64 + nleaf + 1);
+    take(c->fsrt, 8 * (size_t)N);
     double *tr = nullptr, *ti = nullptr, *me = nullptr, *le = nullptr;
     take(tr, 2 * (size_t)(Lm - 1) * 8 * kc); take(ti, 2 * (size_t)(Lm - 1) * 343 * kc2);
     take(me, 2 * btot * 4 * kc); take(le, 2 * btot * 4 * kc);
@@ -646,7 +651,11 @@ static rbm_status fmm_build(rbm_ctx* c, int npts, int M, const double* X, const 
   HIPCHECK(hipStreamSynchronize(st));
   std::memcpy(&maxcnt, c->pinned, sizeof(int));
   if (maxcnt > kFmmLeafCap) return RBM_OK;
-  HIPCHECK(launch_fmm_finish_tree(npts, M, L, X, Nn, c->fstart, c->fperm, c->fXs, c->fNs, c->fmm_cnt, st));
+  HIPCHECK(launch_fmm_finish_tree(npts, M, L, X, Nn, c->fstart, c->fperm, c->fXs, c->fNs, c->fmm_cnt, c->ftcnt,
+                                   c->ftoff, c->ftask, c->fmax + 1, st));
+  HIPCHECK(hipMemcpyAsync(c->pinned, c->ftoff + ((size_t)1 << (3 * L)), sizeof(int), hipMemcpyDeviceToHost, st));
+  HIPCHECK(hipStreamSynchronize(st));
+  std::memcpy(&c->fmm_ntask, c->pinned, sizeof(int));
   c->fmm_npts = npts;
   c->fmm_ready = true;
   return RBM_OK;
@@ -666,13 +675,13 @@ static rbm_status fmm_apply(rbm_ctx* c, int prec, double* out) {
   if (prec == 0) {
     if (L >= 2) HIPCHECK(launch_fmm_tables<double>(P, L, c->fmm_D, c->ftabR, c->ftabI, c->st));
     HIPCHECK(launch_fmm_apply<double>(P, L, c->fmm_lo, c->fmm_D, c->fmm_npts, c->fstart, c->fperm, c->fXs,
-                                      c->fNs, c->fmm_cnt, c->fmm_off, c->ftabR, c->ftabI, c->src, c->fM, c->fL,
-                                      out, c->st));
+                                      c->fNs, c->fmm_cnt, c->fmm_off, c->fmm_ntask, c->ftask, c->ftabR, c->ftabI,
+                                      c->src, c->fsrt, c->fM, c->fL, out, c->st));
   } else {
     if (L >= 2) HIPCHECK(launch_fmm_tables<float>(P, L, c->fmm_D, c->ftabR, c->ftabI, c->st));
     HIPCHECK(launch_fmm_apply<float>(P, L, c->fmm_lo, c->fmm_D, c->fmm_npts, c->fstart, c->fperm, c->fXs,
-                                     c->fNs, c->fmm_cnt, c->fmm_off, c->ftabR, c->ftabI, c->src, c->fM, c->fL,
-                                     out, c->st));
+                                     c->fNs, c->fmm_cnt, c->fmm_off, c->fmm_ntask, c->ftask, c->ftabR, c->ftabI,
+                                     c->src, c->fsrt, c->fM, c->fL, out, c->st));
   }
   return RBM_OK;
 }
