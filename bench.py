@@ -306,26 +306,29 @@ def main_compare(args):
         torch.cuda.empty_cache()
         _log(f"trained on {args.learned_from}: {learned}")
     pu = args.p_up
-    forms = [("fp64", rbm.FP64, False, pu, 0), ("mixed_fp32", rbm.MIXED_FP32, False, pu, 0),
-             ("mixed_bf16", rbm.MIXED_BF16, False, pu, 0)]
+    bd, zero = rbm.GUESS_BLOCKDIAG, rbm.GUESS_ZERO
+    forms = [("fp64", rbm.FP64, False, pu, 0, bd), ("mixed_fp32", rbm.MIXED_FP32, False, pu, 0, bd),
+             ("mixed_bf16", rbm.MIXED_BF16, False, pu, 0, bd)]
     if params is not None:
-        forms.append(("mixed_fp32_learned", rbm.MIXED_FP32, True, pu, 0))
+        forms.append(("mixed_fp32_learned", rbm.MIXED_FP32, True, pu, 0, bd))
     if args.fmm:
-        forms += [("mixed_fp32_fmm", rbm.MIXED_FP32, False, pu, args.fmm),
-                  ("mixed_bf16_fmm", rbm.MIXED_BF16, False, pu, args.fmm)]
+        # with cheap inner iterations the zero initial guess saves the first float64 residual
+        forms += [("mixed_fp32_fmm", rbm.MIXED_FP32, False, pu, args.fmm, bd),
+                  ("mixed_fp32_fmm_zero", rbm.MIXED_FP32, False, pu, args.fmm, zero),
+                  ("mixed_bf16_fmm", rbm.MIXED_BF16, False, pu, args.fmm, bd)]
         out["fmm_order"] = args.fmm
     if args.forms:
         keep = set(args.forms.split(","))
         forms = [f for f in forms if f[0] in keep]
     if pu:
         # the plain smooth rule first: the upsampled float64 solve is then the reference
-        forms.insert(0, ("fp64_plain", rbm.FP64, False, 0, 0))
+        forms.insert(0, ("fp64_plain", rbm.FP64, False, 0, 0, bd))
         out["p_up"], out["near_factor"] = pu, args.near_factor
     ref = None
     plain = None
-    for name, prec, use_net, form_pu, fmm_order in forms:
+    for name, prec, use_net, form_pu, fmm_order, guess in forms:
         t0 = time.perf_counter()
-        s = rbm.solver_for(w, tol=args.tol, precision=prec, guess=rbm.GUESS_BLOCKDIAG, p_up=form_pu,
+        s = rbm.solver_for(w, tol=args.tol, precision=prec, guess=guess, p_up=form_pu,
                            near_factor=args.near_factor, fmm_order=fmm_order)
         if use_net:
             s.learned_bind(k_nbr=8, hidden=256, n_hidden=3, capacity=1, batch_max=1024, seed=7)

@@ -100,3 +100,18 @@ def test_fmm_off_for_float64_and_small_trees():
     assert info2["fmm_level"] < 2
     assert rel_err(VW2, sy.solve_dense(oracle_problem(w2), w2["FT"])[2]) < 1e-8
     s2.close()
+
+
+def test_fmm_inner_iterations_with_near_singular_upsampling():
+    """The near-correction slot follows the FMM's single partial-sum slot."""
+    _case("mixed + fmm + upsampling (p_up 8, kappa 7) vs float64 + upsampling: lattice 32 bodies p=4")
+    w = inputs.lattice(32, 4)
+    ref = rbm.solver_for(w, tol=1e-11, precision=rbm.FP64, p_up=8, near_factor=7.0)
+    VW_ref, info_ref = ref.solve(w["FT"])
+    assert info_ref["near_pairs"] > 0
+    ref.close()
+    s = rbm.solver_for(w, tol=1e-11, precision=rbm.MIXED_FP32, fmm_order=8, p_up=8, near_factor=7.0)
+    VW, info = s.solve(w["FT"])
+    assert info["fmm_applies"] > 0 and info["near_pairs"] == info_ref["near_pairs"]
+    assert rel_err(VW, VW_ref) < 1e-9
+    s.close()
