@@ -348,6 +348,8 @@ def main_compare(args):
             "setup_s": setup, "solve_ms": dt / args.steps * 1e3, "iters": i["iters"],
             "matvecs": i["matvecs"], "refinements": i["refinements"], "rel_residual": i["rel_residual"],
             "traction_launch_ms_avg": i["ms_traction"] / max(i["n_traction"], 1),
+            "traction32_ms_avg": i["ms_traction32"] / max(i["n_traction32"], 1),
+            "n_traction64": i["n_traction"], "n_traction32": i["n_traction32"],
             "stokeslet_ms": i["ms_stokeslet"], "self_ms": i["ms_self"],
             "pairs_per_launch": i["pairs_per_launch"],
             "velocity_rel_err_vs_fp64": float(np.abs(v - ref).max() / np.abs(ref).max()) if ref is not None else 0.0,

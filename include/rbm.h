@@ -114,9 +114,9 @@ typedef struct {
   double ms_far;      /* time in the all-pairs sums (ms, event-timed) */
   double ms_self;     /* time in the per-body operator applies (ms) */
   double far_pairs;   /* off-body pair interactions evaluated (all sums) */
-  int n_traction;     /* launches of the float64/float32 traction sum kernel */
+  int n_traction;     /* launches of the float64 traction sum kernel */
   int n_stokeslet;    /* launches of the Stokeslet sum kernel */
-  double ms_traction; /* summed duration of the traction kernel launches (ms) */
+  double ms_traction; /* summed duration of the float64 traction kernel launches (ms) */
   double ms_stokeslet;/* summed duration of the Stokeslet kernel launches (ms) */
   double pairs_per_launch; /* off-body pairs of one launch: N^2 - n M^2 */
   int guess_used;     /* rbm_guess actually used for mu_0 */
@@ -126,6 +126,8 @@ typedef struct {
   double ms_near;     /* device time of the near-singular corrections (interpolation, sums) */
   int fmm_level;      /* leaf level of the fast multipole tree of this solve (-1: not used) */
   int fmm_applies;    /* far sums evaluated by the fast multipole method */
+  int n_traction32;   /* float32 traction sums (direct kernel or fast multipole method) */
+  double ms_traction32; /* their summed duration (ms) */
 } rbm_solve_info;
 
 /* Default options: p = 8, p_sing = 0, eta = 1, tol = 1e-12, max_iter = 100,

@@ -572,7 +572,9 @@ struct Timer {
 };
 
 struct SolveState {
-  std::vector<std::pair<int, int>> trac_ev, stok_ev, self_ev, near_ev;  // event index pairs
+  // event index pairs: float64 traction sums, float32 (direct or fast multipole) traction
+  // sums, Stokeslet sums, self applies, near corrections
+  std::vector<std::pair<int, int>> trac_ev, trac32_ev, stok_ev, self_ev, near_ev;
   double far_pairs = 0.0;
   int matvecs = 0;
   int fmm_applies = 0;
@@ -700,7 +702,7 @@ static rbm_status far_traction(rbm_ctx* c, SolveState& S, const double* x, int x
     rbm_status s = fmm_apply(c, 1, c->part);
     if (s != RBM_OK) return s;
     t.stop();
-    if (t.on) S.trac_ev.push_back({c->ev_used - 2, c->ev_used - 1});
+    if (t.on) S.trac32_ev.push_back({c->ev_used - 2, c->ev_used - 1});
     c->far_base = 1;
     c->far_nslots = 1 + (c->pu ? 1 : 0);
     S.fmm_applies++;
@@ -719,7 +721,7 @@ static rbm_status far_traction(rbm_ctx* c, SolveState& S, const double* x, int x
     Timer t(c);
     HIPCHECK(launch_far<float>(0, N, c->M, c->Xf, c->Nf, c->src, c->part, nsp, c->st));
     t.stop();
-    if (t.on) S.trac_ev.push_back({c->ev_used - 2, c->ev_used - 1});
+    if (t.on) S.trac32_ev.push_back({c->ev_used - 2, c->ev_used - 1});
   }
   S.far_pairs += (double)N * N - (double)c->n * c->M * c->M;
   return near_correction(c, S, 0, x, x_is_body, prec == 0 ? 0 : 1);
@@ -844,8 +846,11 @@ static rbm_status learned_correction(rbm_ctx* c, const double* dFT);
 static rbm_status learned_capture(rbm_ctx* c, const double* dFT);
 
 // Incident density (§2.2) and right-hand side b = -(A_self rho - L rho + K_far rho).
+// exact = false evaluates K_far rho in the cheaper precision (float32 direct sum, or the
+// fast multipole method when a tree is built): b then serves only the block-diagonal guess
+// and the scale ||b|| of the stopping test, while residuals come from residual_exact().
 static rbm_status build_rhs(rbm_ctx* c, SolveState& S, const double* dFT, const double* d_rho,
-                            double* bnorm) {
+                            double* bnorm, bool exact = true) {
   hipStream_t st = c->st;
   const int n = c->n, M = c->M, N = n * M;
   rbm_status s;
@@ -854,7 +859,7 @@ static rbm_status build_rhs(rbm_ctx* c, SolveState& S, const double* dFT, const 
   else
     HIPCHECK(launch_rho(n, M, dFT, c->cen, c->X, c->tauinv, c->area_b, c->rho, st));
   if ((s = self_apply(c, S, 0, 0, c->rho, c->yb)) != RBM_OK) return s;
-  if ((s = far_traction(c, S, c->rho, 0, 0)) != RBM_OK) return s;
+  if ((s = far_traction(c, S, c->rho, 0, exact ? 0 : 1)) != RBM_OK) return s;
   HIPCHECK(launch_combine(N, M, c->far_nslots, c->part, -1.0, nullptr, 0.0, c->yb, c->Rm, -1.0, c->b, st));
   HIPCHECK(launch_moments(n, M, c->rho, c->X, c->W, c->cen, c->mom, st));
   HIPCHECK(launch_add_rigid(n, M, c->mom, c->X, c->cen, 1.0, c->b, st));
@@ -862,6 +867,23 @@ static rbm_status build_rhs(rbm_ctx* c, SolveState& S, const double* dFT, const 
   if ((s = norm_into(c, c->b, c->scal + 1)) != RBM_OK) return s;
   if ((s = read_scalar(c, c->scal + 1, bnorm)) != RBM_OK) return s;
   if (!std::isfinite(*bnorm)) return fail(RBM_E_INVAL, "non-finite right-hand side");
+  return RBM_OK;
+}
+
+// Float64 residual r = b - A x without forming b: by linearity
+//   r = -(A_self (rho + x) - L rho) - K_far (rho + x),
+// one exact far sum of rho + x (tmp holds rho + x).
+static rbm_status residual_exact(rbm_ctx* c, SolveState& S, const double* x, double* r, double* tmp) {
+  const int n = c->n, M = c->M, N = n * M;
+  hipStream_t st = c->st;
+  rbm_status s;
+  HIPCHECK(launch_axpby(3 * (size_t)N, 1.0, c->rho, 1.0, x, tmp, st));
+  if ((s = self_apply(c, S, 0, 0, tmp, c->yb)) != RBM_OK) return s;
+  if ((s = far_traction(c, S, tmp, 0, 0)) != RBM_OK) return s;
+  HIPCHECK(launch_combine(N, M, c->far_nslots, c->part, -1.0, nullptr, 0.0, c->yb, c->Rm, -1.0, r, st));
+  HIPCHECK(launch_moments(n, M, c->rho, c->X, c->W, c->cen, c->mom, st));
+  HIPCHECK(launch_add_rigid(n, M, c->mom, c->X, c->cen, 1.0, r, st));
+  S.matvecs++;
   return RBM_OK;
 }
 
@@ -884,8 +906,12 @@ static rbm_status solve_impl(rbm_ctx* c, const double* dFT, double* dVW, rbm_sol
   } else {
     c->fmm_ready = false;
   }
+  // Precision form: b only seeds the guess and scales the tolerance (every residual is
+  // exact), so its far sum is the cheap one.  Float64 form, or a zero guess (the first
+  // residual is b itself): b is exact.
   double bnorm;
-  if ((s = build_rhs(c, S, dFT, d_rho, &bnorm)) != RBM_OK) return s;
+  const bool b_exact = c->opt.precision == RBM_FP64 || c->opt.guess == RBM_GUESS_ZERO;
+  if ((s = build_rhs(c, S, dFT, d_rho, &bnorm, b_exact)) != RBM_OK) return s;
   const double abs_tol = c->opt.tol * bnorm;
   const int prec = c->opt.precision;
   // initial guess
@@ -922,8 +948,7 @@ static rbm_status solve_impl(rbm_ctx* c, const double* dFT, double* dVW, rbm_sol
       rn = bnorm;
       mu_zero = false;
     } else {
-      if ((s = apply_A(c, S, c->mu, c->t1)) != RBM_OK) return s;
-      HIPCHECK(launch_axpby(len, 1.0, c->b, -1.0, c->t1, c->r, st));
+      if ((s = residual_exact(c, S, c->mu, c->r, c->t1)) != RBM_OK) return s;
       if ((s = norm_into(c, c->r, c->scal + 2)) != RBM_OK) return s;
       if ((s = read_scalar(c, c->scal + 2, &rn)) != RBM_OK) return s;
     }
@@ -931,8 +956,7 @@ static rbm_status solve_impl(rbm_ctx* c, const double* dFT, double* dVW, rbm_sol
       if (learned_active) {
         // fallback test against the block-diagonal guess's residual ratio
         if (c->bd_ratio < 0.0) {
-          if ((s = apply_A(c, S, c->t2, c->t1)) != RBM_OK) return s;
-          HIPCHECK(launch_axpby(len, 1.0, c->b, -1.0, c->t1, c->t1, st));
+          if ((s = residual_exact(c, S, c->t2, c->t1, c->V)) != RBM_OK) return s;  // V is free before GMRES
           double rbd;
           if ((s = norm_into(c, c->t1, c->scal + 3)) != RBM_OK) return s;
           if ((s = read_scalar(c, c->scal + 3, &rbd)) != RBM_OK) return s;
@@ -941,8 +965,7 @@ static rbm_status solve_impl(rbm_ctx* c, const double* dFT, double* dVW, rbm_sol
         if (!(rn <= c->bd_ratio * bnorm)) {
           fallback = 1;
           HIPCHECK(hipMemcpyAsync(c->mu, c->t2, len * sizeof(double), hipMemcpyDeviceToDevice, st));
-          if ((s = apply_A(c, S, c->mu, c->t1)) != RBM_OK) return s;
-          HIPCHECK(launch_axpby(len, 1.0, c->b, -1.0, c->t1, c->r, st));
+          if ((s = residual_exact(c, S, c->mu, c->r, c->t1)) != RBM_OK) return s;
           if ((s = norm_into(c, c->r, c->scal + 2)) != RBM_OK) return s;
           if ((s = read_scalar(c, c->scal + 2, &rn)) != RBM_OK) return s;
           c->bd_ratio = rn / bnorm;
@@ -997,6 +1020,7 @@ static rbm_status solve_impl(rbm_ctx* c, const double* dFT, double* dVW, rbm_sol
     info->bnorm = bnorm;
     info->far_pairs = S.far_pairs;
     info->n_traction = (int)S.trac_ev.size();
+    info->n_traction32 = (int)S.trac32_ev.size();
     info->n_stokeslet = (int)S.stok_ev.size();
     info->pairs_per_launch = (double)N * N - (double)n * M * M;
     info->near_pairs = c->pu ? c->near_pairs : 0;
@@ -1010,11 +1034,15 @@ static rbm_status solve_impl(rbm_ctx* c, const double* dFT, double* dVW, rbm_sol
         (void)hipEventElapsedTime(&ms, c->ev[e.first], c->ev[e.second]);
         info->ms_traction += ms;
       }
+      for (auto& e : S.trac32_ev) {
+        (void)hipEventElapsedTime(&ms, c->ev[e.first], c->ev[e.second]);
+        info->ms_traction32 += ms;
+      }
       for (auto& e : S.stok_ev) {
         (void)hipEventElapsedTime(&ms, c->ev[e.first], c->ev[e.second]);
         info->ms_stokeslet += ms;
       }
-      info->ms_far = info->ms_traction + info->ms_stokeslet;
+      info->ms_far = info->ms_traction + info->ms_traction32 + info->ms_stokeslet;
       for (auto& e : S.self_ev) {
         (void)hipEventElapsedTime(&ms, c->ev[e.first], c->ev[e.second]);
         info->ms_self += ms;

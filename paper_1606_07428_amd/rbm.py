@@ -50,7 +50,8 @@ class SolveInfo(ctypes.Structure):
                 ("guess_used", ctypes.c_int), ("fallback_used", ctypes.c_int),
                 ("init_rel_residual", ctypes.c_double), ("near_pairs", ctypes.c_int),
                 ("ms_near", ctypes.c_double), ("fmm_level", ctypes.c_int),
-                ("fmm_applies", ctypes.c_int)]
+                ("fmm_applies", ctypes.c_int), ("n_traction32", ctypes.c_int),
+                ("ms_traction32", ctypes.c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
