@@ -115,3 +115,36 @@ def test_fmm_inner_iterations_with_near_singular_upsampling():
     assert info["fmm_applies"] > 0 and info["near_pairs"] == info_ref["near_pairs"]
     assert rel_err(VW, VW_ref) < 1e-9
     s.close()
+
+
+@pytest.mark.parametrize("P,max_level", [(2, 5), (16, 5), (8, 2)])
+def test_fmm_order_and_level_limits(P, max_level):
+    """Smallest and largest orders; a level cap below the level the tree would choose."""
+    _case(f"fmm limits: P={P} max_level={max_level}")
+    side, npts = (4, 12) if max_level > 2 else (6, 12)
+    X, Nn, q, body = _cloud(side, 3.0, npts, 31 + P)
+    ref, (_, _, L) = fmm.traction(X, Nn, q, body, P, 2.0, L_max=max_level)
+    s = _ctx(side ** 3, 4, P, max_level=max_level)
+    y, lev = s.far_traction_fmm(_dev(X), _dev(Nn), _dev(q), npts, 2.0, precision=0)
+    assert lev == L and L == min(max_level, 2 if side == 4 else 3)
+    assert np.abs(y.cpu().numpy().T - ref).max() < 1e-12 * np.abs(ref).max()
+    s.close()
+
+
+def test_fmm_error_paths():
+    _case("fmm error paths: no order, bad d_max, too many points in one leaf")
+    X, Nn, q, _ = _cloud(5, 3.0, 40, 41)                      # 5000 points
+    Xd, Nd, qd = _dev(X), _dev(Nn), _dev(q)
+    s0 = rbm.solver_for(inputs.lattice(128, 4))
+    with pytest.raises(rbm.RbmError):
+        s0.far_traction_fmm(Xd, Nd, qd, 40, 2.0)               # context without fmm_order
+    s0.close()
+    s = _ctx(128, 4, 6)
+    with pytest.raises(rbm.RbmError):
+        s.far_traction_fmm(Xd, Nd, qd, 40, 0.0)
+    with pytest.raises(rbm.RbmError, match="4096"):
+        s.far_traction_fmm(Xd, Nd, qd, 40, 100.0)              # one leaf holds all 5000 points
+    # the context is still usable afterwards
+    y, lev = s.far_traction_fmm(Xd, Nd, qd, 40, 2.0)
+    assert lev == 2 and bool(torch.isfinite(y).all())
+    s.close()
