@@ -978,7 +978,13 @@ static rbm_status solve_impl(rbm_ctx* c, const double* dFT, double* dVW, rbm_sol
     rel = bnorm > 0.0 ? rn / bnorm : 0.0;
     if (rn <= abs_tol || bnorm == 0.0) { converged = true; break; }
     if (outer == max_outer) break;
-    const double inner_abs = prec == 0 ? abs_tol : std::max(c->opt.inner_tol * rn, 0.5 * abs_tol);
+    double inner_abs = prec == 0 ? abs_tol : std::max(c->opt.inner_tol * rn, 0.5 * abs_tol);
+    // Float32 inner operators (direct far sum, float32 self blocks) are accurate to about
+    // 2^-22: when that accuracy times this residual already meets the tolerance, solve the
+    // correction to the tolerance itself and finish in this refinement (the exact residual
+    // still decides; a miss costs one more refinement, never accuracy).
+    if (prec == RBM_MIXED_FP32 && !c->fmm_ready && std::ldexp(rn, -22) <= 0.5 * abs_tol)
+      inner_abs = 0.5 * abs_tol;
     int it = 0;
     if ((s = gmres_cycle(c, S, prec, c->r, rn, inner_abs, &it)) != RBM_OK) return s;
     total_iters += it;
