@@ -17,7 +17,8 @@ Default mode (one JSON line):
      second of wall time), mixed precision with the block-diagonal guess, and mixed
      precision with the learned guess;
   3. the roofline of the dominant kernel (float64 traction sum; HIP events on the
-     library stream) and the FP64 NumPy oracle's pair rate on the host.
+     library stream), that of the float32 traction sum of the mixed solves
+     (``roofline_fp32``), and the FP64 NumPy oracle's pair rate on the host.
 --learned-experiment: paired learned-vs-block-diagonal iteration counts along a
 trajectory (train on the first steps, evaluate on the following ones).
 """
@@ -35,6 +36,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "mobility solve time @1e-8 rel. residual (mixed+learned vs FP64); Gpairs/s"
 FP64_PEAK_TFLOPS = 78.6      # MI355X vector FP64
+FP32_PEAK_TFLOPS = 157.3     # MI355X vector FP32
 TRACTION_FLOPS_PER_PAIR = 30
 
 
@@ -223,6 +225,19 @@ def main_bench(args):
                         f"{name}_fallback": inf[-1]["fallback_used"],
                         f"{name}_vs_fp64_velocity_rel_err": err})
             _log(f"{name}: {dtm / args.steps * 1e3:.3f} ms/solve, iters {inf[-1]['iters']}")
+            if name == "mixed_bd":
+                # float32 traction launches of the mixed solves (inner iterations, right-hand side)
+                ms32 = sum(i["ms_traction32"] for i in inf)
+                n32 = sum(i["n_traction32"] for i in inf)
+                if n32:
+                    avg32 = ms32 / n32 / 1e3
+                    a32 = TRACTION_FLOPS_PER_PAIR * ppl / avg32 / 1e12
+                    result["roofline_fp32"] = {
+                        "bound": "alu",
+                        "kernel": "k_far_lds<float, traction>" if points <= 65536 else "k_far<float, traction>",
+                        "achieved": a32, "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
+                        "frac": a32 / FP32_PEAK_TFLOPS, "launch_ms": avg32 * 1e3, "launches": n32,
+                        "pairs_per_launch": ppl, "flops_per_pair": TRACTION_FLOPS_PER_PAIR}
         out["speedup_mixed_learned_vs_fp64"] = out["fp64_bd_ms"] / out["mixed_learned_ms"]
         result["learned"] = learned
         sl.close()
