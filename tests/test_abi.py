@@ -39,11 +39,25 @@ def _opts(**kw):
 def test_default_options():
     o = _opts()
     assert (o.p, o.eta, o.tol, o.max_iter, o.precision, o.guess) == (8, 1.0, 1e-12, 100, 0, 1)
+    assert (o.p_up, o.near_factor, o.contact_delta, o.magnetic, o.fmm_order, o.fmm_max_level) == \
+        (0, 5.0, 0.0, 0, 0, 5)
+
+
+def test_fmm_level_bound_checked_only_with_an_order():
+    lib = rbm.load()
+    ctx = ctypes.c_void_p()
+    o = _opts(fmm_order=8, fmm_max_level=7)
+    assert lib.rbm_create(ctypes.byref(o), ctypes.byref(ctx)) == rbm.RBM_E_INVAL
+    o = _opts(fmm_order=0, fmm_max_level=7)
+    assert lib.rbm_create(ctypes.byref(o), ctypes.byref(ctx)) == rbm.RBM_OK
+    lib.rbm_destroy(ctx)
 
 
 @pytest.mark.parametrize("field,value", [("p", 1), ("p", 21), ("eta", 0.0), ("eta", float("nan")),
                                          ("tol", -1.0), ("max_iter", 0), ("precision", 7),
-                                         ("guess", 9), ("p_sing", 3)])
+                                         ("guess", 9), ("p_sing", 3), ("p_up", 3),
+                                         ("near_factor", -1.0), ("contact_delta", -0.5),
+                                         ("fmm_order", 1), ("fmm_order", 17)])
 def test_create_rejects_bad_options(field, value):
     lib = rbm.load()
     o = _opts(**{field: value})
