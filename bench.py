@@ -183,7 +183,7 @@ def main_bench(args):
     trac_avg_s = ms_trac / max(n_trac, 1) / 1e3
     achieved = TRACTION_FLOPS_PER_PAIR * ppl / trac_avg_s / 1e12
     points = int(n * 2 * w["p"] * (w["p"] + 1))
-    kernel = "k_far_lds<double, traction>" if points <= 65536 else "k_far<double, traction>"
+    kernel = "k_far<double, traction>"
     traffic = _traffic(kernel, args.workload)
     result = {
         "metric": METRIC,
@@ -245,7 +245,7 @@ def main_bench(args):
                     a32 = TRACTION_FLOPS_PER_PAIR * ppl / avg32 / 1e12
                     result["roofline_fp32"] = {
                         "bound": "alu",
-                        "kernel": "k_far_lds<float, traction>" if points <= 65536 else "k_far<float, traction>",
+                        "kernel": "k_far<float, traction>",
                         "achieved": a32, "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
                         "frac": a32 / FP32_PEAK_TFLOPS, "launch_ms": avg32 * 1e3, "launches": n32,
                         "pairs_per_launch": ppl, "flops_per_pair": TRACTION_FLOPS_PER_PAIR}

@@ -132,74 +132,7 @@ __global__ __launch_bounds__(256) void k_far(int N, int M, const T* __restrict__
   }
 }
 
-// Small-N variant: the workgroup stages a tile of TS sources (AoS in HBM) into LDS as
-// SoA once for its four waves, which then read them as broadcasts.  Below ~64k points
-// the source range per workgroup is short and sharing the load across the four waves
-// beats per-wave scalar loads (+20 % fp32, +7 % fp64 at 20k points on MI355X); above
-// it the scalar-load kernel is faster (-5 %).
-template <typename T, int KIND, int TS>
-__global__ __launch_bounds__(256) void k_far_lds(int N, int M, const T* __restrict__ tx,
-                                                 const T* __restrict__ tn,
-                                                 const Src8<T>* __restrict__ src,
-                                                 double* __restrict__ part, int chunk) {
-  __shared__ T sh[6][TS];
-  const int split = blockIdx.y;
-  const int b0 = split * chunk, b1 = min(N, b0 + chunk);
-  const int base = blockIdx.x * 256;
-  const int a = min(base + (int)threadIdx.x, N - 1);
-  const T xa = tx[a], ya = tx[N + a], za = tx[2 * N + a];
-  T nx = 0, ny = 0, nz = 0;
-  if (KIND == 0 || KIND == 2) {
-    nx = tn[a];
-    ny = tn[N + a];
-    nz = tn[2 * N + a];
-  }
-  T ax = 0, ay = 0, az = 0;
-  const int blo_t = (a / M) * M;
-  const int last = min(N, base + 256) - 1;
-  const int blo = (base / M) * M, bhi = (last / M + 1) * M;
-  for (int t0 = b0; t0 < b1; t0 += TS) {
-    const int cnt = min(TS, b1 - t0);
-    __syncthreads();
-    for (int e = threadIdx.x; e < cnt; e += 256) {
-      const Src8<T> q = src[t0 + e];
-#pragma unroll
-      for (int c = 0; c < 6; ++c) sh[c][e] = q.v[c];
-    }
-    __syncthreads();
-    Src8<T> q;
-    q.v[6] = q.v[7] = 0;
-    if (t0 + cnt <= blo || t0 >= bhi) {
-#pragma unroll 4
-      for (int k = 0; k < cnt; ++k) {
-#pragma unroll
-        for (int c = 0; c < 6; ++c) q.v[c] = sh[c][k];
-        Pair<T, KIND>::add(xa, ya, za, nx, ny, nz, q, ax, ay, az);
-      }
-    } else {
-      for (int k = 0; k < cnt; ++k) {
-#pragma unroll
-        for (int c = 0; c < 6; ++c) q.v[c] = sh[c][k];
-        T px = 0, py = 0, pz = 0;
-        Pair<T, KIND>::add(xa, ya, za, nx, ny, nz, q, px, py, pz);
-        const bool other = (unsigned)(t0 + k - blo_t) >= (unsigned)M;
-        ax += other ? px : (T)0;
-        ay += other ? py : (T)0;
-        az += other ? pz : (T)0;
-      }
-    }
-  }
-  const double scale = kind_scale(KIND);
-  if (base + (int)threadIdx.x < N) {
-    double* o = part + (size_t)split * 3 * N;
-    o[a] = scale * (double)ax;
-    o[N + a] = scale * (double)ay;
-    o[2 * (size_t)N + a] = scale * (double)az;
-  }
-}
-
 constexpr int kTPL = 1;
-constexpr int kLdsMaxN = 65536;
 
 template <typename T>
 hipError_t launch_far(int kind, int N, int M, const T* tx, const T* nrm, const void* src,
@@ -207,7 +140,6 @@ hipError_t launch_far(int kind, int N, int M, const T* tx, const T* nrm, const v
   const int chunk = (N + nsplit - 1) / nsplit;
   dim3 grid((N + 256 * kTPL - 1) / (256 * kTPL), nsplit);
   const Src8<T>* s = reinterpret_cast<const Src8<T>*>(src);
-  constexpr int TS = sizeof(T) == 8 ? 512 : 256;
   if (kind >= 2) {
     // the scalar Laplace sums of the magnetostatic problem (float64 only)
     if constexpr (sizeof(T) == 8) {
@@ -219,16 +151,10 @@ hipError_t launch_far(int kind, int N, int M, const T* tx, const T* nrm, const v
     }
     return hipErrorInvalidValue;
   }
-  if (N <= kLdsMaxN) {
-    if (kind == 0)
-      k_far_lds<T, 0, TS><<<grid, 256, 0, st>>>(N, M, tx, nrm, s, part, chunk);
-    else
-      k_far_lds<T, 1, TS><<<grid, 256, 0, st>>>(N, M, tx, nrm, s, part, chunk);
-  } else if (kind == 0) {
+  if (kind == 0)
     k_far<T, 0, kTPL><<<grid, 256, 0, st>>>(N, M, tx, nrm, s, part, chunk);
-  } else {
+  else
     k_far<T, 1, kTPL><<<grid, 256, 0, st>>>(N, M, tx, nrm, s, part, chunk);
-  }
   return hipGetLastError();
 }
 
@@ -286,43 +212,45 @@ template hipError_t launch_pack_sources<float>(int, int, const double*, const do
                                                const double*, const double*, int, double*, void*,
                                                hipStream_t);
 
-// out = ca*a + cb*(R_i b_body) + cp*sum_s part[s]   (fixed summation order)
+// out = ca*a + cb*(R_i b_body) + cp*sum_s part[s]   (fixed summation order).
+// One thread per (component, point): the slot sum over the split is the memory-bound
+// part, so it gets 3N threads and four independent accumulators (slots s = 4k + j go
+// to accumulator j, combined as ((j0 + j1) + (j2 + j3))).  out may be a, not b_body.
 __global__ void k_combine(int N, int M, int nsplit, const double* __restrict__ part, double cp,
-                          const double* __restrict__ a, double ca, const double* __restrict__ bb,
-                          const double* __restrict__ Rm, double cb, double* __restrict__ out) {
-  const int g = blockIdx.x * blockDim.x + threadIdx.x;
-  if (g >= N) return;
-  double v[3] = {0, 0, 0};
+                          const double* a, double ca, const double* __restrict__ bb,
+                          const double* __restrict__ Rm, double cb, double* out) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= 3 * N) return;
+  const int c = t / N, g = t - c * N;
+  double v = 0.0;
   if (part) {
-    for (int s = 0; s < nsplit; ++s) {
-      const double* p = part + (size_t)s * 3 * N;
-      v[0] += p[g];
-      v[1] += p[N + g];
-      v[2] += p[2 * (size_t)N + g];
+    const size_t stride = 3 * (size_t)N;
+    const double* p = part + t;
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+    int s = 0;
+    for (; s + 4 <= nsplit; s += 4) {
+      s0 += p[(size_t)s * stride];
+      s1 += p[(size_t)(s + 1) * stride];
+      s2 += p[(size_t)(s + 2) * stride];
+      s3 += p[(size_t)(s + 3) * stride];
     }
-    v[0] *= cp; v[1] *= cp; v[2] *= cp;
+    if (s < nsplit) s0 += p[(size_t)s * stride];
+    if (s + 1 < nsplit) s1 += p[(size_t)(s + 1) * stride];
+    if (s + 2 < nsplit) s2 += p[(size_t)(s + 2) * stride];
+    v = cp * ((s0 + s1) + (s2 + s3));
   }
   if (bb) {
-    const double* R = Rm + 9 * (g / M);
-    const double b0 = bb[g], b1 = bb[N + g], b2 = bb[2 * (size_t)N + g];
-    v[0] += cb * (R[0] * b0 + R[1] * b1 + R[2] * b2);
-    v[1] += cb * (R[3] * b0 + R[4] * b1 + R[5] * b2);
-    v[2] += cb * (R[6] * b0 + R[7] * b1 + R[8] * b2);
+    const double* R = Rm + 9 * (g / M) + 3 * c;
+    v += cb * (R[0] * bb[g] + R[1] * bb[N + g] + R[2] * bb[2 * (size_t)N + g]);
   }
-  if (a) {
-    v[0] += ca * a[g];
-    v[1] += ca * a[N + g];
-    v[2] += ca * a[2 * (size_t)N + g];
-  }
-  out[g] = v[0];
-  out[N + g] = v[1];
-  out[2 * (size_t)N + g] = v[2];
+  if (a) v += ca * a[t];
+  out[t] = v;
 }
 
 hipError_t launch_combine(int N, int M, int nsplit, const double* part, double cp,
                           const double* a, double ca, const double* b_body, const double* Rm,
                           double cb, double* out, hipStream_t st) {
-  k_combine<<<(N + 255) / 256, 256, 0, st>>>(N, M, nsplit, part, cp, a, ca, b_body, Rm, cb, out);
+  k_combine<<<(3 * N + 255) / 256, 256, 0, st>>>(N, M, nsplit, part, cp, a, ca, b_body, Rm, cb, out);
   return hipGetLastError();
 }
 

@@ -95,7 +95,8 @@ hipError_t launch_pack_sources(int N, int M, const double* X, const double* W, c
 template <typename T>
 hipError_t launch_far(int kind, int N, int M, const T* tx, const T* nrm, const void* src,
                       double* part, int nsplit, hipStream_t st);
-// out[3][N] = ca * a[3][N] (optional) + cb * R_i b_body (optional) + cp * sum_s part[s]
+// out[3][N] = ca * a[3][N] (optional) + cb * R_i b_body (optional) + cp * sum_s part[s];
+// out may be the same array as a, never as b_body
 hipError_t launch_combine(int N, int M, int nsplit, const double* part, double cp,
                           const double* a, double ca, const double* b_body, const double* Rm,
                           double cb, double* out, hipStream_t st);
