@@ -545,8 +545,9 @@ def main():
         print(json.dumps({"copy_bytes_read": 1 << 30, "copy_bytes_written": 1 << 30}))
         return
     if args.gpus != 1:
-        print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the multi-GPU path is "
-              "not part of this build", file=sys.stderr)
+        print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the multi-GPU path "
+              "(bodies sharded across GPUs, sources all-gathered per matvec) is not implemented",
+              file=sys.stderr)
         sys.exit(2)
     if args.compare:
         args.workload = args.workload or "ellipsoids1000"
