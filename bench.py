@@ -288,11 +288,22 @@ def main_learned_experiment(args):
         rows.append(row)
         _log(json.dumps(row))
         s.set_guess_mode(rbm.GUESS_BLOCKDIAG)
+        if args.retrain_every:
+            # keep capturing the trajectory's stage solves and fine-tune every few steps
+            s.learned_set_capture(True)
         s.step_rk4(dt, FT)
+        if args.retrain_every:
+            s.learned_set_capture(False)
+            if (k + 1) % args.retrain_every == 0:
+                t0 = time.perf_counter()
+                loss = s.learned_train(args.retrain_epochs, 256, 1e-3)
+                torch.cuda.synchronize()
+                row["retrain"] = {"loss": loss, "s": time.perf_counter() - t0}
     it_bd = [r["bd"]["iters"] for r in rows]
     it_l = [r["learned"]["iters"] for r in rows]
     print(json.dumps({"experiment": "learned warm start, paired", "workload": args.workload,
                       "precision": args.precision, "tol": args.tol, "training": learned,
+                      "retrain_every": args.retrain_every, "retrain_epochs": args.retrain_epochs,
                       "eval_steps": args.eval_steps, "mean_iters_bd": float(np.mean(it_bd)),
                       "mean_iters_learned": float(np.mean(it_l)),
                       "mean_ms_bd": float(np.mean([r["bd"]["ms"] for r in rows])),
@@ -522,6 +533,11 @@ def main():
                          "float64 reference solve")
     ap.add_argument("--near-factor", type=float, default=5.0,
                     help="compare mode: kappa of the near test (mean node spacings)")
+    ap.add_argument("--retrain-every", type=int, default=0,
+                    help="learned experiment: keep capturing during evaluation and fine-tune the "
+                         "network every this many RK4 steps (0 = train once)")
+    ap.add_argument("--retrain-epochs", type=int, default=3,
+                    help="learned experiment: epochs of each fine-tuning")
     ap.add_argument("--fmm", type=int, default=0,
                     help="compare mode: add mixed forms whose inner iterations use the fast multipole "
                          "far field of this order")

@@ -205,7 +205,9 @@ typedef struct {
   int k_nbr;                 /* neighbours (1..16), default 8 */
   int hidden;                /* hidden width, default 256 */
   int n_hidden;              /* hidden layers (1..6), default 3 */
-  int capacity;              /* captured body states the buffer holds, default 65536 */
+  int capacity;              /* captured body states the buffer holds, default 65536; once full,
+                                new captures overwrite the oldest rows (a ring), so training
+                                can be repeated along a run on its most recent states */
   int batch_max;             /* largest training batch, default 1024 */
   unsigned long long seed;   /* weight initialisation and epoch shuffles */
 } rbm_learned_config;

@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cfloat>
 #include <cmath>
 #include <type_traits>
 #include <cstdio>
@@ -118,7 +119,7 @@ struct rbm_ctx {
   struct Learned {
     bool bound = false, stats_ready = false, capture_on = false;
     rbm_learned_config cfg;
-    int F = 0, O = 0, S = 0, L = 0, rows_max = 0, count = 0, t = 0, epoch = 0;
+    int F = 0, O = 0, S = 0, L = 0, rows_max = 0, count = 0, head = 0, t = 0, epoch = 0;
     std::vector<int> dims;
     std::vector<size_t> woff, boff;
     size_t nparam = 0;
@@ -847,7 +848,7 @@ static rbm_status learned_capture(rbm_ctx* c, const double* dFT);
 // fast multipole method when a tree is built): b then serves only the block-diagonal guess
 // and the scale ||b|| of the stopping test, while residuals come from residual_exact().
 static rbm_status build_rhs(rbm_ctx* c, SolveState& S, const double* dFT, const double* d_rho,
-                            double* bnorm, bool exact = true) {
+                            double* bnorm, bool exact = true, double* rhonorm = nullptr) {
   hipStream_t st = c->st;
   const int n = c->n, M = c->M, N = n * M;
   rbm_status s;
@@ -861,8 +862,13 @@ static rbm_status build_rhs(rbm_ctx* c, SolveState& S, const double* dFT, const 
   HIPCHECK(launch_moments(n, M, c->rho, c->X, c->W, c->cen, c->mom, st));
   HIPCHECK(launch_add_rigid(n, M, c->mom, c->X, c->cen, 1.0, c->b, st));
   S.matvecs++;
-  if ((s = norm_into(c, c->b, c->scal + 1)) != RBM_OK) return s;
-  if ((s = read_scalar(c, c->scal + 1, bnorm)) != RBM_OK) return s;
+  // ||b|| and ||rho|| read back together
+  if ((s = norm_into(c, c->b, c->scal + 6)) != RBM_OK) return s;
+  if ((s = norm_into(c, c->rho, c->scal + 7)) != RBM_OK) return s;
+  HIPCHECK(hipMemcpyAsync(c->pinned, c->scal + 6, 2 * sizeof(double), hipMemcpyDeviceToHost, st));
+  HIPCHECK(hipStreamSynchronize(st));
+  *bnorm = c->pinned[0];
+  if (rhonorm) *rhonorm = c->pinned[1];
   if (!std::isfinite(*bnorm)) return fail(RBM_E_INVAL, "non-finite right-hand side");
   return RBM_OK;
 }
@@ -906,9 +912,14 @@ static rbm_status solve_impl(rbm_ctx* c, const double* dFT, double* dVW, rbm_sol
   // Precision form: b only seeds the guess and scales the tolerance (every residual is
   // exact), so its far sum is the cheap one.  Float64 form, or a zero guess (the first
   // residual is b itself): b is exact.
-  double bnorm;
+  double bnorm, rhonorm;
   const bool b_exact = c->opt.precision == RBM_FP64 || c->opt.guess == RBM_GUESS_ZERO;
-  if ((s = build_rhs(c, S, dFT, d_rho, &bnorm, b_exact)) != RBM_OK) return s;
+  if ((s = build_rhs(c, S, dFT, d_rho, &bnorm, b_exact, &rhonorm)) != RBM_OK) return s;
+  // b at the rounding level of the terms it is formed from (an isolated sphere, whose incident
+  // density already solves the problem, or zero loads) is zero: mu = 0 solves the system to
+  // rounding and a relative test on ||b|| would only compare rounding errors
+  const bool b_zero = bnorm <= 64.0 * DBL_EPSILON * rhonorm;
+  if (b_zero) bnorm = 0.0;
   const double abs_tol = c->opt.tol * bnorm;
   const int prec = c->opt.precision;
   // initial guess
@@ -1788,6 +1799,7 @@ extern "C" rbm_status rbm_learned_bind(rbm_ctx* c, const rbm_learned_config* cfg
   L.bound = true;
   L.stats_ready = false;
   L.count = 0;
+  L.head = 0;
   L.t = 0;
   L.epoch = 0;
   // weights ~ N(0, 1/fan_in) (last layer 0.1/fan_in), biases 0
@@ -1871,17 +1883,20 @@ static rbm_status learned_capture(rbm_ctx* c, const double* dFT) {
   auto& L = c->L;
   const int n = c->n, M = c->M, N = n * M;
   const size_t len = 3 * (size_t)N;
-  if (L.count + n > L.cfg.capacity) return RBM_OK;  // buffer full
+  // ring buffer: once full, the newest states overwrite the oldest rows
+  if (n > L.cfg.capacity) return RBM_OK;
+  if (L.head + n > L.cfg.capacity) L.head = 0;
   const double* desc = L.S > 0 ? c->rcbuf : nullptr;
   HIPCHECK(launch_features(n, L.cfg.k_nbr, L.S, c->cen, c->Rm, dFT, c->sid, desc,
-                           L.Xbuf + (size_t)L.count * L.F, c->st));
+                           L.Xbuf + (size_t)L.head * L.F, c->st));
   // target: body-frame band coefficients of mu - mu_BD, mu_BD = P^{-1} b in float64
   HIPCHECK(launch_self_apply<double>(n, M, c->sid, c->P0, c->Rm, c->b, c->yb, c->st));
   HIPCHECK(launch_combine(N, M, 0, nullptr, 0.0, c->mu, 1.0, c->yb, c->Rm, -1.0, c->t1, c->st));
-  HIPCHECK(launch_band_analysis(n, M, c->p, c->t1, c->Rm, c->Ftab, L.Tbuf + (size_t)L.count * L.O, c->st));
+  HIPCHECK(launch_band_analysis(n, M, c->p, c->t1, c->Rm, c->Ftab, L.Tbuf + (size_t)L.head * L.O, c->st));
   HIPCHECK(hipStreamSynchronize(c->st));
   (void)len;
-  L.count += n;
+  L.head += n;
+  L.count = std::max(L.count, L.head);
   return RBM_OK;
 }
 

@@ -188,3 +188,41 @@ def test_shared_shape_gemm_path_matches_oracle(prec):
     assert info["rel_residual"] < 1e-12
     assert rel_err(VW, VW_o) < 1e-10
     s.close()
+
+
+@pytest.mark.parametrize("p", [2, 20])
+def test_sphere_drag_laws_at_the_order_limits(p):
+    """Smallest and largest expansion orders the library accepts: the isolated sphere's
+    drag laws v = F/(6 pi), w = T/(8 pi) are exact at every order."""
+    _case(f"single sphere drag, p={p}")
+    w = dict(inputs.workload("single_sphere"), p=p)
+    s = rbm.solver_for(w, tol=1e-13)
+    FT = np.array([[0.4, 1.0, -0.7, -0.2, 0.9, 0.5]])
+    VW, info = s.solve(FT)
+    assert info["rel_residual"] < 1e-13
+    assert np.abs(VW[0, :3] - FT[0, :3] / (6 * math.pi)).max() < 1e-12
+    assert np.abs(VW[0, 3:] - FT[0, 3:] / (8 * math.pi)).max() < 1e-12
+    s.close()
+
+
+def test_ellipsoid_mobility_against_oberbeck_and_jeffery():
+    """Tri-axial ellipsoid (1, 0.8, 0.6) at p = 16: the GPU mobility is diagonal in the body
+    frame with Oberbeck's translational and Jeffery's rotational coefficients (closed forms
+    by elliptic integrals), to the discretization's accuracy."""
+    from tests.test_oracle_system import _oberbeck
+    _case("ellipsoid (1, 0.8, 0.6) p=16 vs Oberbeck/Jeffery")
+    k = math.sqrt(4 * math.pi / 3)
+    a = np.zeros((3, 4))
+    a[0, 3], a[1, 1], a[2, 2] = 1.0 * k, 0.8 * k, 0.6 * k
+    w = {"p": 16, "eta": 1.0, "shapes": [("coef", a)], "shape_id": np.zeros(1, np.int32),
+         "centres": np.zeros((1, 3)), "quats": np.array([[1.0, 0, 0, 0]])}
+    s = rbm.solver_for(w, tol=1e-13)
+    Mm = np.zeros((6, 6))
+    for j in range(6):
+        FT = np.zeros((1, 6))
+        FT[0, j] = 1.0
+        Mm[:, j] = s.solve(FT)[0][0]
+    ref = _oberbeck(1.0, 0.8, 0.6)
+    assert np.abs(np.diag(Mm) / ref - 1).max() < 1e-8
+    assert np.abs(Mm - np.diag(np.diag(Mm))).max() < 1e-11
+    s.close()
