@@ -173,3 +173,27 @@ def test_training_on_time_stepping_reduces_iterations_and_fallback_on_garbage():
     info = s.solve_dev(FT, VW)
     assert info["fallback_used"] == 1 and info["rel_residual"] < 1e-10
     s.close()
+
+
+def test_capture_buffer_is_a_ring():
+    """Capacity of two solves' bodies, three captures: the third overwrites the first."""
+    _case("capture ring buffer: capacity 2n, three captures, n=4 p=6")
+    w = inputs.tiny(4, 6, seed=44)
+    s = rbm.solver_for(w, tol=1e-12)
+    info = s.learned_bind(k_nbr=3, hidden=16, n_hidden=1, capacity=2 * 4, batch_max=8)
+    F = info["F"]
+    prob = oracle_problem(w)
+    rng = np.random.default_rng(3)
+    FTs = [rng.standard_normal((4, 6)) for _ in range(3)]
+    for k, FTk in enumerate(FTs):
+        FT = torch.as_tensor(FTk, device="cuda")
+        VW = torch.zeros_like(FT)
+        s.solve_dev(FT, VW)
+        s.learned_capture(FT)
+        assert s.learned_info()["samples"] == min(2, k + 1) * 4
+    X = s.read("learned_X", 8 * F, dtype=np.float32).reshape(8, F)
+    for rows, FTk in ((slice(0, 4), FTs[2]), (slice(4, 8), FTs[1])):
+        ref = mlp.features(prob.c, prob.R, FTk, _desc(w), 3)
+        assert np.abs(X[rows] - ref).max() < 2e-6 * np.abs(ref).max()
+    assert np.isfinite(s.learned_train(2, 8, 1e-3))
+    s.close()
