@@ -524,67 +524,104 @@ hipError_t launch_velocity_functional(int ns, int M, const double* Sop, const do
 }
 
 // In-place Gauss-Jordan inversion with partial pivoting, one workgroup per matrix,
-// column-major A[j*n + i] = a_ij.  Each step: pivot search in column k, row swap,
-// scale the pivot row, eliminate column k from every other row; finally undo the
-// row interchanges as column interchanges in reverse order.
+// column-major A[j*n + i] = a_ij, blocked by panels of nb pivots.  Each unblocked step on
+// pivot k: search column k, swap rows k and p across all n columns, scale the pivot row,
+// eliminate column k from every other row, and store the step's transformation column
+// in column k.  Within a panel P = [k0, k0 + nb) the scaling and elimination touch only
+// the panel's columns; the panel columns then hold the panel's transformation T
+// restricted to P (T differs from I only in those columns), so every other column is
+// brought up to date at once by the rank-nb update A(:, J) += (T(:, P) - I_P) A_old(P, J),
+// with the panel rows A_old(P, J) staged in LDS.  This reads and writes the matrix once
+// per panel instead of once per pivot.  Finally the row interchanges are undone as
+// column interchanges in reverse order.
+template <int NB>
 __global__ __launch_bounds__(1024) void k_gauss_jordan(int n, double* A_all, int* piv_all) {
+  constexpr int nb = NB;
   extern __shared__ double sh[];
-  double* rowk = sh;                 // [n]
-  double* rv = rowk + n;             // [16]
+  double* rows = sh;                 // [nb][n] panel rows before the rank-nb update
+  double* rowk = rows + (size_t)nb * n;  // [nb] scaled pivot row within the panel
+  double* rv = rowk + nb;            // [16]
   int* ri = (int*)(rv + 16);         // [16]
   __shared__ int pivot_row;
   __shared__ double pivinv_s;
   const int s = blockIdx.x, tid = threadIdx.x, nt = blockDim.x;
   double* A = A_all + (size_t)s * n * n;
   int* piv = piv_all + (size_t)s * n;
-  for (int k = 0; k < n; ++k) {
-    // pivot: max |a_ik|, i >= k (ties -> smallest i)
-    double best = -1.0;
-    int bi = n;
-    for (int i = k + tid; i < n; i += nt) {
-      const double v = fabs(A[(size_t)k * n + i]);
-      if (v > best) { best = v; bi = i; }
-    }
-    for (int o = 32; o > 0; o >>= 1) {
-      const double ov = __shfl_xor(best, o, 64);
-      const int oi = __shfl_xor(bi, o, 64);
-      if (ov > best || (ov == best && oi < bi)) { best = ov; bi = oi; }
-    }
-    if ((tid & 63) == 0) { rv[tid >> 6] = best; ri[tid >> 6] = bi; }
-    __syncthreads();
-    if (tid == 0) {
-      double b = rv[0];
-      int i0 = ri[0];
-      for (int w = 1; w < nt / 64; ++w)
-        if (rv[w] > b || (rv[w] == b && ri[w] < i0)) { b = rv[w]; i0 = ri[w]; }
-      pivot_row = i0;
-      piv[k] = i0;
-    }
-    __syncthreads();
-    const int pr = pivot_row;
-    if (pr != k) {
-      for (int j = tid; j < n; j += nt) {
-        const double t1 = A[(size_t)j * n + k];
-        A[(size_t)j * n + k] = A[(size_t)j * n + pr];
-        A[(size_t)j * n + pr] = t1;
+  for (int k0 = 0; k0 < n; k0 += nb) {
+    const int kb = min(nb, n - k0);
+    for (int k = k0; k < k0 + kb; ++k) {
+      // pivot: max |a_ik|, i >= k (ties -> smallest i)
+      double best = -1.0;
+      int bi = n;
+      for (int i = k + tid; i < n; i += nt) {
+        const double v = fabs(A[(size_t)k * n + i]);
+        if (v > best) { best = v; bi = i; }
       }
+      for (int o = 32; o > 0; o >>= 1) {
+        const double ov = __shfl_xor(best, o, 64);
+        const int oi = __shfl_xor(bi, o, 64);
+        if (ov > best || (ov == best && oi < bi)) { best = ov; bi = oi; }
+      }
+      if ((tid & 63) == 0) { rv[tid >> 6] = best; ri[tid >> 6] = bi; }
+      __syncthreads();
+      if (tid == 0) {
+        double b = rv[0];
+        int i0 = ri[0];
+        for (int w = 1; w < nt / 64; ++w)
+          if (rv[w] > b || (rv[w] == b && ri[w] < i0)) { b = rv[w]; i0 = ri[w]; }
+        pivot_row = i0;
+        piv[k] = i0;
+      }
+      __syncthreads();
+      const int pr = pivot_row;
+      if (pr != k) {
+        for (int j = tid; j < n; j += nt) {
+          const double t1 = A[(size_t)j * n + k];
+          A[(size_t)j * n + k] = A[(size_t)j * n + pr];
+          A[(size_t)j * n + pr] = t1;
+        }
+      }
+      __syncthreads();
+      if (tid == 0) pivinv_s = 1.0 / A[(size_t)k * n + k];
+      __syncthreads();
+      const double pivinv = pivinv_s;
+      for (int j = k0 + tid; j < k0 + kb; j += nt) {
+        const double v = (j == k ? 1.0 : A[(size_t)j * n + k]) * pivinv;
+        rowk[j - k0] = v;
+        A[(size_t)j * n + k] = v;
+      }
+      __syncthreads();
+      for (int i = tid; i < n; i += nt) {
+        if (i == k) continue;
+        const double f = A[(size_t)k * n + i];
+        for (int j = k0; j < k0 + kb; ++j) {
+          const double old = (j == k) ? 0.0 : A[(size_t)j * n + i];
+          A[(size_t)j * n + i] = old - f * rowk[j - k0];
+        }
+      }
+      __syncthreads();
     }
-    __syncthreads();
-    if (tid == 0) pivinv_s = 1.0 / A[(size_t)k * n + k];
-    __syncthreads();
-    const double pivinv = pivinv_s;
-    for (int j = tid; j < n; j += nt) {
-      const double v = (j == k ? 1.0 : A[(size_t)j * n + k]) * pivinv;
-      rowk[j] = v;
-      A[(size_t)j * n + k] = v;
+    // rank-kb update of the columns outside the panel (rows and multipliers of a partial
+    // last panel are zero past kb)
+    for (int e = tid; e < nb * n; e += nt) {
+      const int q = e / n, j = e - q * n;
+      rows[(size_t)q * n + j] = q < kb ? A[(size_t)j * n + k0 + q] : 0.0;
     }
     __syncthreads();
     for (int i = tid; i < n; i += nt) {
-      if (i == k) continue;
-      const double f = A[(size_t)k * n + i];
+      double w[nb];
+#pragma unroll
+      for (int q = 0; q < nb; ++q) {
+        const int col = min(k0 + q, n - 1);
+        const double a = A[(size_t)col * n + i] - (i == col ? 1.0 : 0.0);
+        w[q] = q < kb ? a : 0.0;
+      }
       for (int j = 0; j < n; ++j) {
-        const double old = (j == k) ? 0.0 : A[(size_t)j * n + i];
-        A[(size_t)j * n + i] = old - f * rowk[j];
+        if (j >= k0 && j < k0 + kb) continue;
+        double v = A[(size_t)j * n + i];
+#pragma unroll
+        for (int q = 0; q < nb; ++q) v = fma(w[q], rows[(size_t)q * n + j], v);
+        A[(size_t)j * n + i] = v;
       }
     }
     __syncthreads();
@@ -602,10 +639,25 @@ __global__ __launch_bounds__(1024) void k_gauss_jordan(int n, double* A_all, int
   }
 }
 
-hipError_t launch_gauss_jordan(int ns, int n, double* A, int* piv, hipStream_t st) {
-  const size_t lds = (size_t)n * sizeof(double) + 16 * sizeof(double) + 16 * sizeof(int);
-  k_gauss_jordan<<<ns, 1024, lds, st>>>(n, A, piv);
+template <int NB>
+static hipError_t gj_launch(int ns, int n, double* A, int* piv, hipStream_t st) {
+  const size_t lds = ((size_t)NB * n + NB + 16) * sizeof(double) + 16 * sizeof(int);
+  hipError_t e = hipFuncSetAttribute((const void*)k_gauss_jordan<NB>,
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e != hipSuccess) return e;
+  k_gauss_jordan<NB><<<ns, 1024, lds, st>>>(n, A, piv);
   return hipGetLastError();
+}
+
+// Panel width: the largest power of two (at most 16: the multipliers live in registers,
+// and 1024 threads leave 128 VGPRs) whose staged panel rows fit 128 KiB of LDS.
+hipError_t launch_gauss_jordan(int ns, int n, double* A, int* piv, hipStream_t st) {
+  const size_t fit = (128 * 1024) / (8 * (size_t)n);
+  if (fit >= 16) return gj_launch<16>(ns, n, A, piv, st);
+  if (fit >= 8) return gj_launch<8>(ns, n, A, piv, st);
+  if (fit >= 4) return gj_launch<4>(ns, n, A, piv, st);
+  if (fit >= 2) return gj_launch<2>(ns, n, A, piv, st);
+  return gj_launch<1>(ns, n, A, piv, st);
 }
 
 __global__ void k_cast_f32(size_t n, const double* x, float* y) {
