@@ -13,6 +13,10 @@
 // feed the VALU directly, with no LDS traffic and no VGPRs spent on sources.  The
 // source range is split over blockIdx.y so that small problems still fill the 256
 // CUs; partial sums go to part[split][3][N] and are combined deterministically.
+// Workgroups are dispatched split by split, so the last splits are the ones running
+// while the grid drains and SIMDs fall below full occupancy: the first half of the
+// splits take long chunks (85% of the sources) and the second half share the rest in
+// short ones, which shortens that ragged end at the same number of slots.
 // Same-body pairs are excluded by index range: only the source segment that
 // overlaps the block's body range takes the per-lane masked path.
 #include "common.h"
@@ -32,9 +36,12 @@ template <typename T, int KIND, int TPL>
 __global__ __launch_bounds__(256) void k_far(int N, int M, const T* __restrict__ tx,
                                              const T* __restrict__ tn,
                                              const Src8<T>* __restrict__ src,
-                                             double* __restrict__ part, int chunk) {
+                                             double* __restrict__ part, int s1, int c1, int c2) {
+  // splits below s1 cover c1 sources each, the rest c2; a split past the end is empty
+  // (b0 >= b1) and writes zeros to its slot
   const int split = blockIdx.y;
-  const int b0 = split * chunk, b1 = min(N, b0 + chunk);
+  const int b0 = split < s1 ? split * c1 : s1 * c1 + (split - s1) * c2;
+  const int b1 = min(N, b0 + (split < s1 ? c1 : c2));
   const int base = blockIdx.x * (256 * TPL);
   T xa[TPL], ya[TPL], za[TPL], nx[TPL], ny[TPL], nz[TPL], ax[TPL], ay[TPL], az[TPL];
   int blo_t[TPL];
@@ -119,7 +126,7 @@ __global__ __launch_bounds__(256) void k_far(int N, int M, const T* __restrict__
   }
   // fast segment after the block's bodies
   fast(max(b0, bhi), b1);
-  const double scale = kind_scale(KIND);
+  const double scale = kind_scale(KIND) * Pair<T, KIND>::kPost;
 #pragma unroll
   for (int u = 0; u < TPL; ++u) {
     const int a = base + u * 256 + (int)threadIdx.x;
@@ -134,27 +141,42 @@ __global__ __launch_bounds__(256) void k_far(int N, int M, const T* __restrict__
 
 constexpr int kTPL = 1;
 
+// Source chunks of the nsplit slots: s1 = nsplit/2 long chunks of c1 sources holding
+// 85% of them, then nsplit - s1 short chunks of c2 sharing the rest.
+struct FarChunks {
+  int s1, c1, c2;
+};
+static FarChunks far_chunks(int N, int nsplit) {
+  if (nsplit < 2) return {0, N, N};
+  const int s1 = nsplit / 2, s2 = nsplit - s1;
+  const long c1 = std::min((17L * N + 20L * s1 - 1) / (20L * s1), (long)N / s1);
+  const long rest = N - s1 * c1;
+  const long c2 = std::max(1L, (rest + s2 - 1) / s2);
+  return {s1, (int)c1, (int)c2};
+}
+
 template <typename T>
 hipError_t launch_far(int kind, int N, int M, const T* tx, const T* nrm, const void* src,
                       double* part, int nsplit, hipStream_t st) {
-  const int chunk = (N + nsplit - 1) / nsplit;
+  if (N <= 0 || nsplit < 1) return hipErrorInvalidValue;
+  const FarChunks fc = far_chunks(N, nsplit);
   dim3 grid((N + 256 * kTPL - 1) / (256 * kTPL), nsplit);
   const Src8<T>* s = reinterpret_cast<const Src8<T>*>(src);
   if (kind >= 2) {
     // the scalar Laplace sums of the magnetostatic problem (float64 only)
     if constexpr (sizeof(T) == 8) {
       if (kind == 2)
-        k_far<T, 2, kTPL><<<grid, 256, 0, st>>>(N, M, tx, nrm, s, part, chunk);
+        k_far<T, 2, kTPL><<<grid, 256, 0, st>>>(N, M, tx, nrm, s, part, fc.s1, fc.c1, fc.c2);
       else
-        k_far<T, 3, kTPL><<<grid, 256, 0, st>>>(N, M, tx, nrm, s, part, chunk);
+        k_far<T, 3, kTPL><<<grid, 256, 0, st>>>(N, M, tx, nrm, s, part, fc.s1, fc.c1, fc.c2);
       return hipGetLastError();
     }
     return hipErrorInvalidValue;
   }
   if (kind == 0)
-    k_far<T, 0, kTPL><<<grid, 256, 0, st>>>(N, M, tx, nrm, s, part, chunk);
+    k_far<T, 0, kTPL><<<grid, 256, 0, st>>>(N, M, tx, nrm, s, part, fc.s1, fc.c1, fc.c2);
   else
-    k_far<T, 1, kTPL><<<grid, 256, 0, st>>>(N, M, tx, nrm, s, part, chunk);
+    k_far<T, 1, kTPL><<<grid, 256, 0, st>>>(N, M, tx, nrm, s, part, fc.s1, fc.c1, fc.c2);
   return hipGetLastError();
 }
 

@@ -311,7 +311,7 @@ __global__ __launch_bounds__(1024) void k_near_corr(int N, int M, int Mu, int km
     }
   }
   if (a < M) {
-    const double scale = KIND == 0 ? -3.0 / (4.0 * RBM_PI) : 1.0 / (8.0 * RBM_PI);
+    const double scale = (KIND == 0 ? -3.0 / (4.0 * RBM_PI) : 1.0 / (8.0 * RBM_PI)) * Pair<T, KIND>::kPost;
     double* o = slots + (size_t)t * 3 * M;
     o[a] = scale * (double)ax;
     o[M + a] = scale * (double)ay;

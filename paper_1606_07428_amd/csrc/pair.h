@@ -38,8 +38,24 @@ __device__ __forceinline__ float rinv5_t(float r2) {
   return y2 * y2 * y;
 }
 
+// (2/5) w |r|^-5, the traction pair factor over 5/2.  float64: the two-term correction
+// of rinv5_t, 1 + 5e/2 + 35e^2/8, taken as (5/2)(2/5 + e (1 + 7e/4)) with w folded into
+// y^5 first and the 5/2 left to the caller's final scale (Pair::kPost): every step then
+// has at most one constant that is not an inline operand, and the pair costs one
+// multiply fewer than w * rinv5_t(r2).  float32 has no correction and no post factor.
+__device__ __forceinline__ double w_rinv5_t(double w, double r2) {
+  const double y = __builtin_amdgcn_rsq(r2);
+  const double y2 = y * y;
+  const double e = fma(-r2, y2, 1.0);
+  const double wy5 = (w * y) * (y2 * y2);
+  return wy5 * fma(e, fma(e, 1.75, 1.0), 0.4);
+}
+__device__ __forceinline__ float w_rinv5_t(float w, float r2) { return w * rinv5_t(r2); }
+
 template <typename T, int KIND>
 struct Pair {
+  // factor the caller applies to the accumulated sums with the kernel's constant
+  static constexpr double kPost = (KIND == 0 && sizeof(T) == 8) ? 2.5 : 1.0;
   __device__ __forceinline__ static void add(T xa, T ya, T za, T nx, T ny, T nz,
                                              const Src8<T>& s, T& ax, T& ay, T& az) {
     const T dx = xa - s.v[0], dy = ya - s.v[1], dz = za - s.v[2];
@@ -47,7 +63,7 @@ struct Pair {
     const T dq = dx * s.v[3] + dy * s.v[4] + dz * s.v[5];
     if (KIND == 0) {
       const T dn = dx * nx + dy * ny + dz * nz;
-      const T f = (dn * dq) * rinv5_t(r2);
+      const T f = w_rinv5_t(dn * dq, r2);
       ax += f * dx;
       ay += f * dy;
       az += f * dz;
