@@ -3,7 +3,7 @@
 // [n_shapes][3M][3M] in the body frame (rotation covariance of §3.1 applied to the
 // vector, not to the operator).  Distinct shapes make this a batched GEMV bound by
 // HBM bandwidth: lanes own consecutive rows, so each column read is one coalesced
-// 64-row segment; four waves split the columns and are summed through LDS.
+// segment of 64 lanes' rows; four waves split the columns and are summed through LDS.
 #include "common.h"
 #include "kernels.h"
 
@@ -12,23 +12,29 @@ namespace rbm {
 template <typename TM> struct AccOf { using T = float; };
 template <> struct AccOf<double> { using T = double; };
 
-__device__ __forceinline__ float load_as_f(const float* p) { return *p; }
-__device__ __forceinline__ double load_as_f(const double* p) { return *p; }
-__device__ __forceinline__ float load_as_f(const uint16_t* p) {
-  return __uint_as_float(((uint32_t)(*p)) << 16);
-}
+__device__ __forceinline__ float as_f(float v) { return v; }
+__device__ __forceinline__ double as_f(double v) { return v; }
+__device__ __forceinline__ float as_f(uint16_t v) { return __uint_as_float(((uint32_t)v) << 16); }
 
-template <typename TM>
+// RPL consecutive matrix entries of one column, read as one vector load (RPL * sizeof(TM)
+// bytes, aligned because 3M and the lane's first row are multiples of RPL).
+template <typename TM, int RPL> struct alignas(RPL * sizeof(TM)) RowVec { TM v[RPL]; };
+
+// Lanes own RPL consecutive rows each (one row in float64, where a lane's 8-byte loads
+// already stream at the HBM rate; 2 or 4 in float32 and bf16, whose 4- and 2-byte
+// loads would otherwise leave too few bytes in flight per wave).
+template <typename TM, int RPL>
 __global__ __launch_bounds__(256) void k_self_apply(int M, int N, const int* __restrict__ sid,
                                                     const TM* __restrict__ A_all,
                                                     const double* __restrict__ Rm,
                                                     const double* __restrict__ x_lab,
                                                     double* __restrict__ y_body) {
   using TA = typename AccOf<TM>::T;
+  using V = RowVec<TM, RPL>;
   extern __shared__ double smem[];
   const int M3 = 3 * M;
   TA* xs = reinterpret_cast<TA*>(smem);               // [3M] body-frame input
-  TA* red = xs + ((M3 + 63) / 64) * 64;               // [4][64]
+  TA* red = xs + ((M3 + 63) / 64) * 64;               // [4][64 RPL]
   const int i = blockIdx.y, tid = threadIdx.x;
   const double* R = Rm + 9 * i;
   for (int a = tid; a < M; a += 256) {
@@ -41,41 +47,67 @@ __global__ __launch_bounds__(256) void k_self_apply(int M, int N, const int* __r
   __syncthreads();
   const TM* A = A_all + (size_t)sid[i] * M3 * M3;
   const int lane = tid & 63, w = tid >> 6;
-  const int row = blockIdx.x * 64 + lane;
+  const int row = (blockIdx.x * 64 + lane) * RPL;
   const int cq = (M3 + 3) / 4;
   const int c0 = w * cq, c1 = min(M3, c0 + cq);
-  TA acc = 0;
+  TA acc[4][RPL];
+#pragma unroll
+  for (int u = 0; u < 4; ++u)
+#pragma unroll
+    for (int r = 0; r < RPL; ++r) acc[u][r] = 0;
   if (row < M3) {
     const TM* Ar = A + row;
     int col = c0;
-    TA a1 = 0, a2 = 0, a3 = 0;
     for (; col + 4 <= c1; col += 4) {
-      acc += (TA)load_as_f(Ar + (size_t)col * M3) * xs[col];
-      a1 += (TA)load_as_f(Ar + (size_t)(col + 1) * M3) * xs[col + 1];
-      a2 += (TA)load_as_f(Ar + (size_t)(col + 2) * M3) * xs[col + 2];
-      a3 += (TA)load_as_f(Ar + (size_t)(col + 3) * M3) * xs[col + 3];
+      V a[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) a[u] = *reinterpret_cast<const V*>(Ar + (size_t)(col + u) * M3);
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int r = 0; r < RPL; ++r) acc[u][r] += (TA)as_f(a[u].v[r]) * xs[col + u];
     }
-    for (; col < c1; ++col) acc += (TA)load_as_f(Ar + (size_t)col * M3) * xs[col];
-    acc += (a1 + a2) + a3;
+    for (; col < c1; ++col) {
+      const V a = *reinterpret_cast<const V*>(Ar + (size_t)col * M3);
+#pragma unroll
+      for (int r = 0; r < RPL; ++r) acc[0][r] += (TA)as_f(a.v[r]) * xs[col];
+    }
   }
-  red[w * 64 + lane] = acc;
+#pragma unroll
+  for (int r = 0; r < RPL; ++r)
+    red[w * 64 * RPL + lane * RPL + r] = (acc[0][r] + acc[1][r]) + (acc[2][r] + acc[3][r]);
   __syncthreads();
   if (w == 0 && row < M3) {
-    const TA v = (red[lane] + red[64 + lane]) + (red[128 + lane] + red[192 + lane]);
-    const int c = row / M, a = row % M;
-    y_body[(size_t)c * N + (size_t)i * M + a] = (double)v;
+#pragma unroll
+    for (int r = 0; r < RPL; ++r) {
+      const int q = lane * RPL + r;
+      const TA v = (red[q] + red[64 * RPL + q]) + (red[128 * RPL + q] + red[192 * RPL + q]);
+      const int c = (row + r) / M, a = (row + r) % M;
+      y_body[(size_t)c * N + (size_t)i * M + a] = (double)v;
+    }
   }
+}
+
+template <typename TM, int RPL>
+static hipError_t self_apply_rpl(int n, int M, const int* sid, const TM* A, const double* Rm,
+                                 const double* x_lab, double* y_body, hipStream_t st) {
+  using TA = typename AccOf<TM>::T;
+  const int M3 = 3 * M;
+  dim3 grid((M3 + 64 * RPL - 1) / (64 * RPL), n);
+  const size_t lds = (((M3 + 63) / 64) * 64 + 256 * RPL) * sizeof(TA);
+  k_self_apply<TM, RPL><<<grid, 256, lds, st>>>(M, n * M, sid, A, Rm, x_lab, y_body);
+  return hipGetLastError();
 }
 
 template <typename TM>
 hipError_t launch_self_apply(int n, int M, const int* sid, const TM* A, const double* Rm,
                              const double* x_lab, double* y_body, hipStream_t st) {
-  using TA = typename AccOf<TM>::T;
   const int M3 = 3 * M;
-  dim3 grid((M3 + 63) / 64, n);
-  const size_t lds = (((M3 + 63) / 64) * 64 + 256) * sizeof(TA);
-  k_self_apply<TM><<<grid, 256, lds, st>>>(M, n * M, sid, A, Rm, x_lab, y_body);
-  return hipGetLastError();
+  if (sizeof(TM) < 8 && M3 % 4 == 0 && M3 >= 768)
+    return self_apply_rpl<TM, 4>(n, M, sid, A, Rm, x_lab, y_body, st);
+  if (sizeof(TM) < 8 && M3 % 2 == 0)
+    return self_apply_rpl<TM, 2>(n, M, sid, A, Rm, x_lab, y_body, st);
+  return self_apply_rpl<TM, 1>(n, M, sid, A, Rm, x_lab, y_body, st);
 }
 
 template hipError_t launch_self_apply<double>(int, int, const int*, const double*, const double*,
