@@ -127,6 +127,142 @@ hipError_t launch_givens(int k, int ldh, double* H, double* cs, double* sn, doub
   return hipGetLastError();
 }
 
+// ---- fused Arnoldi step ------------------------------------------------------------
+// The Gram-Schmidt tail of one GMRES iteration in four launches instead of eleven.  Each
+// kernel writes per-block partial sums, and every block of the next kernel sums all of
+// them itself in the same fixed order (kk x nblk values from L2), so no kernel waits on
+// another block and every block holds the same sums.  Block 0 alone writes the
+// Hessenberg column and the rotation state, which no other block reads in the same
+// launch.  Partial buffers: P1 and P2 hold kk x nblk sums, P3 nblk.
+
+// hs[j] = sum over b of P[j * nblk + b], j < kk, in a fixed order: wave j mod 4 takes row
+// j, lane l sums b = l, l + 64, ..., then a butterfly over the wave.
+__device__ __forceinline__ void sum_partial_rows(int kk, const double* P, int nblk, double* hs) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  for (int j = wv; j < kk; j += 4) {
+    double a = 0.0;
+    for (int b = lane; b < nblk; b += 64) a += P[(size_t)j * nblk + b];
+    a = wave_sum(a);
+    if (lane == 0) hs[j] = a;
+  }
+  __syncthreads();
+}
+
+// P1[j][blk] = block's part of V[j] . w, j < kk.
+__global__ __launch_bounds__(256) void k_arnoldi_dots(int kk, size_t len, const double* __restrict__ V,
+                                                      size_t ldv, const double* __restrict__ w,
+                                                      double* __restrict__ P1, int nblk) {
+  __shared__ double red[4];
+  const size_t stride = (size_t)nblk * 256;
+  for (int j = 0; j < kk; ++j) {
+    const double* v = V + (size_t)j * ldv;
+    double acc = 0.0;
+    for (size_t e = (size_t)blockIdx.x * 256 + threadIdx.x; e < len; e += stride) acc += v[e] * w[e];
+    const double s = block_sum(acc, red);
+    if (threadIdx.x == 0) P1[(size_t)j * nblk + blockIdx.x] = s;
+  }
+}
+
+// h = sums of P1 (into hcol by block 0); w -= V h; P2 = block parts of V^T w.
+__global__ __launch_bounds__(256) void k_arnoldi_update_dots(int kk, size_t len,
+                                                             const double* __restrict__ V, size_t ldv,
+                                                             const double* __restrict__ P1,
+                                                             double* __restrict__ P2, int nblk,
+                                                             double* __restrict__ hcol,
+                                                             double* __restrict__ w) {
+  extern __shared__ double hs[];
+  __shared__ double red[4];
+  sum_partial_rows(kk, P1, nblk, hs);
+  if (blockIdx.x == 0)
+    for (int j = threadIdx.x; j < kk; j += 256) hcol[j] = hs[j];
+  const size_t stride = (size_t)nblk * 256;
+  for (size_t e = (size_t)blockIdx.x * 256 + threadIdx.x; e < len; e += stride) {
+    double acc = 0.0;
+    for (int j = 0; j < kk; ++j) acc += V[(size_t)j * ldv + e] * hs[j];
+    w[e] -= acc;
+  }
+  for (int j = 0; j < kk; ++j) {
+    const double* v = V + (size_t)j * ldv;
+    double acc = 0.0;
+    for (size_t e = (size_t)blockIdx.x * 256 + threadIdx.x; e < len; e += stride) acc += v[e] * w[e];
+    const double s = block_sum(acc, red);
+    if (threadIdx.x == 0) P2[(size_t)j * nblk + blockIdx.x] = s;
+  }
+}
+
+// h2 = sums of P2 (added to hcol by block 0); w -= V h2; P3 = block parts of w . w.
+__global__ __launch_bounds__(256) void k_arnoldi_update_norm(int kk, size_t len,
+                                                             const double* __restrict__ V, size_t ldv,
+                                                             const double* __restrict__ P2,
+                                                             double* __restrict__ P3, int nblk,
+                                                             double* __restrict__ hcol,
+                                                             double* __restrict__ w) {
+  extern __shared__ double hs[];
+  __shared__ double red[4];
+  sum_partial_rows(kk, P2, nblk, hs);
+  if (blockIdx.x == 0)
+    for (int j = threadIdx.x; j < kk; j += 256) hcol[j] += hs[j];
+  const size_t stride = (size_t)nblk * 256;
+  double acc2 = 0.0;
+  for (size_t e = (size_t)blockIdx.x * 256 + threadIdx.x; e < len; e += stride) {
+    double acc = 0.0;
+    for (int j = 0; j < kk; ++j) acc += V[(size_t)j * ldv + e] * hs[j];
+    const double v = w[e] - acc;
+    w[e] = v;
+    acc2 += v * v;
+  }
+  const double s = block_sum(acc2, red);
+  if (threadIdx.x == 0) P3[blockIdx.x] = s;
+}
+
+// ||w|| = sqrt(sum of P3); w /= ||w|| (0 if ||w|| = 0); block 0: ||w|| into column k
+// of H, previous rotations and a new one on that column, g updated, |g_{k+1}| to resid.
+__global__ __launch_bounds__(256) void k_arnoldi_normalize(size_t len, const double* __restrict__ P3,
+                                                           int nblk, double* __restrict__ w, int k,
+                                                           int ldh, double* H, double* cs, double* sn,
+                                                           double* g, double* resid) {
+  __shared__ double nsq;
+  sum_partial_rows(1, P3, nblk, &nsq);
+  const double nv = sqrt(nsq);
+  const double f = nv != 0.0 ? 1.0 / nv : 0.0;
+  const size_t stride = (size_t)nblk * 256;
+  for (size_t e = (size_t)blockIdx.x * 256 + threadIdx.x; e < len; e += stride) w[e] *= f;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    double* h = H + (size_t)k * ldh;
+    h[k + 1] = nv;
+    for (int j = 0; j < k; ++j) {
+      const double u = cs[j] * h[j] + sn[j] * h[j + 1];
+      h[j + 1] = -sn[j] * h[j] + cs[j] * h[j + 1];
+      h[j] = u;
+    }
+    const double p = h[k], q = h[k + 1];
+    const double den = hypot(p, q);
+    const double c = den > 0.0 ? p / den : 1.0, sv = den > 0.0 ? q / den : 0.0;
+    cs[k] = c;
+    sn[k] = sv;
+    h[k] = den;
+    h[k + 1] = 0.0;
+    g[k + 1] = -sv * g[k];
+    g[k] = c * g[k];
+    resid[0] = fabs(g[k + 1]);
+  }
+}
+
+hipError_t launch_arnoldi(int k, size_t len, double* V, size_t ldv, double* partial, size_t pstride,
+                          int nblk, int ldh, double* H, double* cs, double* sn, double* g,
+                          double* resid, hipStream_t st) {
+  const int kk = k + 1;
+  double* w = V + (size_t)kk * ldv;
+  double* hcol = H + (size_t)k * ldh;
+  double *P1 = partial, *P2 = partial + pstride, *P3 = partial + 2 * pstride;
+  const size_t hs = (size_t)kk * sizeof(double);
+  k_arnoldi_dots<<<nblk, 256, 0, st>>>(kk, len, V, ldv, w, P1, nblk);
+  k_arnoldi_update_dots<<<nblk, 256, hs, st>>>(kk, len, V, ldv, P1, P2, nblk, hcol, w);
+  k_arnoldi_update_norm<<<nblk, 256, hs, st>>>(kk, len, V, ldv, P2, P3, nblk, hcol, w);
+  k_arnoldi_normalize<<<nblk, 256, 0, st>>>(len, P3, nblk, w, k, ldh, H, cs, sn, g, resid);
+  return hipGetLastError();
+}
+
 // Solve the m x m upper triangle of H y = g.
 __global__ void k_backsolve(int m, int ldh, const double* H, const double* g, double* y) {
   if (threadIdx.x != 0 || blockIdx.x != 0) return;

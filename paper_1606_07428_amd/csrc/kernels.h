@@ -118,6 +118,13 @@ hipError_t launch_givens(int k, int ldh, double* H, double* cs, double* sn, doub
 hipError_t launch_backsolve(int m, int ldh, const double* H, const double* g, double* y,
                             hipStream_t st);
 hipError_t launch_dots_final_sqrt(int nblk, const double* partial, double* h, hipStream_t st);
+// One Arnoldi step after w = V[k+1] has been formed: CGS2 against V[0..k] (column k of H),
+// w normalised and ||w|| into H, the Givens rotations of column k, g updated and
+// |g_{k+1}| written to resid (which may be mapped host memory).  partial holds three
+// regions pstride doubles apart, each at least (k + 1) * nblk.
+hipError_t launch_arnoldi(int k, size_t len, double* V, size_t ldv, double* partial, size_t pstride,
+                          int nblk, int ldh, double* H, double* cs, double* sn, double* g,
+                          double* resid, hipStream_t st);
 
 // ---- learned warm start (k_mlp.hip) --------------------------------------------------
 hipError_t launch_gemm_bf16(int m, int n, int k, const uint16_t* A, long sa0, long sa1,

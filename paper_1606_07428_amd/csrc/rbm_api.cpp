@@ -115,6 +115,7 @@ struct rbm_ctx {
   int* ccand = nullptr;
   std::vector<double> rbc_h;
   double* pinned = nullptr;
+  double* pinned_dev = nullptr;  // the same pinned buffer as a device pointer
   // learned warm start
   struct Learned {
     bool bound = false, stats_ready = false, capture_on = false;
@@ -334,7 +335,7 @@ static size_t layout(rbm_ctx* c, int nmax, bool assign) {
   take(c->V, (size_t)(m + 1) * N3); take(c->H, (size_t)(m + 1) * (m + 1)); take(c->cs, m + 1);
   take(c->sn, m + 1); take(c->g, m + 2); take(c->y, m + 2); take(c->htmp, m + 2);
   take(c->scal, 64);
-  take(c->partial, (size_t)(m + 2) * c->nblk);
+  take(c->partial, 3 * (size_t)(m + 2) * c->nblk);  // three regions for the fused Arnoldi step
   double* srcd = nullptr;
   take(srcd, 8 * N);
   if (assign) c->src = srcd;
@@ -408,7 +409,10 @@ extern "C" rbm_status rbm_bind_workspace(rbm_ctx* c, void* dptr, size_t bytes) {
   c->ws_bytes = bytes;
   c->nmax = lo;
   layout(c, lo, true);
-  if (!c->pinned) HIPCHECK(hipHostMalloc((void**)&c->pinned, 64 * sizeof(double), 0));
+  if (!c->pinned) {
+    HIPCHECK(hipHostMalloc((void**)&c->pinned, 64 * sizeof(double), 0));
+    HIPCHECK(hipHostGetDevicePointer((void**)&c->pinned_dev, c->pinned, 0));
+  }
   c->setup_done = false;
   c->bodies_dirty = true;
   return RBM_OK;
@@ -818,16 +822,12 @@ static rbm_status gmres_cycle(rbm_ctx* c, SolveState& S, int prec, const double*
     double* vk = c->V + (size_t)k * len;
     double* w = c->V + (size_t)(k + 1) * len;
     if ((s = apply_AP(c, S, prec, vk, w)) != RBM_OK) return s;
-    double* hcol = c->H + (size_t)k * ldh;
-    if ((s = dot_into(c, k + 1, c->V, len, w, hcol, nullptr)) != RBM_OK) return s;
-    HIPCHECK(launch_vupdate(k + 1, len, c->V, len, hcol, w, 0, c->st));
-    if ((s = dot_into(c, k + 1, c->V, len, w, c->htmp, hcol)) != RBM_OK) return s;
-    HIPCHECK(launch_vupdate(k + 1, len, c->V, len, c->htmp, w, 0, c->st));
-    if ((s = norm_into(c, w, hcol + k + 1)) != RBM_OK) return s;
-    HIPCHECK(launch_scale_copy(len, w, hcol + k + 1, 1, w, c->st));
-    HIPCHECK(launch_givens(k, ldh, c->H, c->cs, c->sn, c->g, nullptr, nullptr, c->scal, c->st));
-    double res;
-    if ((s = read_scalar(c, c->scal, &res)) != RBM_OK) return s;
+    // CGS2 against V[0..k], normalisation, Givens rotation and |g_{k+1}| in four launches;
+    // the residual estimate lands in pinned host memory, read after the stream sync
+    HIPCHECK(launch_arnoldi(k, len, c->V, len, c->partial, (size_t)(m + 2) * c->nblk, c->nblk, ldh, c->H,
+                            c->cs, c->sn, c->g, c->pinned_dev + 16, c->st));
+    HIPCHECK(hipStreamSynchronize(c->st));
+    const double res = c->pinned[16];
     if (!std::isfinite(res)) return fail(RBM_E_DEVICE, "non-finite GMRES residual");
     if (res <= abs_tol) { ++k; break; }
   }
