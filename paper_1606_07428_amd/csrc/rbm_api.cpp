@@ -794,6 +794,30 @@ static rbm_status norm_into(rbm_ctx* c, const double* w, double* out, size_t len
   return RBM_OK;
 }
 
+// Wait for a value >= 0 (or NaN) that a kernel of the context's stream writes into pinned
+// host memory over the sentinel -1, reading it as soon as it lands instead of waiting
+// for the stream to drain; between reads the stream is checked for errors, and a
+// drained stream without the value is reported.
+static rbm_status wait_pinned(rbm_ctx* c, volatile double* p, double* out) {
+  for (unsigned it = 1;; ++it) {
+    const double v = *p;
+    if (v != -1.0) {
+      *out = v;
+      return RBM_OK;
+    }
+    if ((it & 63) == 0) {
+      const hipError_t q = hipStreamQuery(c->st);
+      if (q == hipSuccess) {
+        const double v2 = *p;
+        if (v2 == -1.0) return fail(RBM_E_DEVICE, "GMRES residual estimate not written");
+        *out = v2;
+        return RBM_OK;
+      }
+      if (q != hipErrorNotReady) return fail(RBM_E_DEVICE, hipGetErrorString(q));
+    }
+  }
+}
+
 static rbm_status read_scalar(rbm_ctx* c, const double* d, double* h) {
   HIPCHECK(hipMemcpyAsync(c->pinned, d, sizeof(double), hipMemcpyDeviceToHost, c->st));
   HIPCHECK(hipStreamSynchronize(c->st));
@@ -817,19 +841,37 @@ static rbm_status gmres_cycle(rbm_ctx* c, SolveState& S, int prec, const double*
   c->pinned[1] = rnorm;
   HIPCHECK(hipMemcpyAsync(c->g, c->pinned + 1, sizeof(double), hipMemcpyHostToDevice, c->st));
   HIPCHECK(launch_scale_copy(len, r, c->g, 1, c->V, c->st));
+  // Iteration j: w = V[j+1] = A P~^-1 V[j], then CGS2 against V[0..j], normalisation,
+  // Givens rotation and |g_{j+1}| in four launches; the residual estimate lands in
+  // pinned host memory (two slots, alternating) and is read as soon as it does.
+  const auto enqueue = [&](int j) -> rbm_status {
+    rbm_status s2;
+    if ((s2 = apply_AP(c, S, prec, c->V + (size_t)j * len, c->V + (size_t)(j + 1) * len)) != RBM_OK)
+      return s2;
+    c->pinned[16 + (j & 1)] = -1.0;
+    HIPCHECK(launch_arnoldi(j, len, c->V, len, c->partial, (size_t)(m + 2) * c->nblk, c->nblk, ldh, c->H,
+                            c->cs, c->sn, c->g, c->pinned_dev + 16 + (j & 1), c->st));
+    return RBM_OK;
+  };
+  // While the residual estimates fall at a steady rate and the next one is predicted at
+  // more than 8 abs_tol, iteration k+1 is queued before iteration k's estimate is read,
+  // so the GPU does not idle through the host's round trip.  If k converges after all,
+  // k+1 only wrote V[k+2], column k+1 of H and g[k+1..k+2], which the solution over the
+  // first k+1 columns does not read.
+  if ((s = enqueue(0)) != RBM_OK) return s;
+  double prev1 = rnorm, prev2 = -1.0;  // estimates after iterations k-1 and k-2
   int k = 0;
   for (k = 0; k < m; ++k) {
-    double* vk = c->V + (size_t)k * len;
-    double* w = c->V + (size_t)(k + 1) * len;
-    if ((s = apply_AP(c, S, prec, vk, w)) != RBM_OK) return s;
-    // CGS2 against V[0..k], normalisation, Givens rotation and |g_{k+1}| in four launches;
-    // the residual estimate lands in pinned host memory, read after the stream sync
-    HIPCHECK(launch_arnoldi(k, len, c->V, len, c->partial, (size_t)(m + 2) * c->nblk, c->nblk, ldh, c->H,
-                            c->cs, c->sn, c->g, c->pinned_dev + 16, c->st));
-    HIPCHECK(hipStreamSynchronize(c->st));
-    const double res = c->pinned[16];
+    bool ahead = false;
+    if (k + 1 < m && prev2 > 0.0) ahead = prev1 * std::min(1.0, prev1 / prev2) > 8.0 * abs_tol;
+    if (ahead && (s = enqueue(k + 1)) != RBM_OK) return s;
+    double res;
+    if ((s = wait_pinned(c, c->pinned + 16 + (k & 1), &res)) != RBM_OK) return s;
     if (!std::isfinite(res)) return fail(RBM_E_DEVICE, "non-finite GMRES residual");
     if (res <= abs_tol) { ++k; break; }
+    if (!ahead && k + 1 < m && (s = enqueue(k + 1)) != RBM_OK) return s;
+    prev2 = prev1;
+    prev1 = res;
   }
   if (k > m) k = m;
   *iters = k;
