@@ -101,6 +101,12 @@ typedef struct {
                            tol.  0 = off (direct sums everywhere) */
   int fmm_max_level;    /* deepest octree level the FMM may use, in [2, 6] (workspace grows as
                            8^level); 0 -> 5 */
+  int gmres_lookahead;  /* queueing of GMRES iterations (§3.2): 1 (default) queues iteration
+                           k+1 before iteration k's residual estimate is read while the
+                           estimates fall steadily and the next is predicted above 8 times the
+                           tolerance; 0 never, 2 always (then a converged cycle may run one
+                           iteration whose result is discarded).  The iterates and the
+                           solution are the same in every mode. */
 } rbm_options;
 
 typedef struct {

@@ -156,6 +156,7 @@ extern "C" void rbm_default_options(rbm_options* o) {
   o->magnetic = 0;
   o->fmm_order = 0;
   o->fmm_max_level = 5;
+  o->gmres_lookahead = 1;
 }
 
 extern "C" const char* rbm_last_error(void) { return g_err.c_str(); }
@@ -181,6 +182,7 @@ extern "C" rbm_status rbm_create(const rbm_options* opt, rbm_ctx** out) {
     return fail(RBM_E_INVAL, "fmm_order must be 0 or in [2, 16]");
   if (opt->fmm_order != 0 && opt->fmm_max_level != 0 && (opt->fmm_max_level < 2 || opt->fmm_max_level > 6))
     return fail(RBM_E_INVAL, "fmm_max_level must be 0 or in [2, 6]");
+  if (opt->gmres_lookahead < 0 || opt->gmres_lookahead > 2) return fail(RBM_E_INVAL, "gmres_lookahead in [0, 2]");
   rbm_ctx* c = new rbm_ctx();
   c->opt = *opt;
   if (c->opt.fmm_max_level == 0) c->opt.fmm_max_level = 5;
@@ -863,7 +865,9 @@ static rbm_status gmres_cycle(rbm_ctx* c, SolveState& S, int prec, const double*
   int k = 0;
   for (k = 0; k < m; ++k) {
     bool ahead = false;
-    if (k + 1 < m && prev2 > 0.0) ahead = prev1 * std::min(1.0, prev1 / prev2) > 8.0 * abs_tol;
+    if (k + 1 < m && c->opt.gmres_lookahead == 2) ahead = true;
+    if (k + 1 < m && c->opt.gmres_lookahead == 1 && prev2 > 0.0)
+      ahead = prev1 * std::min(1.0, prev1 / prev2) > 8.0 * abs_tol;
     if (ahead && (s = enqueue(k + 1)) != RBM_OK) return s;
     double res;
     if ((s = wait_pinned(c, c->pinned + 16 + (k & 1), &res)) != RBM_OK) return s;

@@ -37,7 +37,8 @@ class Options(ctypes.Structure):
                 ("precision", ctypes.c_int), ("guess", ctypes.c_int), ("inner_tol", ctypes.c_double),
                 ("stream", ctypes.c_void_p), ("p_up", ctypes.c_int), ("near_factor", ctypes.c_double),
                 ("contact_delta", ctypes.c_double), ("magnetic", ctypes.c_int),
-                ("fmm_order", ctypes.c_int), ("fmm_max_level", ctypes.c_int)]
+                ("fmm_order", ctypes.c_int), ("fmm_max_level", ctypes.c_int),
+                ("gmres_lookahead", ctypes.c_int)]
 
 
 class SolveInfo(ctypes.Structure):
@@ -153,7 +154,8 @@ class Solver:
     def __init__(self, p, shapes, shape_id, centres, quats, eta=1.0, p_sing=0, tol=1e-12,
                  max_iter=100, max_restart=4, precision=FP64, guess=GUESS_BLOCKDIAG,
                  inner_tol=1e-4, n_max=None, stream=None, device="cuda", p_up=0, near_factor=5.0,
-                 contact_delta=0.0, magnetic=0, fmm_order=0, fmm_max_level=5):
+                 contact_delta=0.0, magnetic=0, fmm_order=0, fmm_max_level=5,
+                 gmres_lookahead=1):
         import torch
         lib = load()
         self.torch = torch
@@ -166,6 +168,7 @@ class Solver:
         opt.p_up, opt.near_factor, opt.contact_delta = p_up, near_factor, contact_delta
         opt.magnetic = magnetic
         opt.fmm_order, opt.fmm_max_level = fmm_order, fmm_max_level
+        opt.gmres_lookahead = gmres_lookahead
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
         opt.stream = ctypes.c_void_p(self.stream.cuda_stream)
         self.opt = opt

@@ -226,3 +226,26 @@ def test_ellipsoid_mobility_against_oberbeck_and_jeffery():
     assert np.abs(np.diag(Mm) / ref - 1).max() < 1e-8
     assert np.abs(Mm - np.diag(np.diag(Mm))).max() < 1e-11
     s.close()
+
+
+@pytest.mark.parametrize("prec", [rbm.FP64, rbm.MIXED_FP32])
+def test_gmres_lookahead_modes_give_the_same_solution(prec):
+    """Queueing GMRES iteration k+1 before iteration k's residual estimate is read (never,
+    when predicted safe, always) changes the schedule only: a queued iteration after
+    convergence writes nothing the solution reads, so the velocities are bitwise equal."""
+    _case(f"gmres lookahead 0/1/2, tiny n=5 p=6, precision={prec}")
+    from oracle import system as sy
+    w = inputs.tiny(5, 6, seed=8)
+    out = []
+    for mode in (0, 1, 2):
+        s = rbm.solver_for(w, tol=1e-11, precision=prec, gmres_lookahead=mode)
+        VW, info = s.solve(w["FT"])
+        assert info["rel_residual"] < 1e-11 and info["iters"] >= 3
+        out.append((VW, info))
+        s.close()
+    for VW, info in out[1:]:
+        assert np.array_equal(VW, out[0][0])
+        assert info["iters"] == out[0][1]["iters"]
+    assert out[2][1]["matvecs"] >= out[0][1]["matvecs"]
+    _, _, VW_o = sy.solve_dense(oracle_problem(w), w["FT"])
+    assert rel_err(out[2][0], VW_o) < 1e-9
