@@ -68,11 +68,13 @@ struct Pair {
       ay += f * dy;
       az += f * dz;
     } else if (KIND == 1) {
+      // q/|d| + d (d.q)/|d|^3 = (q + u d)/|d| with u = (d.q)/|d|^2: two fused
+      // multiply-adds per component
       const T ri = rsqrt_t(r2);
-      const T f = dq * (ri * ri * ri);
-      ax += s.v[3] * ri + f * dx;
-      ay += s.v[4] * ri + f * dy;
-      az += s.v[5] * ri + f * dz;
+      const T u = dq * (ri * ri);
+      ax += ri * (s.v[3] + u * dx);
+      ay += ri * (s.v[4] + u * dy);
+      az += ri * (s.v[5] + u * dz);
     } else if (KIND == 2) {
       // Laplace, normal derivative at the target of the single layer: (d.N_a) q_b / |d|^3
       const T ri = rsqrt_t(r2);
