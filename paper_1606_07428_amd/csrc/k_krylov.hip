@@ -1,6 +1,8 @@
 // GMRES building blocks in float64 (§3.2): classical Gram-Schmidt dot products and
 // updates (applied twice, CGS2), Givens rotations of the Hessenberg column, and the
 // triangular solve.  Reductions are two-stage with a fixed order (deterministic).
+#include <algorithm>
+
 #include "common.h"
 #include "kernels.h"
 
@@ -124,6 +126,26 @@ __global__ void k_givens(int k, int ldh, double* H, double* cs, double* sn, doub
 hipError_t launch_givens(int k, int ldh, double* H, double* cs, double* sn, double* g,
                          const double*, const double*, double* resid, hipStream_t st) {
   k_givens<<<1, 64, 0, st>>>(k, ldh, H, cs, sn, g, resid);
+  return hipGetLastError();
+}
+
+// Start of a GMRES cycle: V0 = r / rnorm (0 if rnorm = 0), g = (rnorm, 0, ..., 0) over ng
+// entries, H = 0 over nh entries; one launch in place of two fills, a copy and a scale.
+__global__ void k_gmres_init(size_t len, const double* __restrict__ r, double rnorm,
+                             double* __restrict__ V0, int ng, double* __restrict__ g, size_t nh,
+                             double* __restrict__ H) {
+  const size_t stride = (size_t)gridDim.x * blockDim.x;
+  const size_t i0 = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const double f = rnorm != 0.0 ? 1.0 / rnorm : 0.0;
+  for (size_t e = i0; e < len; e += stride) V0[e] = r[e] * f;
+  for (size_t e = i0; e < nh; e += stride) H[e] = 0.0;
+  for (size_t e = i0; e < (size_t)ng; e += stride) g[e] = e == 0 ? rnorm : 0.0;
+}
+
+hipError_t launch_gmres_init(size_t len, const double* r, double rnorm, double* V0, int ng, double* g,
+                             size_t nh, double* H, hipStream_t st) {
+  const size_t n = std::max(len, nh);
+  k_gmres_init<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(len, r, rnorm, V0, ng, g, nh, H);
   return hipGetLastError();
 }
 

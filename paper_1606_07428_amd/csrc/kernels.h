@@ -118,6 +118,10 @@ hipError_t launch_givens(int k, int ldh, double* H, double* cs, double* sn, doub
 hipError_t launch_backsolve(int m, int ldh, const double* H, const double* g, double* y,
                             hipStream_t st);
 hipError_t launch_dots_final_sqrt(int nblk, const double* partial, double* h, hipStream_t st);
+// GMRES cycle start: V0 = r / rnorm (0 if rnorm = 0), g[0] = rnorm and g[1..ng) = 0,
+// H[0..nh) = 0.
+hipError_t launch_gmres_init(size_t len, const double* r, double rnorm, double* V0, int ng, double* g,
+                             size_t nh, double* H, hipStream_t st);
 // One Arnoldi step after w = V[k+1] has been formed: CGS2 against V[0..k] (column k of H),
 // w normalised and ||w|| into H, the Givens rotations of column k, g updated and
 // |g_{k+1}| written to resid (which may be mapped host memory).  partial holds three

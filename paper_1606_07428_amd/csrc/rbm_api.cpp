@@ -837,12 +837,8 @@ static rbm_status gmres_cycle(rbm_ctx* c, SolveState& S, int prec, const double*
   const int ldh = m + 1;
   const int N = c->n * c->M;
   rbm_status s;
-  // g = (rnorm, 0, ...), V0 = r / rnorm
-  HIPCHECK(hipMemsetAsync(c->g, 0, (m + 2) * sizeof(double), c->st));
-  HIPCHECK(hipMemsetAsync(c->H, 0, (size_t)(m + 1) * (m + 1) * sizeof(double), c->st));
-  c->pinned[1] = rnorm;
-  HIPCHECK(hipMemcpyAsync(c->g, c->pinned + 1, sizeof(double), hipMemcpyHostToDevice, c->st));
-  HIPCHECK(launch_scale_copy(len, r, c->g, 1, c->V, c->st));
+  // g = (rnorm, 0, ...), H = 0, V0 = r / rnorm
+  HIPCHECK(launch_gmres_init(len, r, rnorm, c->V, m + 2, c->g, (size_t)(m + 1) * (m + 1), c->H, c->st));
   // Iteration j: w = V[j+1] = A P~^-1 V[j], then CGS2 against V[0..j], normalisation,
   // Givens rotation and |g_{j+1}| in four launches; the residual estimate lands in
   // pinned host memory (two slots, alternating) and is read as soon as it does.
