@@ -52,10 +52,22 @@ __device__ __forceinline__ double w_rinv5_t(double w, double r2) {
 }
 __device__ __forceinline__ float w_rinv5_t(float w, float r2) { return w * rinv5_t(r2); }
 
+// (2/3) w |r|^-3 for the Laplace normal derivative: y^3 (1 - e)^(-3/2) = y^3 (1 + 3e/2 +
+// 15e^2/8 + O(e^3)) = (3/2) y^3 (2/3 + e (1 + 5e/4)), the 3/2 left to the caller's final
+// scale (Pair::kPost), so that every step has at most one constant that is not an
+// inline operand.
+__device__ __forceinline__ double w_rinv3_t(double w, double r2) {
+  const double y = __builtin_amdgcn_rsq(r2);
+  const double y2 = y * y;
+  const double e = fma(-r2, y2, 1.0);
+  const double wy3 = (w * y) * y2;
+  return wy3 * fma(e, fma(e, 1.25, 1.0), 2.0 / 3.0);
+}
+
 template <typename T, int KIND>
 struct Pair {
   // factor the caller applies to the accumulated sums with the kernel's constant
-  static constexpr double kPost = (KIND == 0 && sizeof(T) == 8) ? 2.5 : 1.0;
+  static constexpr double kPost = sizeof(T) != 8 ? 1.0 : KIND == 0 ? 2.5 : KIND == 2 ? 1.5 : 1.0;
   __device__ __forceinline__ static void add(T xa, T ya, T za, T nx, T ny, T nz,
                                              const Src8<T>& s, T& ax, T& ay, T& az) {
     const T dx = xa - s.v[0], dy = ya - s.v[1], dz = za - s.v[2];
@@ -77,8 +89,8 @@ struct Pair {
       az += ri * (s.v[5] + u * dz);
     } else if (KIND == 2) {
       // Laplace, normal derivative at the target of the single layer: (d.N_a) q_b / |d|^3
-      const T ri = rsqrt_t(r2);
-      ax += (dx * nx + dy * ny + dz * nz) * s.v[3] * (ri * ri * ri);
+      // (float64 only; the sum carries the factor 2/3 that kPost undoes)
+      ax += w_rinv3_t((dx * nx + dy * ny + dz * nz) * s.v[3], r2);
     } else {
       // Laplace single layer: q_b / |d|
       ax += s.v[3] * rsqrt_t(r2);
