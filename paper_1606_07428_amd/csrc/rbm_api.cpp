@@ -854,8 +854,8 @@ static rbm_status gmres_cycle(rbm_ctx* c, SolveState& S, int prec, const double*
   // While the residual estimates fall at a steady rate and the next one is predicted at
   // more than 8 abs_tol, iteration k+1 is queued before iteration k's estimate is read,
   // so the GPU does not idle through the host's round trip.  If k converges after all,
-  // k+1 only wrote V[k+2], column k+1 of H and g[k+1..k+2], which the solution over the
-  // first k+1 columns does not read.
+  // k+1 only wrote V[k+2], column k+1 of H, rotation k+1 (cs, sn), g[k+1..k+2] and scratch
+  // buffers; the solution over the first k+1 columns reads H and g up to row k only.
   if ((s = enqueue(0)) != RBM_OK) return s;
   double prev1 = rnorm, prev2 = -1.0;  // estimates after iterations k-1 and k-2
   int k = 0;
