@@ -204,57 +204,73 @@ hipError_t launch_to_bf16(size_t cnt, const float* x, uint16_t* y, hipStream_t s
 
 // Per body i: body-frame features (own load, shape descriptor, k nearest neighbours:
 // R^T d/|d|^2, first two columns of R_i^T R_j, R^T F_j, R^T T_j; zero padding).
-__global__ void k_features(int n, int k, int S, const double* cen, const double* Rm,
-                           const double* FT, const int* sid, const double* desc, float* X) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
+// One wave per body.  The k nearest other bodies in (squared distance, index) order are
+// picked in k rounds, each a wave-wide argmin over the pairs after the previous pick
+// (the order an insertion sort over increasing j keeps, ties included); lane s then
+// writes the 15 features of neighbour slot s.
+__global__ __launch_bounds__(64) void k_features(int n, int k, int S, const double* cen, const double* Rm,
+                                                 const double* FT, const int* sid, const double* desc,
+                                                 float* X) {
+  const int i = blockIdx.x, lane = threadIdx.x;
+  const double ci0 = cen[3 * i], ci1 = cen[3 * i + 1], ci2 = cen[3 * i + 2];
+  double pd = -1.0;
+  int pj = -1, myj = -1;
+  for (int s = 0; s < k; ++s) {
+    double bd = 1e300;
+    int bj = 0x7fffffff;
+    for (int j = lane; j < n; j += 64) {
+      if (j == i) continue;
+      const double d0 = cen[3 * j] - ci0, d1 = cen[3 * j + 1] - ci1, d2 = cen[3 * j + 2] - ci2;
+      const double dd = d0 * d0 + d1 * d1 + d2 * d2;
+      const bool after = dd > pd || (dd == pd && j > pj);
+      if (after && (dd < bd || (dd == bd && j < bj))) {
+        bd = dd;
+        bj = j;
+      }
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+      const double od = __shfl_xor(bd, o, 64);
+      const int oj = __shfl_xor(bj, o, 64);
+      if (od < bd || (od == bd && oj < bj)) {
+        bd = od;
+        bj = oj;
+      }
+    }
+    if (bj == 0x7fffffff) break;  // fewer than k other bodies
+    if (lane == s) myj = bj;
+    pd = bd;
+    pj = bj;
+  }
   const int F = 6 + S + 15 * k;
   float* x = X + (size_t)i * F;
-  constexpr int KMAX = 16;
-  double bd[KMAX];
-  int bj[KMAX];
-  for (int s = 0; s < KMAX; ++s) { bd[s] = 1e300; bj[s] = -1; }
-  const double ci0 = cen[3 * i], ci1 = cen[3 * i + 1], ci2 = cen[3 * i + 2];
-  for (int j = 0; j < n; ++j) {
-    if (j == i) continue;
-    const double d0 = cen[3 * j] - ci0, d1 = cen[3 * j + 1] - ci1, d2 = cen[3 * j + 2] - ci2;
-    const double dd = d0 * d0 + d1 * d1 + d2 * d2;
-    if (dd >= bd[k - 1]) continue;
-    int pos = k - 1;
-    while (pos > 0 && bd[pos - 1] > dd) {
-      bd[pos] = bd[pos - 1];
-      bj[pos] = bj[pos - 1];
-      --pos;
-    }
-    bd[pos] = dd;
-    bj[pos] = j;
-  }
   const double* R = Rm + 9 * i;
   auto rt = [&](double a0, double a1, double a2, float* o) {  // R^T a
     o[0] = (float)(R[0] * a0 + R[3] * a1 + R[6] * a2);
     o[1] = (float)(R[1] * a0 + R[4] * a1 + R[7] * a2);
     o[2] = (float)(R[2] * a0 + R[5] * a1 + R[8] * a2);
   };
-  const double* f = FT + 6 * i;
-  rt(f[0], f[1], f[2], x);
-  rt(f[3], f[4], f[5], x + 3);
-  for (int s = 0; s < S; ++s) x[6 + s] = (float)desc[(size_t)sid[i] * S + s];
-  for (int slot = 0; slot < k; ++slot) {
-    float* o = x + 6 + S + 15 * slot;
-    const int j = bj[slot];
+  if (lane == 0) {
+    const double* f = FT + 6 * i;
+    rt(f[0], f[1], f[2], x);
+    rt(f[3], f[4], f[5], x + 3);
+  }
+  for (int q = lane; q < S; q += 64) x[6 + q] = (float)desc[(size_t)sid[i] * S + q];
+  if (lane < k) {
+    float* o = x + 6 + S + 15 * lane;
+    const int j = myj;
     if (j < 0) {
       for (int e = 0; e < 15; ++e) o[e] = 0.f;
-      continue;
+    } else {
+      const double d0 = cen[3 * j] - ci0, d1 = cen[3 * j + 1] - ci1, d2 = cen[3 * j + 2] - ci2;
+      const double id2 = 1.0 / (d0 * d0 + d1 * d1 + d2 * d2);
+      rt(d0 * id2, d1 * id2, d2 * id2, o);
+      const double* Rj = Rm + 9 * j;
+      rt(Rj[0], Rj[3], Rj[6], o + 3);   // first column of R_j
+      rt(Rj[1], Rj[4], Rj[7], o + 6);   // second column of R_j
+      const double* fj = FT + 6 * j;
+      rt(fj[0], fj[1], fj[2], o + 9);
+      rt(fj[3], fj[4], fj[5], o + 12);
     }
-    const double d0 = cen[3 * j] - ci0, d1 = cen[3 * j + 1] - ci1, d2 = cen[3 * j + 2] - ci2;
-    const double id2 = 1.0 / (d0 * d0 + d1 * d1 + d2 * d2);
-    rt(d0 * id2, d1 * id2, d2 * id2, o);
-    const double* Rj = Rm + 9 * j;
-    rt(Rj[0], Rj[3], Rj[6], o + 3);   // first column of R_j
-    rt(Rj[1], Rj[4], Rj[7], o + 6);   // second column of R_j
-    const double* fj = FT + 6 * j;
-    rt(fj[0], fj[1], fj[2], o + 9);
-    rt(fj[3], fj[4], fj[5], o + 12);
   }
 }
 
@@ -262,7 +278,8 @@ hipError_t launch_features(int n, int k, int S, const double* cen, const double*
                            const double* FT, const int* sid, const double* desc, float* X,
                            hipStream_t st) {
   if (k > 16) return hipErrorInvalidValue;
-  k_features<<<(n + 63) / 64, 64, 0, st>>>(n, k, S, cen, Rm, FT, sid, desc, X);
+  if (n < 1 || k < 0) return hipErrorInvalidValue;
+  k_features<<<n, 64, 0, st>>>(n, k, S, cen, Rm, FT, sid, desc, X);
   return hipGetLastError();
 }
 
