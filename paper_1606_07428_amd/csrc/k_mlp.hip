@@ -77,9 +77,56 @@ __global__ __launch_bounds__(256) void k_gemm_bf16(int m, int n, int k, const ui
       }
 }
 
+// Few rows (the per-body network at inference, small batches): one wave per 16x16 output
+// tile, operands read straight from global memory with the same MFMA layout and no LDS,
+// so a 64 x 256 product runs on 64 waves instead of 4 workgroups that each wait on every
+// K step.
+__global__ __launch_bounds__(256) void k_gemm_bf16_tile16(int m, int n, int k,
+                                                          const uint16_t* __restrict__ A, long sa0,
+                                                          long sa1, const uint16_t* __restrict__ B,
+                                                          long sb0, long sb1, float* __restrict__ C,
+                                                          int ldc, const float* __restrict__ bias,
+                                                          float alpha, float beta) {
+  const int lane = threadIdx.x & 63;
+  const int tiles_n = (n + 15) / 16;
+  const int t = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int ti = t / tiles_n, tj = t - ti * tiles_n;
+  if (ti * 16 >= m) return;  // the whole wave
+  const int lr = lane & 15, lk = 4 * (lane >> 4);
+  const int ia = ti * 16 + lr, jb = tj * 16 + lr;
+  f4v acc = (f4v){0.f, 0.f, 0.f, 0.f};
+#pragma unroll 4
+  for (int k0 = 0; k0 < k; k0 += 16) {
+    s4v av, bv;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int kk = k0 + lk + j;
+      av[j] = (short)((ia < m && kk < k) ? A[(long)ia * sa0 + (long)kk * sa1] : (uint16_t)0);
+      bv[j] = (short)((kk < k && jb < n) ? B[(long)kk * sb0 + (long)jb * sb1] : (uint16_t)0);
+    }
+    acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av, bv, acc, 0, 0, 0);
+  }
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    const int i = ti * 16 + lk + e, j = jb;
+    if (i < m && j < n) {
+      float v = alpha * acc[e];
+      if (bias) v += bias[j];
+      if (beta != 0.f) v += beta * C[(long)i * ldc + j];
+      C[(long)i * ldc + j] = v;
+    }
+  }
+}
+
 hipError_t launch_gemm_bf16(int m, int n, int k, const uint16_t* A, long sa0, long sa1,
                             const uint16_t* B, long sb0, long sb1, float* C, int ldc,
                             const float* bias, float alpha, float beta, hipStream_t st) {
+  if (m <= 128) {
+    const long tiles = (long)((m + 15) / 16) * ((n + 15) / 16);
+    k_gemm_bf16_tile16<<<(unsigned)((tiles + 3) / 4), 256, 0, st>>>(m, n, k, A, sa0, sa1, B, sb0, sb1, C,
+                                                                      ldc, bias, alpha, beta);
+    return hipGetLastError();
+  }
   dim3 grid((n + 63) / 64, (m + 63) / 64);
   k_gemm_bf16<<<grid, 256, 0, st>>>(m, n, k, A, sa0, sa1, B, sb0, sb1, C, ldc, bias, alpha, beta);
   return hipGetLastError();
@@ -351,32 +398,44 @@ hipError_t launch_rms(size_t cnt, const float* T, float* out, hipStream_t st) {
 }
 
 // mu[:, body i] += scale * R_i Y_B(grid) coef_i  (band synthesis of a body-frame density)
-__global__ void k_band_synth(int n, int M, int p, const float* coef, const float* scale,
-                             const double* Ytab, const double* Rm, double* mu) {
+// Four lanes per node, each summing a quarter of the band coefficients with independent
+// loads in flight, joined by two butterfly steps; the first lane of the four writes.
+__global__ __launch_bounds__(256) void k_band_synth(int n, int M, int p, const float* coef,
+                                                    const float* scale, const double* Ytab,
+                                                    const double* Rm, double* mu) {
   const size_t N = (size_t)n * M;
-  const size_t g = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (g >= N) return;
-  const int i = (int)(g / M), a = (int)(g % M);
+  const size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const size_t g = t >> 2;
+  const int q = (int)(t & 3);
+  const bool act = g < N;
+  const size_t gc = act ? g : 0;
+  const int i = (int)(gc / M), a = (int)(gc % M);
   const int nB = p * p + 2 * p;
   const float* cf = coef + (size_t)i * 3 * nB;
-  double v[3] = {0, 0, 0};
-  for (int b = 0; b < nB; ++b) {
+  double v0 = 0, v1 = 0, v2 = 0;
+  for (int b = q; b < nB; b += 4) {
     const int full = b < p * p ? b : b + 1;
     const double y = Ytab[(size_t)full * M + a];
-    v[0] += y * cf[b];
-    v[1] += y * cf[nB + b];
-    v[2] += y * cf[2 * nB + b];
+    v0 += y * cf[b];
+    v1 += y * cf[nB + b];
+    v2 += y * cf[2 * nB + b];
   }
+  for (int o = 1; o < 4; o <<= 1) {
+    v0 += __shfl_xor(v0, o, 64);
+    v1 += __shfl_xor(v1, o, 64);
+    v2 += __shfl_xor(v2, o, 64);
+  }
+  if (!act || q != 0) return;
   const double sc = scale ? (double)scale[0] : 1.0;
   const double* R = Rm + 9 * i;
   for (int c = 0; c < 3; ++c)
-    mu[c * N + g] += sc * (R[3 * c] * v[0] + R[3 * c + 1] * v[1] + R[3 * c + 2] * v[2]);
+    mu[c * N + g] += sc * (R[3 * c] * v0 + R[3 * c + 1] * v1 + R[3 * c + 2] * v2);
 }
 
 hipError_t launch_band_synth(int n, int M, int p, const float* coef, const float* scale,
                              const double* Ytab, const double* Rm, double* mu, hipStream_t st) {
   const size_t N = (size_t)n * M;
-  k_band_synth<<<(unsigned)((N + 255) / 256), 256, 0, st>>>(n, M, p, coef, scale, Ytab, Rm, mu);
+  k_band_synth<<<(unsigned)((4 * N + 255) / 256), 256, 0, st>>>(n, M, p, coef, scale, Ytab, Rm, mu);
   return hipGetLastError();
 }
 
