@@ -46,6 +46,27 @@ def test_features_match_oracle():
     s.close()
 
 
+@pytest.mark.parametrize("side,jitter,k", [(6, 0.0, 16), (5, 0.3, 8)])
+def test_features_match_oracle_beyond_one_wave(side, jitter, k):
+    """More bodies than lanes in a wave; on the unjittered lattice many neighbours are at
+    exactly equal distances, where both sides order by body index."""
+    _case(f"features lattice side={side} jitter={jitter} k={k}")
+    w = inputs.mhd_lattice(side=side, p=2, spacing=3.0, jitter=jitter, seed=3)
+    rng = np.random.default_rng(side)
+    q = rng.standard_normal((len(w["centres"]), 4))
+    w["quats"] = q / np.linalg.norm(q, axis=1, keepdims=True)
+    w["FT"] = rng.standard_normal((len(w["centres"]), 6))
+    s = rbm.solver_for(w)
+    info = s.learned_bind(k_nbr=k, hidden=16, n_hidden=1, capacity=64, batch_max=32)
+    FT = torch.as_tensor(np.asarray(w["FT"]), device="cuda")
+    X = torch.zeros((s.n, info["F"]), dtype=torch.float32, device="cuda")
+    s.learned_features(FT, X)
+    prob = oracle_problem(w, with_ops=False)
+    Xo = mlp.features(prob.c, prob.R, np.asarray(w["FT"]), _desc(w), k)
+    assert np.abs(X.cpu().numpy() - Xo).max() < 2e-6 * np.abs(Xo).max()
+    s.close()
+
+
 def test_forward_and_gradients_match_oracle():
     _case("mlp forward/backward vs oracle bf16")
     w = inputs.tiny(3, 5, seed=42)
