@@ -77,26 +77,26 @@ __global__ __launch_bounds__(256) void k_gemm_bf16(int m, int n, int k, const ui
       }
 }
 
-// Few rows (the per-body network at inference, small batches): one wave per 16x16 output
-// tile, operands read straight from global memory with the same MFMA layout and no LDS,
-// so a 64 x 256 product runs on 64 waves instead of 4 workgroups that each wait on every
-// K step.
+// Few rows (the per-body network at inference, small batches): one workgroup per 16x16
+// output tile, its four waves taking every fourth K step of 16 with operands read
+// straight from global memory (the same MFMA layout, no LDS staging), then summed in LDS
+// in wave order; a 64 x 256 product runs on 64 workgroups instead of 4 that each wait on
+// every K step.
 __global__ __launch_bounds__(256) void k_gemm_bf16_tile16(int m, int n, int k,
                                                           const uint16_t* __restrict__ A, long sa0,
                                                           long sa1, const uint16_t* __restrict__ B,
                                                           long sb0, long sb1, float* __restrict__ C,
                                                           int ldc, const float* __restrict__ bias,
                                                           float alpha, float beta) {
-  const int lane = threadIdx.x & 63;
+  __shared__ f4v part[4][64];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int tiles_n = (n + 15) / 16;
-  const int t = blockIdx.x * 4 + (threadIdx.x >> 6);
-  const int ti = t / tiles_n, tj = t - ti * tiles_n;
-  if (ti * 16 >= m) return;  // the whole wave
+  const int ti = blockIdx.x / tiles_n, tj = blockIdx.x - ti * tiles_n;
   const int lr = lane & 15, lk = 4 * (lane >> 4);
   const int ia = ti * 16 + lr, jb = tj * 16 + lr;
   f4v acc = (f4v){0.f, 0.f, 0.f, 0.f};
-#pragma unroll 4
-  for (int k0 = 0; k0 < k; k0 += 16) {
+#pragma unroll 2
+  for (int k0 = 16 * w; k0 < k; k0 += 64) {
     s4v av, bv;
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
@@ -106,11 +106,15 @@ __global__ __launch_bounds__(256) void k_gemm_bf16_tile16(int m, int n, int k,
     }
     acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av, bv, acc, 0, 0, 0);
   }
+  part[w][lane] = acc;
+  __syncthreads();
+  if (w != 0) return;
+  const f4v s = (part[0][lane] + part[1][lane]) + (part[2][lane] + part[3][lane]);
 #pragma unroll
   for (int e = 0; e < 4; ++e) {
     const int i = ti * 16 + lk + e, j = jb;
     if (i < m && j < n) {
-      float v = alpha * acc[e];
+      float v = alpha * s[e];
       if (bias) v += bias[j];
       if (beta != 0.f) v += beta * C[(long)i * ldc + j];
       C[(long)i * ldc + j] = v;
@@ -123,8 +127,8 @@ hipError_t launch_gemm_bf16(int m, int n, int k, const uint16_t* A, long sa0, lo
                             const float* bias, float alpha, float beta, hipStream_t st) {
   if (m <= 128) {
     const long tiles = (long)((m + 15) / 16) * ((n + 15) / 16);
-    k_gemm_bf16_tile16<<<(unsigned)((tiles + 3) / 4), 256, 0, st>>>(m, n, k, A, sa0, sa1, B, sb0, sb1, C,
-                                                                      ldc, bias, alpha, beta);
+    k_gemm_bf16_tile16<<<(unsigned)tiles, 256, 0, st>>>(m, n, k, A, sa0, sa1, B, sb0, sb1, C, ldc, bias,
+                                                         alpha, beta);
     return hipGetLastError();
   }
   dim3 grid((n + 63) / 64, (m + 63) / 64);
