@@ -4,6 +4,8 @@
 
 #include <algorithm>
 #include <cfloat>
+#include <chrono>
+#include <thread>
 #include <cmath>
 #include <type_traits>
 #include <cstdio>
@@ -799,15 +801,21 @@ static rbm_status norm_into(rbm_ctx* c, const double* w, double* out, size_t len
 // Wait for a value >= 0 (or NaN) that a kernel of the context's stream writes into pinned
 // host memory over the sentinel -1, reading it as soon as it lands instead of waiting
 // for the stream to drain; between reads the stream is checked for errors, and a
-// drained stream without the value is reported.
+// drained stream without the value is reported.  The host spins for the first 2 ms (an
+// iteration at up to ~10^5 points) and then polls every few tens of microseconds, so a
+// long iteration does not hold a CPU core.
 static rbm_status wait_pinned(rbm_ctx* c, volatile double* p, double* out) {
+  const auto t0 = std::chrono::steady_clock::now();
+  bool nap = false;
   for (unsigned it = 1;; ++it) {
     const double v = *p;
     if (v != -1.0) {
       *out = v;
       return RBM_OK;
     }
-    if ((it & 63) == 0) {
+    if (nap) std::this_thread::sleep_for(std::chrono::microseconds(20));
+    if ((it & 63) == 0 || nap) {
+      if (!nap && std::chrono::steady_clock::now() - t0 > std::chrono::milliseconds(2)) nap = true;
       const hipError_t q = hipStreamQuery(c->st);
       if (q == hipSuccess) {
         const double v2 = *p;
