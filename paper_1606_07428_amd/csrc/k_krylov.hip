@@ -44,12 +44,6 @@ __global__ __launch_bounds__(256) void k_dots_final(int nblk, const double* part
   }
 }
 
-hipError_t launch_dots_final(int kk, int nblk, const double* partial, double* h, double* hacc,
-                             hipStream_t st) {
-  k_dots_final<<<kk, 256, 0, st>>>(nblk, partial, h, hacc, 0);
-  return hipGetLastError();
-}
-
 hipError_t launch_dots_final_sqrt(int nblk, const double* partial, double* h, hipStream_t st) {
   k_dots_final<<<1, 256, 0, st>>>(nblk, partial, h, nullptr, 1);
   return hipGetLastError();
@@ -71,22 +65,6 @@ hipError_t launch_vupdate(int kk, size_t len, const double* V, size_t ldv, const
   return hipGetLastError();
 }
 
-// y = x * s (or x / s if invert; 0 if s == 0)
-__global__ void k_scale_copy(size_t len, const double* x, const double* s, int invert, double* y) {
-  const size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= len) return;
-  const double sv = *s;
-  double f = sv;
-  if (invert) f = sv != 0.0 ? 1.0 / sv : 0.0;
-  y[e] = x[e] * f;
-}
-
-hipError_t launch_scale_copy(size_t len, const double* x, const double* s, int invert, double* y,
-                             hipStream_t st) {
-  k_scale_copy<<<(unsigned)((len + 255) / 256), 256, 0, st>>>(len, x, s, invert, y);
-  return hipGetLastError();
-}
-
 __global__ void k_axpby(size_t len, double a, const double* x, double b, const double* y,
                         double* out) {
   const size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -97,35 +75,6 @@ __global__ void k_axpby(size_t len, double a, const double* x, double b, const d
 hipError_t launch_axpby(size_t len, double a, const double* x, double b, const double* y,
                         double* out, hipStream_t st) {
   k_axpby<<<(unsigned)((len + 255) / 256), 256, 0, st>>>(len, a, x, b, y, out);
-  return hipGetLastError();
-}
-
-// Column k of H (ldh rows, column-major) holds h_0..h_{k+1}; apply the previous
-// rotations, form the new one, update g, write |g_{k+1}| to resid.
-__global__ void k_givens(int k, int ldh, double* H, double* cs, double* sn, double* g,
-                         double* resid) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
-  double* h = H + (size_t)k * ldh;
-  for (int j = 0; j < k; ++j) {
-    const double t = cs[j] * h[j] + sn[j] * h[j + 1];
-    h[j + 1] = -sn[j] * h[j] + cs[j] * h[j + 1];
-    h[j] = t;
-  }
-  const double a = h[k], b = h[k + 1];
-  const double den = hypot(a, b);
-  const double c = den > 0.0 ? a / den : 1.0, s = den > 0.0 ? b / den : 0.0;
-  cs[k] = c;
-  sn[k] = s;
-  h[k] = den;
-  h[k + 1] = 0.0;
-  g[k + 1] = -s * g[k];
-  g[k] = c * g[k];
-  resid[0] = fabs(g[k + 1]);
-}
-
-hipError_t launch_givens(int k, int ldh, double* H, double* cs, double* sn, double* g,
-                         const double*, const double*, double* resid, hipStream_t st) {
-  k_givens<<<1, 64, 0, st>>>(k, ldh, H, cs, sn, g, resid);
   return hipGetLastError();
 }
 

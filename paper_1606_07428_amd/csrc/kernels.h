@@ -104,17 +104,11 @@ hipError_t launch_combine(int N, int M, int nsplit, const double* part, double c
 // ---- Krylov (k_krylov.hip) --------------------------------------------------------
 hipError_t launch_dots(int kk, size_t len, const double* V, size_t ldv, const double* w,
                        double* partial, int nblk, hipStream_t st);
-hipError_t launch_dots_final(int kk, int nblk, const double* partial, double* h, double* hacc,
-                             hipStream_t st);
 // w -= sum_j V[j] h[j]  (or w = sum_j V[j] h[j] if overwrite)
 hipError_t launch_vupdate(int kk, size_t len, const double* V, size_t ldv, const double* h,
                           double* w, int overwrite, hipStream_t st);
-hipError_t launch_scale_copy(size_t len, const double* x, const double* s, int invert, double* y,
-                             hipStream_t st);
 hipError_t launch_axpby(size_t len, double a, const double* x, double b, const double* y,
                         double* out, hipStream_t st);
-hipError_t launch_givens(int k, int ldh, double* H, double* cs, double* sn, double* g,
-                         const double* hcol, const double* hnext, double* resid, hipStream_t st);
 hipError_t launch_backsolve(int m, int ldh, const double* H, const double* g, double* y,
                             hipStream_t st);
 hipError_t launch_dots_final_sqrt(int nblk, const double* partial, double* h, hipStream_t st);

@@ -78,7 +78,7 @@ struct rbm_ctx {
   double* gB = nullptr;  // shared-shape GEMM operand (3N values)
   float* gZ = nullptr;   // shared-shape bf16 GEMM product (3N floats)
   // Krylov
-  double *V, *H, *cs, *sn, *g, *y, *htmp, *scal, *partial;
+  double *V, *H, *cs, *sn, *g, *y, *scal, *partial;
   // far field
   void* src;
   double* part;
@@ -337,7 +337,7 @@ static size_t layout(rbm_ctx* c, int nmax, bool assign) {
   }
   const int m = c->opt.max_iter;
   take(c->V, (size_t)(m + 1) * N3); take(c->H, (size_t)(m + 1) * (m + 1)); take(c->cs, m + 1);
-  take(c->sn, m + 1); take(c->g, m + 2); take(c->y, m + 2); take(c->htmp, m + 2);
+  take(c->sn, m + 1); take(c->g, m + 2); take(c->y, m + 2);
   take(c->scal, 64);
   take(c->partial, 3 * (size_t)(m + 2) * c->nblk);  // three regions for the fused Arnoldi step
   double* srcd = nullptr;
@@ -779,14 +779,6 @@ static rbm_status apply_AP(rbm_ctx* c, SolveState& S, int prec, const double* v,
   if ((s = far_traction(c, S, c->yb, 1, prec == 0 ? 0 : 1)) != RBM_OK) return s;
   HIPCHECK(launch_combine(N, c->M, c->far_nslots, c->part, 1.0, v, 1.0, nullptr, nullptr, 0.0, out, c->st));
   S.matvecs++;
-  return RBM_OK;
-}
-
-static rbm_status dot_into(rbm_ctx* c, int kk, const double* Vb, size_t ldv, const double* w,
-                           double* h, double* hacc) {
-  const size_t len = 3 * (size_t)c->n * c->M;
-  HIPCHECK(launch_dots(kk, len, Vb, ldv, w, c->partial, c->nblk, c->st));
-  HIPCHECK(launch_dots_final(kk, c->nblk, c->partial, h, hacc, c->st));
   return RBM_OK;
 }
 
@@ -1387,29 +1379,17 @@ static rbm_status magnetic_gmres(rbm_ctx* c, double eta, const double* b, double
   HIPCHECK(hipMemcpyAsync(r, b, len * sizeof(double), hipMemcpyDeviceToDevice, c->st));
   double rn = bn;
   for (int cycle = 0; cycle <= c->opt.max_restart; ++cycle) {
-    HIPCHECK(hipMemsetAsync(c->g, 0, (m + 2) * sizeof(double), c->st));
-    HIPCHECK(hipMemsetAsync(c->H, 0, (size_t)(m + 1) * (m + 1) * sizeof(double), c->st));
-    c->pinned[1] = rn;
-    HIPCHECK(hipMemcpyAsync(c->g, c->pinned + 1, sizeof(double), hipMemcpyHostToDevice, c->st));
-    HIPCHECK(launch_scale_copy(len, r, c->g, 1, c->V, c->st));
+    HIPCHECK(launch_gmres_init(len, r, rn, c->V, m + 2, c->g, (size_t)(m + 1) * (m + 1), c->H, c->st));
     int k;
     for (k = 0; k < m; ++k) {
-      double* vk = c->V + (size_t)k * len;
-      double* w = c->V + (size_t)(k + 1) * len;
-      if ((s = magnetic_apply(c, eta, vk, w)) != RBM_OK) return s;
-      double* hcol = c->H + (size_t)k * ldh;
-      HIPCHECK(launch_dots(k + 1, len, c->V, len, w, c->partial, c->nblk, c->st));
-      HIPCHECK(launch_dots_final(k + 1, c->nblk, c->partial, hcol, nullptr, c->st));
-      HIPCHECK(launch_vupdate(k + 1, len, c->V, len, hcol, w, 0, c->st));
-      HIPCHECK(launch_dots(k + 1, len, c->V, len, w, c->partial, c->nblk, c->st));
-      HIPCHECK(launch_dots_final(k + 1, c->nblk, c->partial, c->htmp, hcol, c->st));
-      HIPCHECK(launch_vupdate(k + 1, len, c->V, len, c->htmp, w, 0, c->st));
-      HIPCHECK(launch_dots(1, len, w, len, w, c->partial, c->nblk, c->st));
-      HIPCHECK(launch_dots_final_sqrt(c->nblk, c->partial, hcol + k + 1, c->st));
-      HIPCHECK(launch_scale_copy(len, w, hcol + k + 1, 1, w, c->st));
-      HIPCHECK(launch_givens(k, ldh, c->H, c->cs, c->sn, c->g, nullptr, nullptr, c->scal, c->st));
+      // w = V[k+1] = A V[k], then the fused Arnoldi step of the mobility GMRES
+      if ((s = magnetic_apply(c, eta, c->V + (size_t)k * len, c->V + (size_t)(k + 1) * len)) != RBM_OK)
+        return s;
+      c->pinned[16] = -1.0;
+      HIPCHECK(launch_arnoldi(k, len, c->V, len, c->partial, (size_t)(m + 2) * c->nblk, c->nblk, ldh, c->H,
+                              c->cs, c->sn, c->g, c->pinned_dev + 16, c->st));
       double res;
-      if ((s = read_scalar(c, c->scal, &res)) != RBM_OK) return s;
+      if ((s = wait_pinned(c, c->pinned + 16, &res)) != RBM_OK) return s;
       if (!std::isfinite(res)) return fail(RBM_E_DEVICE, "non-finite GMRES residual");
       ++*iters;
       if (res <= tol * bn) { ++k; break; }
