@@ -782,14 +782,6 @@ static rbm_status apply_AP(rbm_ctx* c, SolveState& S, int prec, const double* v,
   return RBM_OK;
 }
 
-// 2-norm of w[0, len) into out; len = 0 means a traction-sized vector (3 n M).
-static rbm_status norm_into(rbm_ctx* c, const double* w, double* out, size_t len = 0) {
-  if (len == 0) len = 3 * (size_t)c->n * c->M;
-  HIPCHECK(launch_dots(1, len, w, len, w, c->partial, c->nblk, c->st));
-  HIPCHECK(launch_dots_final_sqrt(c->nblk, c->partial, out, c->st));
-  return RBM_OK;
-}
-
 // Wait for a value >= 0 (or NaN) that a kernel of the context's stream writes into pinned
 // host memory over the sentinel -1, reading it as soon as it lands instead of waiting
 // for the stream to drain; between reads the stream is checked for errors, and a
@@ -811,13 +803,29 @@ static rbm_status wait_pinned(rbm_ctx* c, volatile double* p, double* out) {
       const hipError_t q = hipStreamQuery(c->st);
       if (q == hipSuccess) {
         const double v2 = *p;
-        if (v2 == -1.0) return fail(RBM_E_DEVICE, "GMRES residual estimate not written");
+        if (v2 == -1.0) return fail(RBM_E_DEVICE, "device result not written to pinned memory");
         *out = v2;
         return RBM_OK;
       }
       if (q != hipErrorNotReady) return fail(RBM_E_DEVICE, hipGetErrorString(q));
     }
   }
+}
+
+// ||w|| of w[0, len) (len = 0: a traction-sized vector) written by the norm kernel into
+// pinned slot `slot` over the sentinel -1; wait_pinned reads it.
+static rbm_status norm_to_pinned(rbm_ctx* c, const double* w, int slot, size_t len = 0) {
+  if (len == 0) len = 3 * (size_t)c->n * c->M;
+  c->pinned[slot] = -1.0;
+  HIPCHECK(launch_dots(1, len, w, len, w, c->partial, c->nblk, c->st));
+  HIPCHECK(launch_dots_final_sqrt(c->nblk, c->partial, c->pinned_dev + slot, c->st));
+  return RBM_OK;
+}
+
+static rbm_status read_norm(rbm_ctx* c, const double* w, double* v, size_t len = 0) {
+  rbm_status s;
+  if ((s = norm_to_pinned(c, w, 24, len)) != RBM_OK) return s;
+  return wait_pinned(c, c->pinned + 24, v);
 }
 
 static rbm_status read_scalar(rbm_ctx* c, const double* d, double* h) {
@@ -904,13 +912,13 @@ static rbm_status build_rhs(rbm_ctx* c, SolveState& S, const double* dFT, const 
   HIPCHECK(launch_moments(n, M, c->rho, c->X, c->W, c->cen, c->mom, st));
   HIPCHECK(launch_add_rigid(n, M, c->mom, c->X, c->cen, 1.0, c->b, st));
   S.matvecs++;
-  // ||b|| and ||rho|| read back together
-  if ((s = norm_into(c, c->b, c->scal + 6)) != RBM_OK) return s;
-  if ((s = norm_into(c, c->rho, c->scal + 7)) != RBM_OK) return s;
-  HIPCHECK(hipMemcpyAsync(c->pinned, c->scal + 6, 2 * sizeof(double), hipMemcpyDeviceToHost, st));
-  HIPCHECK(hipStreamSynchronize(st));
-  *bnorm = c->pinned[0];
-  if (rhonorm) *rhonorm = c->pinned[1];
+  // ||b|| and ||rho|| in one round trip
+  if ((s = norm_to_pinned(c, c->b, 24)) != RBM_OK) return s;
+  if ((s = norm_to_pinned(c, c->rho, 25)) != RBM_OK) return s;
+  double rh;
+  if ((s = wait_pinned(c, c->pinned + 24, bnorm)) != RBM_OK) return s;
+  if ((s = wait_pinned(c, c->pinned + 25, &rh)) != RBM_OK) return s;
+  if (rhonorm) *rhonorm = rh;
   if (!std::isfinite(*bnorm)) return fail(RBM_E_INVAL, "non-finite right-hand side");
   return RBM_OK;
 }
@@ -999,8 +1007,7 @@ static rbm_status solve_impl(rbm_ctx* c, const double* dFT, double* dVW, rbm_sol
       mu_zero = false;
     } else {
       if ((s = residual_exact(c, S, c->mu, c->r, c->t1)) != RBM_OK) return s;
-      if ((s = norm_into(c, c->r, c->scal + 2)) != RBM_OK) return s;
-      if ((s = read_scalar(c, c->scal + 2, &rn)) != RBM_OK) return s;
+      if ((s = read_norm(c, c->r, &rn)) != RBM_OK) return s;
     }
     if (outer == 0 && bnorm > 0.0) {
       if (learned_active) {
@@ -1008,16 +1015,14 @@ static rbm_status solve_impl(rbm_ctx* c, const double* dFT, double* dVW, rbm_sol
         if (c->bd_ratio < 0.0) {
           if ((s = residual_exact(c, S, c->t2, c->t1, c->V)) != RBM_OK) return s;  // V is free before GMRES
           double rbd;
-          if ((s = norm_into(c, c->t1, c->scal + 3)) != RBM_OK) return s;
-          if ((s = read_scalar(c, c->scal + 3, &rbd)) != RBM_OK) return s;
+          if ((s = read_norm(c, c->t1, &rbd)) != RBM_OK) return s;
           c->bd_ratio = rbd / bnorm;
         }
         if (!(rn <= c->bd_ratio * bnorm)) {
           fallback = 1;
           HIPCHECK(hipMemcpyAsync(c->mu, c->t2, len * sizeof(double), hipMemcpyDeviceToDevice, st));
           if ((s = residual_exact(c, S, c->mu, c->r, c->t1)) != RBM_OK) return s;
-          if ((s = norm_into(c, c->r, c->scal + 2)) != RBM_OK) return s;
-          if ((s = read_scalar(c, c->scal + 2, &rn)) != RBM_OK) return s;
+          if ((s = read_norm(c, c->r, &rn)) != RBM_OK) return s;
           c->bd_ratio = rn / bnorm;
         }
       } else if (guess_used == RBM_GUESS_BLOCKDIAG) {
@@ -1370,8 +1375,7 @@ static rbm_status magnetic_gmres(rbm_ctx* c, double eta, const double* b, double
   const int m = c->opt.max_iter, ldh = m + 1;
   rbm_status s;
   double bn;
-  if ((s = norm_into(c, b, c->scal + 4, len)) != RBM_OK) return s;
-  if ((s = read_scalar(c, c->scal + 4, &bn)) != RBM_OK) return s;
+  if ((s = read_norm(c, b, &bn, len)) != RBM_OK) return s;
   HIPCHECK(hipMemsetAsync(x, 0, len * sizeof(double), c->st));
   *iters = 0;
   if (bn == 0.0) return RBM_OK;
@@ -1401,8 +1405,7 @@ static rbm_status magnetic_gmres(rbm_ctx* c, double eta, const double* b, double
     // true residual r = b - A x
     if ((s = magnetic_apply(c, eta, x, c->mphi)) != RBM_OK) return s;
     HIPCHECK(launch_axpby(len, 1.0, b, -1.0, c->mphi, r, c->st));
-    if ((s = norm_into(c, r, c->scal + 4, len)) != RBM_OK) return s;
-    if ((s = read_scalar(c, c->scal + 4, &rn)) != RBM_OK) return s;
+    if ((s = read_norm(c, r, &rn, len)) != RBM_OK) return s;
     if (rn <= tol * bn) return RBM_OK;
   }
   return fail(RBM_E_NOCONV, "magnetic GMRES did not reach tol");
