@@ -68,10 +68,11 @@ def _cpu_baseline(w, budget_s):
 
 
 def _kernel_source_hash():
-    """sha256 of the far-sum kernel's sources (the kernel file and its pair arithmetic)."""
+    """sha256 of the far-sum kernel's sources (the kernel file, its pair arithmetic and its
+    source-chunk plan)."""
     import hashlib
     h = hashlib.sha256()
-    for name in ("k_far.hip", "pair.h"):
+    for name in ("k_far.hip", "pair.h", "far_plan.h"):
         with open(os.path.join(ROOT, "paper_1606_07428_amd", "csrc", name), "rb") as f:
             h.update(f.read())
     return h.hexdigest()

@@ -21,6 +21,7 @@
 // overlaps the block's body range takes the per-lane masked path.
 #include "common.h"
 #include "kernels.h"
+#include "far_plan.h"
 #include "pair.h"
 
 namespace rbm {
@@ -140,20 +141,6 @@ __global__ __launch_bounds__(256) void k_far(int N, int M, const T* __restrict__
 }
 
 constexpr int kTPL = 1;
-
-// Source chunks of the nsplit slots: s1 = nsplit/2 long chunks of c1 sources holding
-// 85% of them, then nsplit - s1 short chunks of c2 sharing the rest.
-struct FarChunks {
-  int s1, c1, c2;
-};
-static FarChunks far_chunks(int N, int nsplit) {
-  if (nsplit < 2) return {0, N, N};
-  const int s1 = nsplit / 2, s2 = nsplit - s1;
-  const long c1 = std::min((17L * N + 20L * s1 - 1) / (20L * s1), (long)N / s1);
-  const long rest = N - s1 * c1;
-  const long c2 = std::max(1L, (rest + s2 - 1) / s2);
-  return {s1, (int)c1, (int)c2};
-}
 
 template <typename T>
 hipError_t launch_far(int kind, int N, int M, const T* tx, const T* nrm, const void* src,
