@@ -225,29 +225,32 @@ template hipError_t launch_pack_sources<float>(int, int, const double*, const do
 // One thread per (component, point): the slot sum over the split is the memory-bound
 // part, so it gets 3N threads and four independent accumulators (slots s = 4k + j go
 // to accumulator j, combined as ((j0 + j1) + (j2 + j3))).  out may be a, not b_body.
-__global__ void k_combine(int N, int M, int nsplit, const double* __restrict__ part, double cp,
-                          const double* a, double ca, const double* __restrict__ bb,
-                          const double* __restrict__ Rm, double cb, double* out) {
-  const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= 3 * N) return;
+// 64 outputs per workgroup: wave q of the four sums slots s = q, q + 4, ... of them in
+// increasing s (each load a coalesced 512-byte segment), and wave 0 adds the four sums as
+// (s0 + s1) + (s2 + s3), so every output is the same as with one thread and four
+// round-robin accumulators, with four times the loads in flight.
+__global__ __launch_bounds__(256) void k_combine(int N, int M, int nsplit, const double* __restrict__ part,
+                                                 double cp, const double* a, double ca,
+                                                 const double* __restrict__ bb,
+                                                 const double* __restrict__ Rm, double cb, double* out) {
+  __shared__ double red[4][64];
+  const int lane = threadIdx.x & 63, q = threadIdx.x >> 6;
+  const int t = blockIdx.x * 64 + lane;
+  const bool act = t < 3 * N;
+  if (part) {
+    double sq = 0.0;
+    if (act) {
+      const size_t stride = 3 * (size_t)N;
+      const double* p = part + t;
+      for (int s = q; s < nsplit; s += 4) sq += p[(size_t)s * stride];
+    }
+    red[q][lane] = sq;
+  }
+  __syncthreads();
+  if (q != 0 || !act) return;
   const int c = t / N, g = t - c * N;
   double v = 0.0;
-  if (part) {
-    const size_t stride = 3 * (size_t)N;
-    const double* p = part + t;
-    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
-    int s = 0;
-    for (; s + 4 <= nsplit; s += 4) {
-      s0 += p[(size_t)s * stride];
-      s1 += p[(size_t)(s + 1) * stride];
-      s2 += p[(size_t)(s + 2) * stride];
-      s3 += p[(size_t)(s + 3) * stride];
-    }
-    if (s < nsplit) s0 += p[(size_t)s * stride];
-    if (s + 1 < nsplit) s1 += p[(size_t)(s + 1) * stride];
-    if (s + 2 < nsplit) s2 += p[(size_t)(s + 2) * stride];
-    v = cp * ((s0 + s1) + (s2 + s3));
-  }
+  if (part) v = cp * ((red[0][lane] + red[1][lane]) + (red[2][lane] + red[3][lane]));
   if (bb) {
     const double* R = Rm + 9 * (g / M) + 3 * c;
     v += cb * (R[0] * bb[g] + R[1] * bb[N + g] + R[2] * bb[2 * (size_t)N + g]);
@@ -259,7 +262,7 @@ __global__ void k_combine(int N, int M, int nsplit, const double* __restrict__ p
 hipError_t launch_combine(int N, int M, int nsplit, const double* part, double cp,
                           const double* a, double ca, const double* b_body, const double* Rm,
                           double cb, double* out, hipStream_t st) {
-  k_combine<<<(3 * N + 255) / 256, 256, 0, st>>>(N, M, nsplit, part, cp, a, ca, b_body, Rm, cb, out);
+  k_combine<<<(3 * N + 63) / 64, 256, 0, st>>>(N, M, nsplit, part, cp, a, ca, b_body, Rm, cb, out);
   return hipGetLastError();
 }
 
