@@ -1,24 +1,29 @@
 """Benchmark of the mobility solve on one MI355X.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload random64]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload dense4000]
     python bench.py --learned-experiment [--workload sediment512]
 
 A step is one full mobility solve (incident density, right-hand side, GMRES to the
 relative residual tolerance 1e-8, velocities) with the loads already resident in
 HBM; setup (singular operators, block inverses) happens once before timing.
 
-Default mode (one JSON line):
-  1. a mixed-precision context with the learned warm start runs a short RK4
-     trajectory from the workload's configuration, capturing every stage solve, and
-     trains its network on them;
-  2. at the configuration the trajectory reached (not in the training data) it
-     times K solves each of: plain float64 with the block-diagonal guess (this is
-     ``value``: off-body pair interactions evaluated by all of the solve's sums per
-     second of wall time), mixed precision with the block-diagonal guess, and mixed
-     precision with the learned guess;
-  3. the roofline of the dominant kernel (float64 traction sum; HIP events on the
-     library stream), that of the float32 traction sum of the mixed solves
-     (``roofline_fp32``), and the FP64 NumPy oracle's pair rate on the host.
+Default mode (one JSON line), on the 4000-body suspension at 20 % volume fraction with
+surfaces 0.1 apart (p = 12, 1.25 M points, near-singular upsampling of order 24 for near
+body pairs):
+  1. a precision-form context (float32 inner far sums by the fast multipole method of
+     order 10, float32 block preconditioner, float64 refinement residuals) runs a short RK4
+     trajectory from the configuration, capturing every stage solve, and trains its warm
+     start network on them;
+  2. at the configuration the trajectory reached (not in the training data) it times K
+     solves of the precision form with the learned guess (``ms_per_step``); then, at the
+     same state, a stated smaller count of precision-form solves with the block-diagonal
+     guess and of plain float64 solves with the block-diagonal guess (float64 direct sums
+     throughout);
+  3. ``value`` is the off-body pair interactions the float64 solve evaluates divided by the
+     learned precision-form solve's time (the float64 solve's work delivered per second);
+     ``roofline`` is the float64 traction kernel of the timed solves (their exact residual
+     sums; HIP events on the library stream); ``cpu_baseline`` is the FP64 NumPy oracle's
+     traction sum on a sample of targets, threaded over the host's cores.
 --learned-experiment: paired learned-vs-block-diagonal iteration counts along a
 trajectory (train on the first steps, evaluate on the following ones).
 """
@@ -39,14 +44,36 @@ FP64_PEAK_TFLOPS = 78.6      # MI355X vector FP64
 FP32_PEAK_TFLOPS = 157.3     # MI355X vector FP32
 TRACTION_FLOPS_PER_PAIR = 30
 
+# Per workload: near-singular upsampling order (0 = plain smooth rule), fast multipole order
+# of the inner far sums (0 = direct float32 sums) and RK4 steps of the training trajectory.
+WORKLOAD_DEFAULTS = {
+    "dense4000": (24, 10, 2),
+    "dense512": (24, 0, 4),
+    "ellipsoids1000": (0, 10, 2),
+    "sediment512": (0, 0, 4),
+    "random64": (0, 0, 8),
+}
+
 
 def _log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def _cpu_baseline(w, budget_s):
-    """Oracle traction sum (float64 NumPy) on a bounded sample of targets of the
-    same workload; returns Gpairs/s on the host."""
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def _cpu_baseline(w, budget_s, threads):
+    """Oracle traction sum (float64 NumPy) on a bounded sample of targets of the same
+    workload, the targets split over `threads` host threads; Gpairs/s on the host."""
+    from concurrent.futures import ThreadPoolExecutor
     from oracle import farfield as ff
     from tests.helpers import oracle_problem  # geometry only, no singular operators
     prob = oracle_problem(w, with_ops=False)
@@ -54,17 +81,30 @@ def _cpu_baseline(w, budget_s):
     mu = rng.standard_normal((prob.N, 3))
     q = prob.w[:, None] * mu
     order = rng.permutation(prob.N)
-    done, pairs = 0, 0.0
+    chunk = 8
+
+    def work(k):
+        done = pairs = 0
+        t0 = time.perf_counter()
+        pos = k * chunk
+        while time.perf_counter() - t0 < budget_s and pos < prob.N:
+            idx = order[pos:pos + chunk]
+            ff.traction_sum(prob.X[idx], prob.Nn[idx], prob.X, q, prob.body[idx], prob.body)
+            pairs += len(idx) * (prob.N - prob.M)
+            done += len(idx)
+            pos += threads * chunk
+        return done, pairs
+
     t0 = time.perf_counter()
-    while time.perf_counter() - t0 < budget_s and done < prob.N:
-        idx = order[done:done + 64]
-        ff.traction_sum(prob.X[idx], prob.Nn[idx], prob.X, q, prob.body[idx], prob.body)
-        pairs += len(idx) * (prob.N - prob.M)
-        done += len(idx)
+    with ThreadPoolExecutor(threads) as ex:
+        res = list(ex.map(work, range(threads)))
     dt = time.perf_counter() - t0
-    return {"value": pairs / dt / 1e9, "unit": "Gpairs/s", "cores": 1, "kind": "oracle",
-            "sample": f"oracle float64 traction sum at {done} of {prob.N} targets against all "
-                      f"{prob.N} sources ({pairs:.3e} pairs, {dt:.1f} s, NumPy single thread)"}
+    done = sum(r[0] for r in res)
+    pairs = float(sum(r[1] for r in res))
+    return {"value": pairs / dt / 1e9, "unit": "Gpairs/s", "cores": threads, "kind": "oracle",
+            "cpu_model": _cpu_model(), "host_cpus": os.cpu_count(),
+            "sample": f"oracle float64 traction sum at {done} of {prob.N} targets against all {prob.N} "
+                      f"sources ({pairs:.3e} pairs, {dt:.1f} s, NumPy in {threads} threads)"}
 
 
 def _kernel_source_hash():
@@ -99,7 +139,11 @@ def _timed(torch, solver, FT, VW, steps, warmup):
         solver.solve_dev(FT, VW)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    infos = [solver.solve_dev(FT, VW) for _ in range(steps)]
+    infos = []
+    for k in range(steps):
+        infos.append(solver.solve_dev(FT, VW))
+        if steps > 4 and solver.N > 200_000:
+            _log(f"  solve {k + 1}/{steps}: {infos[-1]['ms_total']:.0f} ms, {infos[-1]['iters']} it")
     torch.cuda.synchronize()
     return time.perf_counter() - t0, infos
 
@@ -118,15 +162,19 @@ def _dt_rule(VW):
     return 0.02 / max(np.abs(v - v.mean(axis=0)).max(), 1e-12)
 
 
-def _train_on_trajectory(rbm, torch, w, FT, tol, steps, epochs, lr, precision, p_up=0, near_factor=5.0):
+def _train_on_trajectory(rbm, torch, w, FT, tol, steps, epochs, lr, precision, p_up=0, near_factor=5.0,
+                         fmm_order=0):
+    t0 = time.perf_counter()
     s = rbm.solver_for(w, tol=tol, precision=precision, guess=rbm.GUESS_BLOCKDIAG, p_up=p_up,
-                       near_factor=near_factor)
+                       near_factor=near_factor, fmm_order=fmm_order)
     s.learned_bind(k_nbr=8, hidden=256, n_hidden=3, capacity=max(4 * steps * s.n, 1),
                    batch_max=1024, seed=7)
+    torch.cuda.synchronize()
+    setup_s = time.perf_counter() - t0
     VW = torch.zeros_like(FT)
     s.solve_dev(FT, VW)
     dt = _dt_rule(VW.cpu().numpy())
-    _log(f"training trajectory: dt {dt:.4g}, {steps} RK4 steps")
+    _log(f"training trajectory: setup {setup_s:.1f} s, dt {dt:.4g}, {steps} RK4 steps")
     s.learned_set_capture(True)
     t0 = time.perf_counter()
     for k in range(steps):
@@ -143,119 +191,140 @@ def _train_on_trajectory(rbm, torch, w, FT, tol, steps, epochs, lr, precision, p
     t_train = time.perf_counter() - t0
     return s, dt, {"trajectory_steps": steps, "dt": dt, "samples": s.learned_info()["samples"],
                    "epochs": epochs, "loss_first_epoch": loss0, "loss_last_epoch": loss,
-                   "trajectory_s": t_traj, "train_s": t_train}
+                   "setup_s": setup_s, "trajectory_s": t_traj, "train_s": t_train}
+
+
+def _form_record(prefix, dt, infos, steps, warmup):
+    med, iqr = _spread(infos)
+    i = infos[-1]
+    return {f"{prefix}_ms": dt / steps * 1e3, f"{prefix}_timed_solves": steps, f"{prefix}_warmup": warmup,
+            f"{prefix}_ms_median": med, f"{prefix}_ms_iqr": iqr, f"{prefix}_iters": i["iters"],
+            f"{prefix}_matvecs": i["matvecs"], f"{prefix}_refinements": i["refinements"],
+            f"{prefix}_rel_residual": i["rel_residual"], f"{prefix}_init_rel_residual": i["init_rel_residual"],
+            f"{prefix}_fallback": i["fallback_used"], f"{prefix}_fp64_cycles": i["fp64_cycles"],
+            f"{prefix}_traction64_launches": i["n_traction"], f"{prefix}_fmm_applies": i["fmm_applies"],
+            f"{prefix}_near_ms": i["ms_near"]}
 
 
 def main_bench(args):
     import torch
     from paper_1606_07428_amd import inputs, rbm
 
+    t_start = time.perf_counter()
     w = inputs.workload(args.workload)
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     n = len(w["shape_id"])
-    _log(f"workload {args.workload}: n={n} p={w['p']}")
+    p_up, fmm, _ = WORKLOAD_DEFAULTS.get(args.workload, (0, 0, 4))
+    p_up = p_up if args.p_up is None else args.p_up
+    fmm = fmm if args.fmm is None else args.fmm
+    points = int(n * 2 * w["p"] * (w["p"] + 1))
+    _log(f"workload {args.workload}: n={n} p={w['p']} points={points} p_up={p_up} fmm={fmm} "
+         f"({time.perf_counter() - t_start:.1f} s)")
     FT = torch.as_tensor(np.asarray(w["FT"], dtype=np.float64), device=dev)
     VW = torch.zeros_like(FT)
 
-    learned = None
-    if not args.no_learned:
-        sl, dt, learned = _train_on_trajectory(rbm, torch, w, FT, args.tol, args.train_steps,
-                                               args.epochs, 1e-3, rbm.MIXED_FP32)
-        cen, quat = sl.bodies()
-        _log(f"trained on {learned['samples']} samples, loss {learned['loss_first_epoch']:.3e} -> "
-             f"{learned['loss_last_epoch']:.3e}")
-    else:
-        cen, quat = np.asarray(w["centres"]), np.asarray(w["quats"])
+    # 1. the learned warm start, trained on the workload's own RK4 trajectory
+    sl, dt, learned = _train_on_trajectory(rbm, torch, w, FT, args.tol, args.train_steps, args.epochs, 1e-3,
+                                           rbm.MIXED_FP32, p_up=p_up, fmm_order=fmm)
+    cen, quat = sl.bodies()
+    _log(f"trained on {learned['samples']} samples, loss {learned['loss_first_epoch']:.3e} -> "
+         f"{learned['loss_last_epoch']:.3e} ({time.perf_counter() - t_start:.1f} s)")
 
+    # 2a. the subject: precision form + learned guess, K timed solves
+    sl.set_guess_mode(rbm.GUESS_LEARNED)
+    dtl, infl = _timed(torch, sl, FT, VW, args.steps, args.warmup)
+    VWl = VW.cpu().numpy().copy()
+    _log(f"mixed + learned: {dtl / args.steps * 1e3:.1f} ms/solve, {infl[-1]['iters']} it, "
+         f"fallback {infl[-1]['fallback_used']} ({time.perf_counter() - t_start:.1f} s)")
+    # 2b. precision form + block-diagonal guess, same state
+    sl.set_guess_mode(rbm.GUESS_BLOCKDIAG)
+    dtb, infb = _timed(torch, sl, FT, VW, args.aux_steps, 1)
+    VWb = VW.cpu().numpy().copy()
+    _log(f"mixed + block-diagonal: {dtb / args.aux_steps * 1e3:.1f} ms/solve, {infb[-1]['iters']} it "
+         f"({time.perf_counter() - t_start:.1f} s)")
+    sl.close()
+    del sl
+    torch.cuda.empty_cache()
+    # 2c. plain float64 + block-diagonal guess, same state
     t0 = time.perf_counter()
-    s64 = rbm.solver_for(w, tol=args.tol, precision=rbm.FP64, guess=rbm.GUESS_BLOCKDIAG)
+    s64 = rbm.solver_for(w, tol=args.tol, precision=rbm.FP64, guess=rbm.GUESS_BLOCKDIAG, p_up=p_up)
     s64.set_bodies(w["shape_id"], cen, quat)
     torch.cuda.synchronize()
-    setup_s = time.perf_counter() - t0
-    dt64, infos = _timed(torch, s64, FT, VW, args.steps, args.warmup)
+    setup64 = time.perf_counter() - t0
+    dt64, inf64 = _timed(torch, s64, FT, VW, args.fp64_steps, 0)
     VW64 = VW.cpu().numpy().copy()
-    _log(f"fp64 block-diagonal: {dt64 / args.steps * 1e3:.3f} ms/solve, iters {infos[-1]['iters']}")
+    _log(f"fp64 + block-diagonal: {dt64 / args.fp64_steps * 1e3:.1f} ms/solve, {inf64[-1]['iters']} it "
+         f"({time.perf_counter() - t_start:.1f} s)")
+    s64.close()
+    del s64
+    torch.cuda.empty_cache()
 
-    pairs = sum(i["far_pairs"] for i in infos)
-    ms_trac = sum(i["ms_traction"] for i in infos)
-    n_trac = sum(i["n_traction"] for i in infos)
-    ppl = infos[-1]["pairs_per_launch"]
+    ms_l = dtl / args.steps * 1e3
+    ms_64 = dt64 / args.fp64_steps * 1e3
+    pairs64 = inf64[-1]["far_pairs"]
+    ppl = infl[-1]["pairs_per_launch"]
+    # roofline: the float64 traction launches of the timed learned solves
+    ms_trac = sum(i["ms_traction"] for i in infl)
+    n_trac = sum(i["n_traction"] for i in infl)
     trac_avg_s = ms_trac / max(n_trac, 1) / 1e3
     achieved = TRACTION_FLOPS_PER_PAIR * ppl / trac_avg_s / 1e12
-    points = int(n * 2 * w["p"] * (w["p"] + 1))
     kernel = "k_far<double, traction>"
     traffic = _traffic(kernel, args.workload)
+    vscale = np.abs(VW64).max()
+    solve = {"fp64_solve_far_pairs": pairs64, "pairs_per_launch": ppl}
+    solve.update(_form_record("mixed_learned", dtl, infl, args.steps, args.warmup))
+    solve.update(_form_record("mixed_bd", dtb, infb, args.aux_steps, 1))
+    solve.update(_form_record("fp64_bd", dt64, inf64, args.fp64_steps, 0))
+    solve.update({
+        "speedup_mixed_learned_vs_fp64": ms_64 / ms_l,
+        "speedup_mixed_bd_vs_fp64": ms_64 / (dtb / args.aux_steps * 1e3),
+        "mixed_learned_vs_fp64_velocity_rel_err": float(np.abs(VWl - VW64).max() / vscale),
+        "mixed_bd_vs_fp64_velocity_rel_err": float(np.abs(VWb - VW64).max() / vscale),
+        "solves_per_s": args.steps / dtl,
+        "matvecs_per_s": sum(i["matvecs"] for i in infl) / dtl,
+        "fp64_solves_per_s": args.fp64_steps / dt64,
+        "fp64_matvecs_per_s": sum(i["matvecs"] for i in inf64) / dt64,
+        "fp64_solve_gpairs_per_s": pairs64 / (ms_64 / 1e3) / 1e9,
+        "traction64_gpairs_per_s": ppl / trac_avg_s / 1e9,
+        "fp64_setup_s": setup64,
+        "near_pairs": infl[-1]["near_pairs"], "fmm_level": infl[-1]["fmm_level"],
+    })
+    if infl[-1]["fmm_applies"]:
+        solve["fmm_apply_ms_avg"] = sum(i["ms_traction32"] for i in infl) / sum(i["n_traction32"] for i in infl)
     result = {
         "metric": METRIC,
-        "value": pairs / dt64 / 1e9,
+        "value": pairs64 / (ms_l / 1e3) / 1e9,
         "unit": "Gpairs/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": dt64 / args.steps * 1e3,
+        "ms_per_step": ms_l,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": "f64+f32",
         "data": "synthetic",
-        "config": {"workload": args.workload, "bodies": n, "p": w["p"],
-                   "points": int(n * 2 * w["p"] * (w["p"] + 1)), "tol": args.tol,
-                   "precision": "fp64", "guess": "block-diagonal",
-                   "state": f"after {args.train_steps} RK4 steps" if learned else "initial"},
+        "config": {"workload": args.workload, "bodies": n, "p": w["p"], "points": points, "tol": args.tol,
+                   "step": "precision form (float32 inner sums"
+                           + (f" by the fast multipole method of order {fmm}" if fmm else "")
+                           + ", float32 preconditioner, float64 refinement residuals) + learned guess",
+                   "near_singular_order": p_up,
+                   "value": "off-body pairs of the float64 solve / time of the step",
+                   "state": f"after {args.train_steps} RK4 steps (trained on their stage solves)"},
         "roofline": {"bound": "alu", "kernel": kernel,
                      "achieved": achieved, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / FP64_PEAK_TFLOPS,
                      "traffic": traffic["bytes_per_launch"] if traffic else None,
                      "traffic_detail": traffic,
-                     "launch_ms": trac_avg_s * 1e3, "pairs_per_launch": ppl,
+                     "launch_ms": trac_avg_s * 1e3, "launches": n_trac, "pairs_per_launch": ppl,
                      "flops_per_pair": TRACTION_FLOPS_PER_PAIR},
-        "solve": {"fp64_bd_ms": dt64 / args.steps * 1e3, "fp64_bd_iters": infos[-1]["iters"],
-                  "fp64_bd_ms_median": _spread(infos)[0], "fp64_bd_ms_iqr": _spread(infos)[1],
-                  "fp64_bd_matvecs": infos[-1]["matvecs"],
-                  "fp64_bd_rel_residual": infos[-1]["rel_residual"],
-                  "solves_per_s": args.steps / dt64,
-                  "matvecs_per_s": sum(i["matvecs"] for i in infos) / dt64,
-                  "traction_gpairs_per_s": ppl / trac_avg_s / 1e9, "setup_s": setup_s},
+        "solve": solve,
+        "learned": learned,
     }
-    s64.close()
-    del s64
-    torch.cuda.empty_cache()
-
-    if learned is not None:
-        out = result["solve"]
-        for name, g in (("mixed_bd", rbm.GUESS_BLOCKDIAG), ("mixed_learned", rbm.GUESS_LEARNED)):
-            sl.set_guess_mode(g)
-            dtm, inf = _timed(torch, sl, FT, VW, args.steps, args.warmup)
-            err = float(np.abs(VW.cpu().numpy() - VW64).max() / np.abs(VW64).max())
-            med, iqr = _spread(inf)
-            out.update({f"{name}_ms": dtm / args.steps * 1e3, f"{name}_iters": inf[-1]["iters"],
-                        f"{name}_ms_median": med, f"{name}_ms_iqr": iqr,
-                        f"{name}_refinements": inf[-1]["refinements"],
-                        f"{name}_rel_residual": inf[-1]["rel_residual"],
-                        f"{name}_init_rel_residual": inf[-1]["init_rel_residual"],
-                        f"{name}_fallback": inf[-1]["fallback_used"],
-                        f"{name}_vs_fp64_velocity_rel_err": err})
-            _log(f"{name}: {dtm / args.steps * 1e3:.3f} ms/solve, iters {inf[-1]['iters']}")
-            if name == "mixed_bd":
-                # float32 traction launches of the mixed solves (inner iterations, right-hand side)
-                ms32 = sum(i["ms_traction32"] for i in inf)
-                n32 = sum(i["n_traction32"] for i in inf)
-                if n32:
-                    avg32 = ms32 / n32 / 1e3
-                    a32 = TRACTION_FLOPS_PER_PAIR * ppl / avg32 / 1e12
-                    result["roofline_fp32"] = {
-                        "bound": "alu",
-                        "kernel": "k_far<float, traction>",
-                        "achieved": a32, "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
-                        "frac": a32 / FP32_PEAK_TFLOPS, "launch_ms": avg32 * 1e3, "launches": n32,
-                        "pairs_per_launch": ppl, "flops_per_pair": TRACTION_FLOPS_PER_PAIR}
-        out["speedup_mixed_learned_vs_fp64"] = out["fp64_bd_ms"] / out["mixed_learned_ms"]
-        result["learned"] = learned
-        sl.close()
-
     if not args.no_cpu:
-        result["cpu_baseline"] = _cpu_baseline(w, args.cpu_budget)
+        result["cpu_baseline"] = _cpu_baseline(w, args.cpu_budget, max(1, min(16, os.cpu_count() or 1)))
+    _log(f"done ({time.perf_counter() - t_start:.1f} s)")
     print(json.dumps(result), flush=True)
 
 
@@ -336,14 +405,14 @@ def main_compare(args):
         _log(f"training workload {args.learned_from} generated")
         FTs = torch.as_tensor(np.asarray(ws["FT"], dtype=np.float64), device=dev)
         st, _, learned = _train_on_trajectory(rbm, torch, ws, FTs, args.tol, args.train_steps or 25,
-                                              args.epochs, 1e-3, rbm.MIXED_FP32, args.p_up, args.near_factor)
+                                              args.epochs, 1e-3, rbm.MIXED_FP32, args.p_up or 0, args.near_factor)
         params = st.learned_params()
         out["learned_transfer"] = dict(learned, trained_on=args.learned_from)
         st.close()
         del st
         torch.cuda.empty_cache()
         _log(f"trained on {args.learned_from}: {learned}")
-    pu = args.p_up
+    pu = args.p_up or 0
     bd, zero = rbm.GUESS_BLOCKDIAG, rbm.GUESS_ZERO
     forms = [("fp64", rbm.FP64, False, pu, 0, bd), ("mixed_fp32", rbm.MIXED_FP32, False, pu, 0, bd),
              ("mixed_bf16", rbm.MIXED_BF16, False, pu, 0, bd)]
@@ -518,7 +587,11 @@ def main():
     ap.add_argument("--eval-steps", type=int, default=10)
     ap.add_argument("--epochs", type=int, default=60)
     ap.add_argument("--precision", default="fp32", choices=["fp64", "fp32", "bf16"])
-    ap.add_argument("--cpu-budget", type=float, default=12.0)
+    ap.add_argument("--cpu-budget", type=float, default=10.0)
+    ap.add_argument("--aux-steps", type=int, default=2,
+                    help="timed solves of the precision form with the block-diagonal guess")
+    ap.add_argument("--fp64-steps", type=int, default=1,
+                    help="timed plain float64 solves (no warm-up solve)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-learned", action="store_true")
     ap.add_argument("--learned-experiment", action="store_true")
@@ -529,9 +602,9 @@ def main():
     ap.add_argument("--learned-from", default=None,
                     help="with --compare: train the warm start on this workload's trajectory and "
                          "add a mixed fp32 + learned solve (same p and feature layout)")
-    ap.add_argument("--p-up", type=int, default=0,
-                    help="compare mode: near-singular upsampling order (0 = off); adds a plain-rule "
-                         "float64 reference solve")
+    ap.add_argument("--p-up", type=int, default=None,
+                    help="near-singular upsampling order (0 = off; default per workload); in compare mode "
+                         "a plain-rule float64 reference solve is added")
     ap.add_argument("--near-factor", type=float, default=5.0,
                     help="compare mode: kappa of the near test (mean node spacings)")
     ap.add_argument("--retrain-every", type=int, default=0,
@@ -539,9 +612,9 @@ def main():
                          "network every this many RK4 steps (0 = train once)")
     ap.add_argument("--retrain-epochs", type=int, default=3,
                     help="learned experiment: epochs of each fine-tuning")
-    ap.add_argument("--fmm", type=int, default=0,
-                    help="compare mode: add mixed forms whose inner iterations use the fast multipole "
-                         "far field of this order")
+    ap.add_argument("--fmm", type=int, default=None,
+                    help="fast multipole order of the inner far sums (default per workload); in compare "
+                         "mode adds mixed forms whose inner iterations use it")
     ap.add_argument("--lattice", action="store_true",
                     help="per-matvec and per-solve times on the paper's sphere lattice (Table 2)")
     ap.add_argument("--mhd", action="store_true",
@@ -581,8 +654,9 @@ def main():
         args.train_steps = 25 if args.train_steps is None else args.train_steps
         main_learned_experiment(args)
     else:
-        args.workload = args.workload or "random64"
-        args.train_steps = 8 if args.train_steps is None else args.train_steps
+        args.workload = args.workload or "dense4000"
+        if args.train_steps is None:
+            args.train_steps = WORKLOAD_DEFAULTS.get(args.workload, (0, 0, 4))[2]
         main_bench(args)
 
 

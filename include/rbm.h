@@ -36,6 +36,14 @@
  *  - Errors: every call returns an rbm_status; rbm_last_error() gives a
  *    thread-local message.  No call throws across the ABI.  Calls on one context
  *    are not thread safe; different contexts are independent.
+ *  - Overlap: the formulation of §2 assumes disjoint bodies.  Whenever poses change
+ *    (the first solve after rbm_set_bodies, every RK4 stage) bodies whose bounding
+ *    spheres (largest centroid-to-node distance) intersect are compared node by node:
+ *    for each node y of one body, X the nearest node of the other and N its outward
+ *    normal, (y - X).N < -h^2 (h the other shape's largest nearest-neighbour node
+ *    spacing) marks y as inside, and the call returns RBM_E_OVERLAP without solving.
+ *    Separated bodies never trip the test however close they are; penetrations shallower
+ *    than about h^2 may pass it.
  */
 #ifndef RBM_H
 #define RBM_H
@@ -54,6 +62,7 @@ typedef enum {
   RBM_E_NOMEM = -2,   /* no workspace bound, or the bound one is too small */
   RBM_E_DEVICE = -3,  /* a HIP runtime call failed */
   RBM_E_NOCONV = -4,  /* GMRES hit max_iter before tol; outputs are still written */
+  RBM_E_OVERLAP = -5, /* two bodies overlap at the poses of a solve or RK4 stage (see below) */
   RBM_E_STATE = -6    /* call out of order (e.g. solve before setup) */
 } rbm_status;
 
@@ -72,7 +81,7 @@ typedef enum {
 } rbm_guess;
 
 typedef struct {
-  int p;            /* SH order, 2 <= p <= 32; M = 2p(p+1) nodes per body */
+  int p;            /* SH order, 2 <= p <= 20; M = 2p(p+1) nodes per body */
   int p_sing;       /* order of the rotated grid of the singular rule; 0 -> 2p; >= p+1 */
   double eta;       /* viscosity (> 0) */
   double tol;       /* stop when ||b - A mu||_2 <= tol ||b||_2 */
@@ -107,6 +116,10 @@ typedef struct {
                            tolerance; 0 never, 2 always (then a converged cycle may run one
                            iteration whose result is discarded).  The iterates and the
                            solution are the same in every mode. */
+  double ir_stall;      /* precision form: a refinement whose float64 residual is not below
+                           ir_stall times the previous one counts as stalled, and the remaining
+                           refinements run their GMRES cycles with float64 operators (exact far
+                           sums, float64 preconditioner) to the tolerance; 0 -> 0.5 */
 } rbm_options;
 
 typedef struct {
@@ -134,10 +147,13 @@ typedef struct {
   int fmm_applies;    /* far sums evaluated by the fast multipole method */
   int n_traction32;   /* float32 traction sums (direct kernel or fast multipole method) */
   double ms_traction32; /* their summed duration (ms) */
+  int fp64_cycles;    /* precision form: GMRES cycles run with float64 operators after a stalled
+                         refinement (see rbm_options.ir_stall) */
 } rbm_solve_info;
 
 /* Default options: p = 8, p_sing = 0, eta = 1, tol = 1e-12, max_iter = 100,
- * max_restart = 4, RBM_FP64, RBM_GUESS_BLOCKDIAG, inner_tol = 1e-4, stream NULL. */
+ * max_restart = 4, RBM_FP64, RBM_GUESS_BLOCKDIAG, inner_tol = 1e-4, stream NULL,
+ * ir_stall = 0.5. */
 void rbm_default_options(rbm_options* opt);
 
 /* Create a context.  Validates opt; no device work. */
@@ -181,13 +197,40 @@ rbm_status rbm_solve(rbm_ctx* ctx, const double* FT, double* VW, rbm_solve_info*
  * scalar is read back per GMRES iteration for the stopping test). */
 rbm_status rbm_solve_dev(rbm_ctx* ctx, const double* d_FT, double* d_VW, rbm_solve_info* info);
 
+/* Mobility matrix of §1 (V = M F, M symmetric positive definite by the reciprocal theorem
+ * and the uniqueness argument of §2) at the current poses: Mmat[6n][6n] (host, row-major),
+ * column k = the velocities (v_i, omega_i) for the unit load e_k (forces then torques per
+ * body, lab frame), by 6n mobility solves with the context's precision and tolerance.  The
+ * solves use the block-diagonal guess (also in the learned or user guess modes, which are
+ * restored afterwards) and are not captured as training data.  info (may be NULL): summed
+ * iterations, matvecs and times, largest relative residual.  RBM_E_NOCONV if a solve missed
+ * tol (all columns are still written). */
+rbm_status rbm_mobility_matrix(rbm_ctx* ctx, double* Mmat, rbm_solve_info* info);
+
+/* Run state of Algorithm 1's time loop, to resume it later in this or another context with
+ * the same options, shapes and learned configuration: body shape ids, centroids and
+ * quaternions, the last solve's densities mu and rho (when there is one), the guess mode,
+ * the running block-diagonal residual ratio of the learned fallback test and, when a
+ * learned workspace is bound, the network parameters, Adam moments and step count, the
+ * training epoch counter, the feature/target scalings and the captured samples.
+ * rbm_get_state: buf == NULL writes the record size to *bytes; otherwise *bytes must be at
+ * least that size and receives it.  Host memory, owned by the caller.  rbm_set_state
+ * restores a record (RBM_E_INVAL for a record of other shapes, order, sizes or learned
+ * configuration; RBM_E_STATE if the record holds a learned part and no learned workspace is
+ * bound; RBM_E_NOMEM if it has more bodies than the workspace).  A run resumed from a record
+ * repeats the uninterrupted run bit for bit. */
+rbm_status rbm_get_state(rbm_ctx* ctx, void* buf, size_t* bytes);
+rbm_status rbm_set_state(rbm_ctx* ctx, const void* buf, size_t bytes);
+
 /* One classical RK4 step of the rigid-body evolution (§3.3; Algorithm 1, evolve
  * line): four mobility solves with the loads d_FT[n][6] (device pointer, held
  * fixed over the step), dc/dt = v, dq/dt = 1/2 (0, omega) (x) q with omega in the
  * lab frame; stage quaternions are normalised before they define a pose, and so is
  * the final one.  Poses are updated on the device (and mirrored to the host copy
  * read by rbm_get_bodies).  stage_info[4] may be NULL.  Returns RBM_E_NOCONV if a
- * stage solve missed its tolerance (the step is still taken). */
+ * stage solve missed its tolerance (the step is still taken), and RBM_E_OVERLAP if the
+ * poses of a stage or of the step's end overlap (the step is not taken: the context keeps
+ * the poses it started from). */
 rbm_status rbm_step_rk4(rbm_ctx* ctx, double dt, const double* d_FT, rbm_solve_info* stage_info);
 
 /* Current poses: centre[n][3], quat[n][4] (host arrays). */
@@ -311,12 +354,13 @@ rbm_status rbm_step_rk4_magnetic(rbm_ctx* ctx, double dt, const double* H0, doub
 
 /* Device pointers of internal arrays for inspection (valid until the workspace is
  * rebound).  name: "X","N","W" ([3][N]/[N] lab nodes, normals, weights), "mu",
- * "rho", "b" ([3][N]), "A0","P0" ([n_shapes][3M][3M] column-major body-frame
+ * "rho", "b" ([3][N]), "r" ([3][N]: the float64 residual b - A mu of the last refinement), "A0","P0" ([n_shapes][3M][3M] column-major body-frame
  * operators), "V0" ([n_shapes][6][3M]), "gx","gn","gr" ([n_shapes][3][M] shape points,
  * normals, recentred points), "gw" ([n_shapes][M] weights), "coef" ([n_shapes][3][(p+1)^2]),
  * "shape" (per shape 32 values: area, xc[3], tau[9], tauinv[9]), "Rm" ([n][9]),
  * "Ftab" ([p^2+2p][M]), "Ytab" ([(p+1)^2][M]), "learned_X" / "learned_T" (captured
- * features [capacity][F] and targets [capacity][O], fp32); with p_up > 0 also "U" (band-
+ * features [capacity][F] and targets [capacity][O], fp32), "learned_m" / "learned_v" (Adam's first
+ * and second moments [n_params], fp32); with p_up > 0 also "U" (band-
  * limited interpolation, column-major [M][Mu], Mu = 2 p_up (p_up+1)), "fr" ([n_shapes][3][Mu]
  * fine nodes minus the centroid), "fw" ([n_shapes][Mu] fine weights), "rb" ([n_shapes]
  * bounding radii), "near_list" ([n][64] int, increasing j) and "near_count" ([n] int).

@@ -39,6 +39,16 @@ def quat_to_rot(q):
     ])
 
 
+class _LazyR:
+    """Per-shape fine-grid bounding radii, computed when indexed."""
+
+    def __init__(self, prob):
+        self.prob = prob
+
+    def __getitem__(self, s):
+        return self.prob.fine(int(s))["R"]
+
+
 class Shape:
     """One body shape: geometry at the grid plus its singular self operators."""
 
@@ -88,18 +98,51 @@ class Problem:
             self.area[i] = wi.sum()
             self.tau[i] = np.eye(3) * np.sum(wi * np.sum(rr * rr, axis=1)) - (rr * wi[:, None]).T @ rr
         self.upsample = upsample
-        self.near = np.zeros((self.n, self.n), dtype=bool)
+        self._near = None if upsample is not None else np.zeros((self.n, self.n), dtype=bool)
+        self._near_rows = {}
         if upsample is not None:
             p_u, kappa = upsample
             p = shapes[0].p
-            self.fine = [nf.fine_geometry(s.coef, s.geom["xc"], p_u) for s in shapes]
+            self._fine = [None] * len(shapes)
             self.U = nf.interp_matrix(p, p_u)
-            h = [math.sqrt(s.geom["area"] / s.M) for s in shapes]
-            self.near = nf.near_matrix(self.c, [f["R"] for f in self.fine], h, self.shape_id, kappa)
+            self._h = [math.sqrt(s.geom["area"] / s.M) for s in shapes]
+
+    # The fine geometry of a shape and the near test of a body are evaluated on first use
+    # (large suspensions need them only for a few bodies); the values are those of
+    # ``nearfield.fine_geometry`` and ``nearfield.near_matrix``.
+    def fine(self, s):
+        if self._fine[s] is None:
+            sh_ = self.shapes[s]
+            self._fine[s] = nf.fine_geometry(sh_.coef, sh_.geom["xc"], self.upsample[0])
+        return self._fine[s]
+
+    @property
+    def near(self):
+        """near[i, j]: body j is near body i (all bodies)."""
+        if self._near is None:
+            R = [self.fine(s)["R"] for s in range(len(self.shapes))]
+            self._near = nf.near_matrix(self.c, R, self._h, self.shape_id, self.upsample[1])
+        return self._near
+
+    def near_row(self, i):
+        """Row i of ``near``, computed from the bodies that can possibly be near i: a fine
+        grid's bounding radius is within a factor 2 of the coarse grid's."""
+        if self._near is not None:
+            return self._near[i]
+        if i not in self._near_rows:
+            rc = [float(np.sqrt(np.max(np.sum(s_.geom["r"] ** 2, axis=0)))) for s_ in self.shapes]
+            reach = 2.0 * rc[self.shape_id[i]] + 2.0 * max(rc) + self.upsample[1] * max(self._h)
+            dist = np.sqrt(np.sum((self.c - self.c[i]) ** 2, axis=1))
+            cand = np.where(dist < reach)[0]                # includes i itself
+            sub = nf.near_matrix(self.c[cand], _LazyR(self), self._h, self.shape_id[cand], self.upsample[1])
+            row = np.zeros(self.n, dtype=bool)
+            row[cand] = sub[int(np.where(cand == i)[0][0])]
+            self._near_rows[i] = row
+        return self._near_rows[i]
 
     def fine_sources(self, j):
         """Lab-frame fine nodes X' of body j and their weights w'."""
-        f = self.fine[self.shape_id[j]]
+        f = self.fine(self.shape_id[j])
         return (self.c[j][:, None] + self.R[j] @ f["r"]).T, f["w"]
 
     def _far_upsampled(self, kind, vec, idx):
@@ -110,10 +153,11 @@ class Problem:
         for i in np.unique(tb):
             sel = np.where(tb == i)[0]
             Xt = self.X[idx[sel]]
+            near_i = self.near_row(i)
             for j in range(self.n):
                 if j == i:
                     continue
-                if self.near[i, j]:
+                if near_i[j]:
                     Xs, ws = self.fine_sources(j)
                     q = ws[:, None] * (self.U @ vec[self.sl(j)])
                 else:

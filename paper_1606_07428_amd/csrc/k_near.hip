@@ -438,6 +438,92 @@ __global__ __launch_bounds__(256) void k_closest_pair(int N, int M, const int* _
   }
 }
 
+// Overlap test of candidate body pairs (a, b): for every node y of one body, the node X_r
+// of the other body nearest to y (ties: smaller index) and the signed offset
+// s = (y - X_r) . N_r along that node's outward normal.  A node of a smooth body lying
+// outside the other body has s >= -(covering radius)^2 x curvature / 2, one inside has
+// s < 0 growing with its depth.  out[2k + dir] = min over y of s, dir 0: nodes of b against
+// body a, dir 1: nodes of a against body b.  One workgroup per (pair, direction); the
+// reference body's nodes and normals are staged in LDS.
+__global__ __launch_bounds__(256) void k_overlap_depth(int N, int M, const int* __restrict__ cand,
+                                                       const double* __restrict__ X,
+                                                       const double* __restrict__ Nn,
+                                                       double* __restrict__ out) {
+  extern __shared__ double sref[];  // [6][M]: reference nodes then normals
+  const int k = blockIdx.x, dir = blockIdx.y;
+  const int a = cand[2 * k], b = cand[2 * k + 1];
+  const int rb = dir == 0 ? a : b, tb = dir == 0 ? b : a;
+  for (int e = threadIdx.x; e < 3 * M; e += 256) {
+    const int c = e / M, i = e - c * M;
+    sref[e] = X[(size_t)c * N + (size_t)rb * M + i];
+    sref[3 * M + e] = Nn[(size_t)c * N + (size_t)rb * M + i];
+  }
+  __syncthreads();
+  double smin = 1e300;
+  for (int t = threadIdx.x; t < M; t += 256) {
+    const size_t g = (size_t)tb * M + t;
+    const double yx = X[g], yy = X[N + g], yz = X[2 * (size_t)N + g];
+    double best = 1e300;
+    int bi = 0;
+    for (int i = 0; i < M; ++i) {
+      const double dx = yx - sref[i], dy = yy - sref[M + i], dz = yz - sref[2 * M + i];
+      const double d2 = dx * dx + dy * dy + dz * dz;
+      if (d2 < best) {
+        best = d2;
+        bi = i;
+      }
+    }
+    const double s = (yx - sref[bi]) * sref[3 * M + bi] + (yy - sref[M + bi]) * sref[4 * M + bi] +
+                     (yz - sref[2 * M + bi]) * sref[5 * M + bi];
+    smin = fmin(smin, s);
+  }
+  __shared__ double red[256];
+  red[threadIdx.x] = smin;
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if (threadIdx.x < h) red[threadIdx.x] = fmin(red[threadIdx.x], red[threadIdx.x + h]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[2 * k + dir] = red[0];
+}
+
+// Largest nearest-neighbour spacing of a shape's nodes: hs[s] = max_a min_{b != a} |r_a - r_b|
+// over r [ns][3][M].  One workgroup per shape.
+__global__ __launch_bounds__(256) void k_node_spacing(int M, const double* __restrict__ r,
+                                                      double* __restrict__ hs) {
+  const double* rs = r + (size_t)blockIdx.x * 3 * M;
+  double hmax = 0.0;
+  for (int a = threadIdx.x; a < M; a += 256) {
+    double best = 1e300;
+    for (int b = 0; b < M; ++b) {
+      if (b == a) continue;
+      const double dx = rs[a] - rs[b], dy = rs[M + a] - rs[M + b], dz = rs[2 * M + a] - rs[2 * M + b];
+      best = fmin(best, dx * dx + dy * dy + dz * dz);
+    }
+    hmax = fmax(hmax, best);
+  }
+  __shared__ double red[256];
+  red[threadIdx.x] = hmax;
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if (threadIdx.x < h) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + h]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) hs[blockIdx.x] = sqrt(red[0]);
+}
+
+hipError_t launch_overlap_depth(int ncand, int N, int M, const int* cand, const double* X, const double* Nn,
+                                double* out, hipStream_t st) {
+  if (ncand < 1) return hipSuccess;
+  k_overlap_depth<<<dim3(ncand, 2), 256, 6 * (size_t)M * sizeof(double), st>>>(N, M, cand, X, Nn, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_node_spacing(int ns, int M, const double* r, double* hs, hipStream_t st) {
+  k_node_spacing<<<ns, 256, 0, st>>>(M, r, hs);
+  return hipGetLastError();
+}
+
 hipError_t launch_closest_pairs(int ncand, int N, int M, const int* cand, const double* X, double* out,
                                 hipStream_t st) {
   if (ncand < 1) return hipSuccess;

@@ -182,6 +182,12 @@ hipError_t launch_near_corr(int kind, int n, int M, int Mu, int kmax, int nneed,
 // (distance^2, node-pair index ia*M + ib, midpoint x*)
 hipError_t launch_closest_pairs(int ncand, int N, int M, const int* cand, const double* X, double* out,
                                 hipStream_t st);
+// overlap test: out [k][2] = min over the nodes y of one body of (y - X_r) . N_r, X_r the
+// other body's node nearest to y (dir 0: nodes of b against a, dir 1: nodes of a against b)
+hipError_t launch_overlap_depth(int ncand, int N, int M, const int* cand, const double* X, const double* Nn,
+                                double* out, hipStream_t st);
+// hs[s] = largest nearest-neighbour spacing of the M points r [ns][3][M]
+hipError_t launch_node_spacing(int ns, int M, const double* r, double* hs, hipStream_t st);
 // rb[s] = max_a |r_a| over the M points r [ns][3][M]
 hipError_t launch_bound_radius(int ns, int M, const double* r, double* rb, hipStream_t st);
 

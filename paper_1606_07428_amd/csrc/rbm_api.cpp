@@ -8,6 +8,7 @@
 #include <thread>
 #include <cmath>
 #include <type_traits>
+#include <cstdint>
 #include <cstdio>
 #include <cstring>
 #include <string>
@@ -116,6 +117,9 @@ struct rbm_ctx {
   double *rbc = nullptr, *cres = nullptr;
   int* ccand = nullptr;
   std::vector<double> rbc_h;
+  // overlap test: largest nearest-neighbour node spacing per shape (device and host)
+  double* hsp = nullptr;
+  std::vector<double> hsp_h;
   double* pinned = nullptr;
   double* pinned_dev = nullptr;  // the same pinned buffer as a device pointer
   // learned warm start
@@ -159,6 +163,7 @@ extern "C" void rbm_default_options(rbm_options* o) {
   o->fmm_order = 0;
   o->fmm_max_level = 5;
   o->gmres_lookahead = 1;
+  o->ir_stall = 0.5;
 }
 
 extern "C" const char* rbm_last_error(void) { return g_err.c_str(); }
@@ -185,10 +190,12 @@ extern "C" rbm_status rbm_create(const rbm_options* opt, rbm_ctx** out) {
   if (opt->fmm_order != 0 && opt->fmm_max_level != 0 && (opt->fmm_max_level < 2 || opt->fmm_max_level > 6))
     return fail(RBM_E_INVAL, "fmm_max_level must be 0 or in [2, 6]");
   if (opt->gmres_lookahead < 0 || opt->gmres_lookahead > 2) return fail(RBM_E_INVAL, "gmres_lookahead in [0, 2]");
+  if (!(opt->ir_stall >= 0.0 && opt->ir_stall < 1.0)) return fail(RBM_E_INVAL, "ir_stall in [0, 1)");
   rbm_ctx* c = new rbm_ctx();
   c->opt = *opt;
   if (c->opt.fmm_max_level == 0) c->opt.fmm_max_level = 5;
   if (!(c->opt.inner_tol > 0.0)) c->opt.inner_tol = 1e-4;
+  if (!(c->opt.ir_stall > 0.0)) c->opt.ir_stall = 0.5;
   c->p = opt->p;
   c->ps = ps;
   c->M = (c->p + 1) * 2 * c->p;
@@ -316,6 +323,7 @@ static size_t layout(rbm_ctx* c, int nmax, bool assign) {
   take(c->gx, ns * 3 * M); take(c->gn, ns * 3 * M); take(c->gr, ns * 3 * M); take(c->gw, ns * M);
   take(c->shp, ns * 32);
   take(c->rbc, ns);
+  take(c->hsp, ns);
   take(c->A0, ns * M3 * M3); take(c->P0, ns * M3 * M3); take(c->V0, ns * 6 * M3);
   take(c->piv, ns * M3);
   if (c->opt.precision == RBM_MIXED_FP32) take(c->P0f, ns * M3 * M3); else if (assign) c->P0f = nullptr;
@@ -469,8 +477,11 @@ extern "C" rbm_status rbm_setup(rbm_ctx* c) {
                                     c->tang, st));
   }
   HIPCHECK(launch_bound_radius(c->ns, M, c->gr, c->rbc, st));
+  HIPCHECK(launch_node_spacing(c->ns, M, c->gr, c->hsp, st));
   c->rbc_h.resize(c->ns);
+  c->hsp_h.resize(c->ns);
   HIPCHECK(hipMemcpyAsync(c->rbc_h.data(), c->rbc, c->ns * sizeof(double), hipMemcpyDeviceToHost, st));
+  HIPCHECK(hipMemcpyAsync(c->hsp_h.data(), c->hsp, c->ns * sizeof(double), hipMemcpyDeviceToHost, st));
   if (c->pu) {
     HIPCHECK(launch_gauss_legendre(c->pu + 1, c->glu_t, c->glu_w, st));
     HIPCHECK(launch_fine_geometry(c->ns, p, c->pu, c->coef, c->glu_t, c->glu_w, c->shp, c->fr, c->fw,
@@ -541,6 +552,60 @@ static rbm_status build_near(rbm_ctx* c) {
   return RBM_OK;
 }
 
+// Overlap test at the current poses (centres read from the device): bodies whose bounding
+// spheres (largest centroid-to-node distance) intersect are compared node by node, and
+// RBM_E_OVERLAP is returned when a node of one body lies inside the other by more than the
+// allowance h^2, h the largest nearest-neighbour node spacing of the other body's shape.  A
+// node outside a smooth body is never below -(covering radius)^2 x curvature / 2 >= -h^2
+// (curvature up to 4 for unit-size bodies), so separated bodies pass however close they are.
+static rbm_status check_overlap(rbm_ctx* c) {
+  const int n = c->n, M = c->M;
+  if (n < 2) return RBM_OK;
+  hipStream_t st = c->st;
+  std::vector<double> cen(3 * (size_t)n);
+  HIPCHECK(hipMemcpyAsync(cen.data(), c->cen, cen.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+  HIPCHECK(hipStreamSynchronize(st));
+  double rmax = 0.0;
+  for (int i = 0; i < n; ++i) rmax = std::max(rmax, c->rbc_h[c->sid_h[i]]);
+  // sweep over bodies sorted by x: a pair can intersect only within 2 rmax in x
+  std::vector<int> ord(n);
+  for (int i = 0; i < n; ++i) ord[i] = i;
+  std::sort(ord.begin(), ord.end(), [&](int a, int b) {
+    return cen[3 * a] < cen[3 * b] || (cen[3 * a] == cen[3 * b] && a < b);
+  });
+  std::vector<int> cand;
+  for (int ia = 0; ia < n; ++ia) {
+    const int a = ord[ia];
+    for (int ib = ia + 1; ib < n; ++ib) {
+      const int b = ord[ib];
+      const double dx = cen[3 * b] - cen[3 * a];
+      if (dx >= 2.0 * rmax) break;
+      const double dy = cen[3 * b + 1] - cen[3 * a + 1], dz = cen[3 * b + 2] - cen[3 * a + 2];
+      const double rr = c->rbc_h[c->sid_h[a]] + c->rbc_h[c->sid_h[b]];
+      if (dx * dx + dy * dy + dz * dz < rr * rr) {
+        cand.push_back(std::min(a, b));
+        cand.push_back(std::max(a, b));
+      }
+    }
+  }
+  const int ncand = (int)cand.size() / 2;
+  if (ncand == 0) return RBM_OK;
+  if ((size_t)ncand > (size_t)kContactCand * c->nmax)
+    return fail(RBM_E_OVERLAP, "more than 32 n body pairs with intersecting bounding spheres");
+  std::vector<double> res(2 * (size_t)ncand);
+  HIPCHECK(hipMemcpyAsync(c->ccand, cand.data(), cand.size() * sizeof(int), hipMemcpyHostToDevice, st));
+  HIPCHECK(launch_overlap_depth(ncand, n * M, M, c->ccand, c->X, c->Nn, c->cres, st));
+  HIPCHECK(hipMemcpyAsync(res.data(), c->cres, res.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+  HIPCHECK(hipStreamSynchronize(st));
+  for (int k = 0; k < ncand; ++k) {
+    const int a = cand[2 * k], b = cand[2 * k + 1];
+    const double ha = c->hsp_h[c->sid_h[a]], hb = c->hsp_h[c->sid_h[b]];
+    if (!(res[2 * k] >= -ha * ha) || !(res[2 * k + 1] >= -hb * hb))
+      return fail(RBM_E_OVERLAP, "bodies " + std::to_string(a) + " and " + std::to_string(b) + " overlap");
+  }
+  return RBM_OK;
+}
+
 static rbm_status upload_bodies(rbm_ctx* c) {
   if (!c->bodies_dirty) return RBM_OK;
   hipStream_t st = c->st;
@@ -552,7 +617,9 @@ static rbm_status upload_bodies(rbm_ctx* c) {
   HIPCHECK(launch_nodes(n, c->M, c->sid, c->cen, c->Rm, c->gr, c->gn, c->gw, c->X, c->Nn, c->W,
                         c->Xf, c->Nf, st));
   HIPCHECK(hipStreamSynchronize(st));
-  rbm_status s = build_near(c);
+  rbm_status s = check_overlap(c);
+  if (s != RBM_OK) return s;
+  s = build_near(c);
   if (s != RBM_OK) return s;
   c->bodies_dirty = false;
   return RBM_OK;
@@ -994,10 +1061,14 @@ static rbm_status solve_impl(rbm_ctx* c, const double* dFT, double* dVW, rbm_sol
     if (!c->guess_set) return fail(RBM_E_STATE, "RBM_GUESS_USER needs rbm_set_guess_dev");
     HIPCHECK(hipMemcpyAsync(c->mu, c->guess, len * sizeof(double), hipMemcpyDeviceToDevice, st));
   }
-  int total_iters = 0, cycles = 0, refinements = 0;
+  int total_iters = 0, cycles = 0, refinements = 0, fp64_cycles = 0;
   double rel = 0.0, init_rel = 0.0;
   bool converged = false;
   const int max_outer = prec == 0 ? c->opt.max_restart + 1 : 50;
+  // GMRES-IR: inner operators in the form's precision until a refinement stalls (its
+  // float64 residual not below ir_stall times the previous one); then float64 operators
+  int prec_in = prec;
+  double rn_prev = -1.0;
   for (int outer = 0; outer <= max_outer; ++outer) {
     // float64 residual r = b - A mu
     double rn;
@@ -1033,18 +1104,21 @@ static rbm_status solve_impl(rbm_ctx* c, const double* dFT, double* dVW, rbm_sol
     rel = bnorm > 0.0 ? rn / bnorm : 0.0;
     if (rn <= abs_tol || bnorm == 0.0) { converged = true; break; }
     if (outer == max_outer) break;
-    double inner_abs = prec == 0 ? abs_tol : std::max(c->opt.inner_tol * rn, 0.5 * abs_tol);
+    if (prec_in != 0 && rn_prev > 0.0 && !(rn < c->opt.ir_stall * rn_prev)) prec_in = 0;
+    rn_prev = rn;
+    double inner_abs = prec_in == 0 ? abs_tol : std::max(c->opt.inner_tol * rn, 0.5 * abs_tol);
     // Float32 inner operators (direct far sum, float32 self blocks) are accurate to about
     // 2^-22: when that accuracy times this residual already meets the tolerance, solve the
     // correction to the tolerance itself and finish in this refinement (the exact residual
     // still decides; a miss costs one more refinement, never accuracy).
-    if (prec == RBM_MIXED_FP32 && !c->fmm_ready && std::ldexp(rn, -22) <= 0.5 * abs_tol)
+    if (prec_in == RBM_MIXED_FP32 && !c->fmm_ready && std::ldexp(rn, -22) <= 0.5 * abs_tol)
       inner_abs = 0.5 * abs_tol;
     int it = 0;
-    if ((s = gmres_cycle(c, S, prec, c->r, rn, inner_abs, &it)) != RBM_OK) return s;
+    if ((s = gmres_cycle(c, S, prec_in, c->r, rn, inner_abs, &it)) != RBM_OK) return s;
     total_iters += it;
     cycles++;
     if (prec != 0) refinements++;
+    if (prec != 0 && prec_in == 0) fp64_cycles++;
   }
   // velocities u = S[rho + mu]: far Stokeslet sum + self functional, float64
   HIPCHECK(launch_axpby(len, 1.0, c->rho, 1.0, c->mu, c->t2, st));
@@ -1087,6 +1161,7 @@ static rbm_status solve_impl(rbm_ctx* c, const double* dFT, double* dVW, rbm_sol
     info->near_pairs = c->pu ? c->near_pairs : 0;
     info->fmm_level = c->fmm_ready ? c->fmm_level : -1;
     info->fmm_applies = S.fmm_applies;
+    info->fp64_cycles = fp64_cycles;
     if (total.on) {
       float ms = 0;
       (void)hipEventElapsedTime(&ms, total.a, total.b);
@@ -1475,6 +1550,7 @@ extern "C" const void* rbm_debug_ptr(rbm_ctx* c, const char* name) {
   if (s == "mu") return c->mu;
   if (s == "rho") return c->rho;
   if (s == "b") return c->b;
+  if (s == "r") return c->r;
   if (s == "A0") return c->A0;
   if (s == "P0") return c->P0;
   if (s == "V0") return c->V0;
@@ -1500,6 +1576,8 @@ extern "C" const void* rbm_debug_ptr(rbm_ctx* c, const char* name) {
   if (s == "near_count") return c->ncnt;
   if (s == "learned_X") return c->L.bound ? c->L.Xbuf : nullptr;
   if (s == "learned_T") return c->L.bound ? c->L.Tbuf : nullptr;
+  if (s == "learned_m") return c->L.bound ? c->L.Mo : nullptr;
+  if (s == "learned_v") return c->L.bound ? c->L.Vo : nullptr;
   return nullptr;
 }
 
@@ -1589,7 +1667,28 @@ static rbm_status refresh_nodes(rbm_ctx* c) {
   HIPCHECK(launch_body_prep(c->n, c->quat, c->sid, c->shp, c->Rm, c->tauinv, c->area_b, c->st));
   HIPCHECK(launch_nodes(c->n, c->M, c->sid, c->cen, c->Rm, c->gr, c->gn, c->gw, c->X, c->Nn, c->W,
                         c->Xf, c->Nf, c->st));
+  rbm_status s = check_overlap(c);
+  if (s != RBM_OK) return s;
   return build_near(c);
+}
+
+// An RK4 stage (or the step's end) whose poses overlap: put back the poses the step
+// started from, so that the context stays at a valid configuration, and return `why`
+// with the overlap message.
+static rbm_status restore_step_start(rbm_ctx* c, rbm_status why) {
+  const std::string msg = g_err;
+  const int n = c->n;
+  HIPCHECK(hipMemcpyAsync(c->cen, c->cen0, 3 * n * sizeof(double), hipMemcpyDeviceToDevice, c->st));
+  HIPCHECK(hipMemcpyAsync(c->quat, c->quat0, 4 * n * sizeof(double), hipMemcpyDeviceToDevice, c->st));
+  HIPCHECK(launch_body_prep(n, c->quat, c->sid, c->shp, c->Rm, c->tauinv, c->area_b, c->st));
+  HIPCHECK(launch_nodes(n, c->M, c->sid, c->cen, c->Rm, c->gr, c->gn, c->gw, c->X, c->Nn, c->W, c->Xf,
+                        c->Nf, c->st));
+  HIPCHECK(hipMemcpyAsync(c->cen_h.data(), c->cen0, 3 * n * sizeof(double), hipMemcpyDeviceToHost, c->st));
+  HIPCHECK(hipMemcpyAsync(c->quat_h.data(), c->quat0, 4 * n * sizeof(double), hipMemcpyDeviceToHost, c->st));
+  HIPCHECK(hipStreamSynchronize(c->st));
+  c->fmm_ready = false;
+  c->bodies_dirty = true;  // near lists are rebuilt by the next call that needs them
+  return fail(why, msg + " (the step's initial poses are kept)");
 }
 
 extern "C" rbm_status rbm_step_rk4(rbm_ctx* c, double dt, const double* d_FT,
@@ -1615,7 +1714,7 @@ extern "C" rbm_status rbm_step_rk4(rbm_ctx* c, double dt, const double* d_FT,
   }
   for (int k = 0; k < 4; ++k) {
     HIPCHECK(launch_rk_stage(n, c->cen0, c->quat0, c->kst, a[k], dt, c->cen, c->quat, st));
-    if ((s = refresh_nodes(c)) != RBM_OK) return s;
+    if ((s = refresh_nodes(c)) != RBM_OK) return s == RBM_E_OVERLAP ? restore_step_start(c, s) : s;
     c->bodies_dirty = false;
     if (c->opt.contact_delta > 0.0) {
       // stage poses to the host for the contact search, then the contact-corrected solve
@@ -1643,7 +1742,7 @@ extern "C" rbm_status rbm_step_rk4(rbm_ctx* c, double dt, const double* d_FT,
     HIPCHECK(launch_rk_deriv(n, c->VW, c->quat, c->kst, c->kacc, wgt[k], k == 0, st));
   }
   HIPCHECK(launch_rk_final(n, c->cen0, c->quat0, c->kacc, dt, c->cen, c->quat, st));
-  if ((s = refresh_nodes(c)) != RBM_OK) return s;
+  if ((s = refresh_nodes(c)) != RBM_OK) return s == RBM_E_OVERLAP ? restore_step_start(c, s) : s;
   HIPCHECK(hipMemcpyAsync(c->cen_h.data(), c->cen, 3 * n * sizeof(double), hipMemcpyDeviceToHost, st));
   HIPCHECK(hipMemcpyAsync(c->quat_h.data(), c->quat, 4 * n * sizeof(double), hipMemcpyDeviceToHost, st));
   HIPCHECK(hipStreamSynchronize(st));
@@ -1678,7 +1777,7 @@ extern "C" rbm_status rbm_step_rk4_magnetic(rbm_ctx* c, double dt, const double*
   rbm_status worst = RBM_OK;
   for (int k = 0; k < 4; ++k) {
     HIPCHECK(launch_rk_stage(n, c->cen0, c->quat0, c->kst, a[k], dt, c->cen, c->quat, st));
-    if ((s = refresh_nodes(c)) != RBM_OK) return s;
+    if ((s = refresh_nodes(c)) != RBM_OK) return s == RBM_E_OVERLAP ? restore_step_start(c, s) : s;
     c->bodies_dirty = false;
     int it = 0;
     if ((s = magnetic_traction_impl(c, H0, mu_ratio, mu0, tol_mag, c->mrho, nullptr, &it)) != RBM_OK) return s;
@@ -1710,7 +1809,7 @@ extern "C" rbm_status rbm_step_rk4_magnetic(rbm_ctx* c, double dt, const double*
     HIPCHECK(hipStreamSynchronize(st));
   }
   HIPCHECK(launch_rk_final(n, c->cen0, c->quat0, c->kacc, dt, c->cen, c->quat, st));
-  if ((s = refresh_nodes(c)) != RBM_OK) return s;
+  if ((s = refresh_nodes(c)) != RBM_OK) return s == RBM_E_OVERLAP ? restore_step_start(c, s) : s;
   HIPCHECK(hipMemcpyAsync(c->cen_h.data(), c->cen, 3 * n * sizeof(double), hipMemcpyDeviceToHost, st));
   HIPCHECK(hipMemcpyAsync(c->quat_h.data(), c->quat, 4 * n * sizeof(double), hipMemcpyDeviceToHost, st));
   HIPCHECK(hipStreamSynchronize(st));
@@ -2104,5 +2203,245 @@ extern "C" rbm_status rbm_set_guess(rbm_ctx* c, int guess) {
   if (!c) return fail(RBM_E_INVAL, "null argument");
   if (guess < 0 || guess > 3) return fail(RBM_E_INVAL, "bad guess");
   c->opt.guess = guess;
+  return RBM_OK;
+}
+
+// ---------------------------------------------------------------------------------
+// Mobility matrix (§1: V = M F) by unit-load solves
+
+extern "C" rbm_status rbm_mobility_matrix(rbm_ctx* c, double* Mmat, rbm_solve_info* info) {
+  if (!c || !Mmat) return fail(RBM_E_INVAL, "null argument");
+  if (!c->ws) return fail(RBM_E_NOMEM, "bind a workspace first");
+  if (!c->setup_done) return fail(RBM_E_STATE, "call rbm_setup first");
+  if (c->n < 1) return fail(RBM_E_STATE, "set bodies first");
+  const int m = 6 * c->n;
+  const int guess = c->opt.guess;
+  const bool capture = c->L.capture_on;
+  // unit loads get the block-diagonal guess and are not captured as training data
+  if (guess == RBM_GUESS_LEARNED || guess == RBM_GUESS_USER) c->opt.guess = RBM_GUESS_BLOCKDIAG;
+  c->L.capture_on = false;
+  std::vector<double> load(m, 0.0), vw(m);
+  rbm_solve_info tot, ik;
+  std::memset(&tot, 0, sizeof(tot));
+  rbm_status s = RBM_OK, worst = RBM_OK;
+  for (int k = 0; k < m && (s == RBM_OK || s == RBM_E_NOCONV); ++k) {
+    load[k] = 1.0;
+    s = rbm_solve(c, load.data(), vw.data(), &ik);
+    load[k] = 0.0;
+    if (s == RBM_E_NOCONV) worst = s;
+    if (s != RBM_OK && s != RBM_E_NOCONV) break;
+    for (int r = 0; r < m; ++r) Mmat[(size_t)r * m + k] = vw[r];
+    tot.iters += ik.iters;
+    tot.matvecs += ik.matvecs;
+    tot.cycles += ik.cycles;
+    tot.refinements += ik.refinements;
+    tot.ms_total += ik.ms_total;
+    tot.ms_far += ik.ms_far;
+    tot.ms_self += ik.ms_self;
+    tot.far_pairs += ik.far_pairs;
+    tot.rel_residual = std::max(tot.rel_residual, ik.rel_residual);
+  }
+  c->opt.guess = guess;
+  c->L.capture_on = capture;
+  if (info) *info = tot;
+  if (s != RBM_OK && s != RBM_E_NOCONV) return s;
+  if (worst != RBM_OK) return fail(worst, "a unit-load solve did not reach tol");
+  return RBM_OK;
+}
+
+// ---------------------------------------------------------------------------------
+// Run state (Algorithm 1's loop: poses, densities, learned warm start)
+
+namespace {
+
+constexpr char kStateMagic[8] = {'R', 'B', 'M', 'S', 'T', 'A', 'T', '1'};
+
+struct StateHeader {
+  char magic[8];
+  uint64_t bytes;        // whole record
+  uint64_t shape_hash;   // FNV-1a of the shape input (kind, lmax, coefficients)
+  int32_t p, M, ns, n;
+  int32_t guess, have_solution, learned, pad0;
+  double bd_ratio;
+  // learned warm start (zeros when learned == 0)
+  int32_t F, O, capacity, count, head, t, epoch, stats_ready, capture_on, pad1;
+  uint64_t nparam;
+};
+
+uint64_t fnv1a(uint64_t h, const void* p, size_t n) {
+  const unsigned char* b = static_cast<const unsigned char*>(p);
+  for (size_t i = 0; i < n; ++i) {
+    h ^= b[i];
+    h *= 1099511628211ULL;
+  }
+  return h;
+}
+
+uint64_t shape_hash(const rbm_ctx* c) {
+  uint64_t h = 1469598103934665603ULL;
+  h = fnv1a(h, &c->shape_kind, sizeof(c->shape_kind));
+  h = fnv1a(h, &c->shape_lmax, sizeof(c->shape_lmax));
+  return fnv1a(h, c->shape_data.data(), c->shape_data.size() * sizeof(double));
+}
+
+// Byte count of the record for the context's current contents.
+size_t state_bytes(const rbm_ctx* c, const StateHeader& h) {
+  const size_t N = (size_t)h.n * h.M;
+  size_t b = sizeof(StateHeader) + (size_t)h.n * (sizeof(int32_t) + 7 * sizeof(double));
+  if (h.have_solution) b += 6 * N * sizeof(double);
+  if (h.learned)
+    b += (3 * h.nparam + 2 * (size_t)h.F + 2 + (size_t)h.count * (h.F + h.O)) * sizeof(float);
+  (void)c;
+  return b;
+}
+
+}  // namespace
+
+extern "C" rbm_status rbm_get_state(rbm_ctx* c, void* buf, size_t* bytes) {
+  if (!c || !bytes) return fail(RBM_E_INVAL, "null argument");
+  if (!c->ws || !c->setup_done) return fail(RBM_E_STATE, "call rbm_setup first");
+  if (c->n < 1) return fail(RBM_E_STATE, "set bodies first");
+  StateHeader h;
+  std::memset(&h, 0, sizeof(h));
+  std::memcpy(h.magic, kStateMagic, 8);
+  h.shape_hash = shape_hash(c);
+  h.p = c->p;
+  h.M = c->M;
+  h.ns = c->ns;
+  h.n = c->n;
+  h.guess = c->opt.guess;
+  h.have_solution = c->have_solution ? 1 : 0;
+  h.learned = c->L.bound ? 1 : 0;
+  h.bd_ratio = c->bd_ratio;
+  const auto& L = c->L;
+  if (L.bound) {
+    h.F = L.F;
+    h.O = L.O;
+    h.capacity = L.cfg.capacity;
+    h.count = L.count;
+    h.head = L.head;
+    h.t = L.t;
+    h.epoch = L.epoch;
+    h.stats_ready = L.stats_ready ? 1 : 0;
+    h.capture_on = L.capture_on ? 1 : 0;
+    h.nparam = L.nparam;
+  }
+  h.bytes = state_bytes(c, h);
+  if (!buf) {
+    *bytes = h.bytes;
+    return RBM_OK;
+  }
+  if (*bytes < h.bytes) return fail(RBM_E_INVAL, "state buffer too small (query the size with buf = NULL)");
+  *bytes = h.bytes;
+  char* o = static_cast<char*>(buf);
+  auto put = [&](const void* src, size_t nb) {
+    std::memcpy(o, src, nb);
+    o += nb;
+  };
+  auto put_dev = [&](const void* dsrc, size_t nb) -> hipError_t {
+    hipError_t e = hipMemcpy(o, dsrc, nb, hipMemcpyDeviceToHost);
+    o += nb;
+    return e;
+  };
+  HIPCHECK(hipStreamSynchronize(c->st));
+  const int n = c->n;
+  const size_t N = (size_t)n * c->M;
+  put(&h, sizeof(h));
+  std::vector<int32_t> sid(c->sid_h.begin(), c->sid_h.end());
+  put(sid.data(), n * sizeof(int32_t));
+  put(c->cen_h.data(), 3 * n * sizeof(double));
+  put(c->quat_h.data(), 4 * n * sizeof(double));
+  if (h.have_solution) {
+    HIPCHECK(put_dev(c->mu, 3 * N * sizeof(double)));
+    HIPCHECK(put_dev(c->rho, 3 * N * sizeof(double)));
+  }
+  if (h.learned) {
+    HIPCHECK(put_dev(L.P, L.nparam * sizeof(float)));
+    HIPCHECK(put_dev(L.Mo, L.nparam * sizeof(float)));
+    HIPCHECK(put_dev(L.Vo, L.nparam * sizeof(float)));
+    HIPCHECK(put_dev(L.mean, L.F * sizeof(float)));
+    HIPCHECK(put_dev(L.istd, L.F * sizeof(float)));
+    HIPCHECK(put_dev(L.tsc, 2 * sizeof(float)));
+    HIPCHECK(put_dev(L.Xbuf, (size_t)L.count * L.F * sizeof(float)));
+    HIPCHECK(put_dev(L.Tbuf, (size_t)L.count * L.O * sizeof(float)));
+  }
+  return RBM_OK;
+}
+
+extern "C" rbm_status rbm_set_state(rbm_ctx* c, const void* buf, size_t bytes) {
+  if (!c || !buf) return fail(RBM_E_INVAL, "null argument");
+  if (!c->ws || !c->setup_done) return fail(RBM_E_STATE, "call rbm_setup first");
+  if (bytes < sizeof(StateHeader)) return fail(RBM_E_INVAL, "state record too short");
+  StateHeader h;
+  std::memcpy(&h, buf, sizeof(h));
+  if (std::memcmp(h.magic, kStateMagic, 8) != 0) return fail(RBM_E_INVAL, "not a state record");
+  if (h.bytes != bytes || state_bytes(c, h) != bytes) return fail(RBM_E_INVAL, "state record size mismatch");
+  if (h.p != c->p || h.M != c->M || h.ns != c->ns || h.shape_hash != shape_hash(c))
+    return fail(RBM_E_INVAL, "state record belongs to other shapes or another order p");
+  if (h.n < 1 || h.n > c->nmax) return fail(RBM_E_NOMEM, "more bodies than the workspace holds");
+  if (h.guess < 0 || h.guess > 3) return fail(RBM_E_INVAL, "bad guess mode in the state record");
+  auto& L = c->L;
+  if (h.learned) {
+    if (!L.bound) return fail(RBM_E_STATE, "the record has a learned warm start: bind the learned workspace first");
+    if (h.F != L.F || h.O != L.O || h.nparam != L.nparam || h.capacity != L.cfg.capacity)
+      return fail(RBM_E_INVAL, "learned configuration of the record differs from the bound one");
+    if (h.count < 0 || h.count > h.capacity || h.head < 0 || h.head > h.capacity)
+      return fail(RBM_E_INVAL, "bad sample counts in the state record");
+  }
+  const char* in = static_cast<const char*>(buf) + sizeof(h);
+  const int n = h.n;
+  const size_t N = (size_t)n * c->M;
+  std::vector<int32_t> sid(n);
+  std::memcpy(sid.data(), in, n * sizeof(int32_t));
+  in += n * sizeof(int32_t);
+  for (int i = 0; i < n; ++i)
+    if (sid[i] < 0 || sid[i] >= c->ns) return fail(RBM_E_INVAL, "unknown shape id in the state record");
+  std::vector<double> cen(3 * (size_t)n), quat(4 * (size_t)n);
+  std::memcpy(cen.data(), in, cen.size() * sizeof(double));
+  in += cen.size() * sizeof(double);
+  std::memcpy(quat.data(), in, quat.size() * sizeof(double));
+  in += quat.size() * sizeof(double);
+  if (!all_finite(cen.data(), cen.size()) || !all_finite(quat.data(), quat.size()))
+    return fail(RBM_E_INVAL, "non-finite pose in the state record");
+  hipStream_t st = c->st;
+  HIPCHECK(hipStreamSynchronize(st));
+  c->n = n;
+  c->sid_h.assign(sid.begin(), sid.end());
+  c->cen_h = cen;
+  c->quat_h = quat;
+  c->bodies_dirty = true;
+  c->fmm_ready = false;
+  c->opt.guess = h.guess;
+  c->bd_ratio = h.bd_ratio;
+  if (h.have_solution) {
+    HIPCHECK(hipMemcpy(c->mu, in, 3 * N * sizeof(double), hipMemcpyHostToDevice));
+    in += 3 * N * sizeof(double);
+    HIPCHECK(hipMemcpy(c->rho, in, 3 * N * sizeof(double), hipMemcpyHostToDevice));
+    in += 3 * N * sizeof(double);
+  }
+  c->have_solution = h.have_solution != 0;
+  if (h.learned) {
+    auto get = [&](void* ddst, size_t nb) -> hipError_t {
+      hipError_t e = hipMemcpy(ddst, in, nb, hipMemcpyHostToDevice);
+      in += nb;
+      return e;
+    };
+    HIPCHECK(get(L.P, L.nparam * sizeof(float)));
+    HIPCHECK(get(L.Mo, L.nparam * sizeof(float)));
+    HIPCHECK(get(L.Vo, L.nparam * sizeof(float)));
+    HIPCHECK(get(L.mean, L.F * sizeof(float)));
+    HIPCHECK(get(L.istd, L.F * sizeof(float)));
+    HIPCHECK(get(L.tsc, 2 * sizeof(float)));
+    HIPCHECK(get(L.Xbuf, (size_t)h.count * L.F * sizeof(float)));
+    HIPCHECK(get(L.Tbuf, (size_t)h.count * L.O * sizeof(float)));
+    HIPCHECK(launch_to_bf16(L.nparam, L.P, L.Wb, st));
+    HIPCHECK(hipStreamSynchronize(st));
+    L.count = h.count;
+    L.head = h.head;
+    L.t = h.t;
+    L.epoch = h.epoch;
+    L.stats_ready = h.stats_ready != 0;
+    L.capture_on = h.capture_on != 0;
+  }
   return RBM_OK;
 }

@@ -13,7 +13,7 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "librbm.so")
 
-RBM_OK, RBM_E_INVAL, RBM_E_NOMEM, RBM_E_DEVICE, RBM_E_NOCONV, RBM_E_STATE = 0, -1, -2, -3, -4, -6
+RBM_OK, RBM_E_INVAL, RBM_E_NOMEM, RBM_E_DEVICE, RBM_E_NOCONV, RBM_E_OVERLAP, RBM_E_STATE = 0, -1, -2, -3, -4, -5, -6
 FP64, MIXED_FP32, MIXED_BF16 = 0, 1, 2
 GUESS_ZERO, GUESS_BLOCKDIAG, GUESS_USER, GUESS_LEARNED = 0, 1, 2, 3
 
@@ -27,7 +27,8 @@ EXPORTED = [
     "rbm_learned_get_params", "rbm_learned_set_params", "rbm_learned_forward_dev",
     "rbm_learned_loss_grad_dev", "rbm_learned_features_dev", "rbm_learned_guess_dev", "rbm_set_guess",
     "rbm_apply_dev", "rbm_find_contacts", "rbm_solve_contacts", "rbm_magnetic_traction_dev",
-    "rbm_solve_density_dev", "rbm_step_rk4_magnetic", "rbm_far_traction_fmm",
+    "rbm_solve_density_dev", "rbm_step_rk4_magnetic", "rbm_far_traction_fmm", "rbm_mobility_matrix",
+    "rbm_get_state", "rbm_set_state",
 ]
 
 
@@ -38,7 +39,7 @@ class Options(ctypes.Structure):
                 ("stream", ctypes.c_void_p), ("p_up", ctypes.c_int), ("near_factor", ctypes.c_double),
                 ("contact_delta", ctypes.c_double), ("magnetic", ctypes.c_int),
                 ("fmm_order", ctypes.c_int), ("fmm_max_level", ctypes.c_int),
-                ("gmres_lookahead", ctypes.c_int)]
+                ("gmres_lookahead", ctypes.c_int), ("ir_stall", ctypes.c_double)]
 
 
 class SolveInfo(ctypes.Structure):
@@ -52,7 +53,7 @@ class SolveInfo(ctypes.Structure):
                 ("init_rel_residual", ctypes.c_double), ("near_pairs", ctypes.c_int),
                 ("ms_near", ctypes.c_double), ("fmm_level", ctypes.c_int),
                 ("fmm_applies", ctypes.c_int), ("n_traction32", ctypes.c_int),
-                ("ms_traction32", ctypes.c_double)]
+                ("ms_traction32", ctypes.c_double), ("fp64_cycles", ctypes.c_int)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -116,6 +117,9 @@ def load():
         "rbm_solve_density_dev": (I, [P, P, P, P]),
         "rbm_step_rk4_magnetic": (I, [P, D, P, D, D, D, P]),
         "rbm_far_traction_fmm": (I, [P, I, I, P, P, P, D, P, I, P]),
+        "rbm_mobility_matrix": (I, [P, P, P]),
+        "rbm_get_state": (I, [P, P, P]),
+        "rbm_set_state": (I, [P, P, S]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -155,7 +159,7 @@ class Solver:
                  max_iter=100, max_restart=4, precision=FP64, guess=GUESS_BLOCKDIAG,
                  inner_tol=1e-4, n_max=None, stream=None, device="cuda", p_up=0, near_factor=5.0,
                  contact_delta=0.0, magnetic=0, fmm_order=0, fmm_max_level=5,
-                 gmres_lookahead=1):
+                 gmres_lookahead=1, ir_stall=0.5):
         import torch
         lib = load()
         self.torch = torch
@@ -169,6 +173,7 @@ class Solver:
         opt.magnetic = magnetic
         opt.fmm_order, opt.fmm_max_level = fmm_order, fmm_max_level
         opt.gmres_lookahead = gmres_lookahead
+        opt.ir_stall = ir_stall
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
         opt.stream = ctypes.c_void_p(self.stream.cuda_stream)
         self.opt = opt
@@ -215,7 +220,6 @@ class Solver:
         sid = np.ascontiguousarray(shape_id, dtype=np.int32)
         cen = _f64(centres, (-1, 3))
         q = _f64(quats, (-1, 4))
-        q = q / np.linalg.norm(q, axis=1)[:, None]
         _check(lib.rbm_set_bodies(self.ctx, len(sid), _ptr(sid), _ptr(cen), _ptr(q)))
         self.n = len(sid)
         self.N = self.n * self.M
@@ -239,6 +243,27 @@ class Solver:
                     allow=(RBM_E_NOCONV,))
         self.last_status = st
         return info.as_dict()
+
+    def mobility_matrix(self):
+        """(6n, 6n) mobility matrix at the current poses and the summed solve info."""
+        m = 6 * self.n
+        Mm = np.zeros((m, m))
+        info = SolveInfo()
+        st = _check(load().rbm_mobility_matrix(self.ctx, _ptr(Mm), ctypes.byref(info)), allow=(RBM_E_NOCONV,))
+        self.last_status = st
+        return Mm, info.as_dict()
+
+    def get_state(self):
+        """The run state as a bytes object."""
+        nb = ctypes.c_size_t()
+        _check(load().rbm_get_state(self.ctx, None, ctypes.byref(nb)))
+        buf = ctypes.create_string_buffer(nb.value)
+        _check(load().rbm_get_state(self.ctx, buf, ctypes.byref(nb)))
+        return buf.raw[:nb.value]
+
+    def set_state(self, state):
+        buf = ctypes.create_string_buffer(bytes(state), len(state))
+        _check(load().rbm_set_state(self.ctx, buf, len(state)))
 
     def apply_dev(self, mu_dev):
         """y = A mu at the current poses; mu_dev: float64 (3, N) CUDA tensor."""

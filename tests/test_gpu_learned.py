@@ -218,3 +218,80 @@ def test_capture_buffer_is_a_ring():
         assert np.abs(X[rows] - ref).max() < 2e-6 * np.abs(ref).max()
     assert np.isfinite(s.learned_train(2, 8, 1e-3))
     s.close()
+
+
+def _unflat(flat, dims):
+    out, off = [], 0
+    for a, b in zip(dims[:-1], dims[1:]):
+        W = flat[off:off + a * b].reshape(a, b).astype(np.float64)
+        off += a * b
+        out.append((W, flat[off:off + b].astype(np.float64)))
+        off += b
+    return out
+
+
+def test_training_step_matches_oracle_standardisation_gradients_and_adam():
+    """One rbm_learned_train epoch whose single batch holds every captured sample: the
+    feature standardisation and target scale fixed from the buffer, the bf16 gradients and
+    the Adam update (moments, bias-corrected step) against the oracle's statistics,
+    loss_and_grads and adam_step on the same samples and initial weights."""
+    _case("training step vs oracle: 12 samples, layers F-32-32-O")
+    w = inputs.tiny(4, 6, seed=46)
+    s = rbm.solver_for(w, tol=1e-12)
+    info = s.learned_bind(k_nbr=3, hidden=32, n_hidden=2, capacity=12, batch_max=16, seed=9)
+    F, O, npar = info["F"], info["O"], info["n_params"]
+    rng = np.random.default_rng(12)
+    for _ in range(3):
+        FT = torch.as_tensor(rng.standard_normal((4, 6)), device="cuda")
+        VW = torch.zeros_like(FT)
+        s.solve_dev(FT, VW)
+        s.learned_capture(FT)
+    assert s.learned_info()["samples"] == 12
+    P0 = s.learned_params()[:npar]
+    X = s.read("learned_X", 12 * F, dtype=np.float32).reshape(12, F).astype(np.float64)
+    T = s.read("learned_T", 12 * O, dtype=np.float32).reshape(12, O).astype(np.float64)
+    lr = 1e-3
+    loss = s.learned_train(1, 12, lr)
+    after = s.learned_params()
+    P1, mean, istd, tsc = after[:npar], after[npar:npar + F], after[npar + F:npar + 2 * F], after[-2:]
+    m_g = s.read("learned_m", npar, dtype=np.float32).astype(np.float64)
+    v_g = s.read("learned_v", npar, dtype=np.float32).astype(np.float64)
+    # standardisation and target scale
+    mean_o = X.mean(axis=0)
+    var_o = X.var(axis=0)
+    istd_o = np.where(var_o > 1e-20, 1.0 / np.sqrt(np.maximum(var_o, 1e-300)), 0.0)
+    rms_o = math.sqrt(np.mean(T * T))
+    assert np.abs(mean - mean_o).max() <= 1e-6 * max(np.abs(mean_o).max(), 1.0)
+    assert np.abs(istd - istd_o).max() <= 1e-6 * np.abs(istd_o).max()
+    assert abs(tsc[0] - rms_o) <= 1e-6 * rms_o and abs(tsc[1] - 1.0 / rms_o) <= 1e-6 / rms_o
+    # gradients and Adam on the oracle
+    dims = [F, 32, 32, O]
+    params0 = _unflat(P0, dims)
+    Xs = (X - mean_o) * istd_o
+    loss_o, grads = mlp.loss_and_grads(params0, Xs, T / rms_o, bf16=True)
+    state = {"t": 0, "m": [[np.zeros_like(W), np.zeros_like(b)] for W, b in params0],
+             "v": [[np.zeros_like(W), np.zeros_like(b)] for W, b in params0]}
+    params1 = mlp.adam_step(params0, grads, state, lr)
+    assert abs(loss - loss_o) < 1e-2 * loss_o
+    flat = lambda lst: np.concatenate([np.concatenate([a.reshape(-1), b]) for a, b in lst])  # noqa: E731
+    m_o, v_o, g_o, P1_o = flat(state["m"]), flat(state["v"]), flat(grads), flat(params1)
+    off = 0
+    for a, b in zip(dims[:-1], dims[1:]):
+        for size in (a * b, b):
+            sl = slice(off, off + size)
+            off += size
+            for got, ref in ((m_g[sl], m_o[sl]), (v_g[sl], v_o[sl])):
+                nr = np.linalg.norm(ref)
+                if nr == 0.0:
+                    assert np.abs(got).max() == 0.0
+                    continue
+                assert got @ ref / (np.linalg.norm(got) * nr) > 0.999
+                assert np.linalg.norm(got - ref) / nr < 6e-2
+            # Adam's first step moves each parameter by lr g / (|g| + eps): the two sides agree
+            # except where bf16 rounding flips the sign of a gradient that is small next to
+            # the tensor's largest
+            d = np.abs(P1[sl] - P1_o[sl])
+            big = np.abs(g_o[sl]) > 0.05 * np.abs(g_o[sl]).max()
+            assert d[big].max(initial=0.0) < 1e-3 * lr + 1e-7 * np.abs(P1_o[sl]).max()
+            assert np.mean(d > 1e-3 * lr + 1e-7 * np.abs(P1_o[sl]).max()) < 0.03
+    s.close()
