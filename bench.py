@@ -340,8 +340,11 @@ def main_learned_experiment(args):
     FT = torch.as_tensor(np.asarray(w["FT"], dtype=np.float64), device=dev)
     VW = torch.zeros_like(FT)
     prec = {"fp64": rbm.FP64, "fp32": rbm.MIXED_FP32, "bf16": rbm.MIXED_BF16}[args.precision]
+    p_up, fmm, _ = WORKLOAD_DEFAULTS.get(args.workload, (0, 0, 4))
+    p_up = p_up if args.p_up is None else args.p_up
+    fmm = fmm if args.fmm is None else args.fmm
     s, dt, learned = _train_on_trajectory(rbm, torch, w, FT, args.tol, args.train_steps, args.epochs,
-                                          1e-3, prec)
+                                          1e-3, prec, p_up=p_up, fmm_order=fmm if prec != rbm.FP64 else 0)
     _log(f"trained: {learned}")
     rows = []
     for k in range(args.eval_steps):
