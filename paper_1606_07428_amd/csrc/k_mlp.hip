@@ -125,7 +125,12 @@ __global__ __launch_bounds__(256) void k_gemm_bf16_tile16(int m, int n, int k,
 hipError_t launch_gemm_bf16(int m, int n, int k, const uint16_t* A, long sa0, long sa1,
                             const uint16_t* B, long sb0, long sb1, float* C, int ldc,
                             const float* bias, float alpha, float beta, hipStream_t st) {
-  if (m <= 128) {
+  // The network's products (at most a few thousand 16x16 output tiles: inference, and the
+  // training batches' forward, weight-gradient and input-gradient products) take one
+  // workgroup per 16x16 tile, so that even a 256 x 256 x 256 product fills 256 workgroups;
+  // larger ones the 64x64-tile kernel.
+  const long tiles16 = (long)((m + 15) / 16) * ((n + 15) / 16);
+  if (tiles16 <= 8192) {
     const long tiles = (long)((m + 15) / 16) * ((n + 15) / 16);
     k_gemm_bf16_tile16<<<(unsigned)tiles, 256, 0, st>>>(m, n, k, A, sa0, sa1, B, sb0, sb1, C, ldc, bias,
                                                          alpha, beta);
@@ -192,32 +197,57 @@ hipError_t launch_mse(size_t cnt, float inv, const float* Y, const float* T, flo
   return hipGetLastError();
 }
 
+// out[0] = scale * sum(part); with accumulate, out[1] += out[0] as well (a running sum of
+// the batch losses of an epoch, read once at its end).
 __global__ __launch_bounds__(256) void k_sum_parts(int nparts, const double* part, double scale,
-                                                   double* out) {
+                                                   double* out, int accumulate) {
   __shared__ double red[4];
   double a = 0.0;
   for (int i = threadIdx.x; i < nparts; i += 256) a += part[i];
   const double s = block_sum(a, red);
-  if (threadIdx.x == 0) out[0] = s * scale;
+  if (threadIdx.x == 0) {
+    out[0] = s * scale;
+    if (accumulate) out[1] += s * scale;
+  }
 }
 
-hipError_t launch_sum_parts(int nparts, const double* part, double scale, double* out,
+hipError_t launch_sum_parts(int nparts, const double* part, double scale, double* out, int accumulate,
                             hipStream_t st) {
-  k_sum_parts<<<1, 256, 0, st>>>(nparts, part, scale, out);
+  k_sum_parts<<<1, 256, 0, st>>>(nparts, part, scale, out, accumulate);
   return hipGetLastError();
 }
 
-// db[j] = sum_i dZ[i][j] (fixed order)
-__global__ void k_colsum(int rows, int cols, const float* dZ, float* db) {
-  const int j = blockIdx.x * blockDim.x + threadIdx.x;
-  if (j >= cols) return;
-  float a = 0.f;
-  for (int i = 0; i < rows; ++i) a += dZ[(size_t)i * cols + j];
-  db[j] = a;
+// db[j] = sum_i dZ[i][j] in a fixed order.  A workgroup takes 16 columns; its 256 threads
+// are 16 row groups x 16 columns, row group g summing rows g, g + 16, ... (four independent
+// accumulators, so eight loads of each lane are in flight), and the 16 group sums of a
+// column are added in group order through LDS.
+__global__ __launch_bounds__(256) void k_colsum(int rows, int cols, const float* __restrict__ dZ,
+                                                float* __restrict__ db) {
+  __shared__ float red[16][17];
+  const int c = threadIdx.x & 15, g = threadIdx.x >> 4;
+  const int j = blockIdx.x * 16 + c;
+  float a0 = 0.f, a1 = 0.f, a2 = 0.f, a3 = 0.f;
+  if (j < cols) {
+    int i = g;
+    for (; i + 48 < rows; i += 64) {
+      a0 += dZ[(size_t)i * cols + j];
+      a1 += dZ[(size_t)(i + 16) * cols + j];
+      a2 += dZ[(size_t)(i + 32) * cols + j];
+      a3 += dZ[(size_t)(i + 48) * cols + j];
+    }
+    for (; i < rows; i += 16) a0 += dZ[(size_t)i * cols + j];
+  }
+  red[g][c] = (a0 + a1) + (a2 + a3);
+  __syncthreads();
+  if (g == 0 && j < cols) {
+    float v = 0.f;
+    for (int k = 0; k < 16; ++k) v += red[k][c];
+    db[j] = v;
+  }
 }
 
 hipError_t launch_colsum(int rows, int cols, const float* dZ, float* db, hipStream_t st) {
-  k_colsum<<<(cols + 63) / 64, 64, 0, st>>>(rows, cols, dZ, db);
+  k_colsum<<<(cols + 15) / 16, 256, 0, st>>>(rows, cols, dZ, db);
   return hipGetLastError();
 }
 

@@ -133,7 +133,7 @@ hipError_t launch_silu_bwd(size_t cnt, const float* dH, const float* Z, float* d
                            hipStream_t st);
 hipError_t launch_mse(size_t cnt, float inv, const float* Y, const float* T, float* dY,
                       uint16_t* dYb, double* part, hipStream_t st);
-hipError_t launch_sum_parts(int nparts, const double* part, double scale, double* out,
+hipError_t launch_sum_parts(int nparts, const double* part, double scale, double* out, int accumulate,
                             hipStream_t st);
 hipError_t launch_colsum(int rows, int cols, const float* dZ, float* db, hipStream_t st);
 hipError_t launch_adam(size_t cnt, float* P, const float* G, float* m, float* v, float lr, float b1,

@@ -1973,14 +1973,15 @@ static rbm_status mlp_forward(rbm_ctx* c, int rows) {
   return RBM_OK;
 }
 
-// Loss against L.Tb (scaled targets) and gradients into L.G; loss value in L.lsum[0].
-static rbm_status mlp_backward(rbm_ctx* c, int rows) {
+// Loss against L.Tb (scaled targets) and gradients into L.G; loss value in L.lsum[0], and
+// added to the running sum L.lsum[1] when accumulate is set.
+static rbm_status mlp_backward(rbm_ctx* c, int rows, int accumulate = 0) {
   auto& L = c->L;
   const int last = L.L - 1, O = L.dims[last + 1];
   const size_t cnt = (size_t)rows * O;
   const int nparts = (int)((cnt + 255) / 256);
   HIPCHECK(launch_mse(cnt, 1.f / (float)cnt, L.Z[last], L.Tb, L.dZ[last], L.dZb[last], L.lpart, c->st));
-  HIPCHECK(launch_sum_parts(nparts, L.lpart, 1.0 / (double)cnt, L.lsum, c->st));
+  HIPCHECK(launch_sum_parts(nparts, L.lpart, 1.0 / (double)cnt, L.lsum, accumulate, c->st));
   for (int l = last; l >= 0; --l) {
     const int in = L.dims[l], out = L.dims[l + 1];
     const uint16_t* Aprev = l == 0 ? L.Xb : L.Hb[l - 1];
@@ -2069,7 +2070,8 @@ extern "C" rbm_status rbm_learned_train(rbm_ctx* c, int epochs, int batch, doubl
     for (int i = 0; i < L.count; ++i) perm[i] = i;
     std::shuffle(perm.begin(), perm.end(), rng);
     HIPCHECK(hipMemcpyAsync(L.idx, perm.data(), L.count * sizeof(int), hipMemcpyHostToDevice, st));
-    double acc = 0.0;
+    // the batch losses are summed on the device (lsum[1]) and read once per epoch
+    HIPCHECK(hipMemsetAsync(L.lsum + 1, 0, sizeof(double), st));
     int nb = 0;
     for (int off = 0; off < L.count; off += batch) {
       const int rows = std::min(batch, L.count - off);
@@ -2077,14 +2079,14 @@ extern "C" rbm_status rbm_learned_train(rbm_ctx* c, int epochs, int batch, doubl
                              tsc[1], L.Tb, st));
       rbm_status s;
       if ((s = mlp_forward(c, rows)) != RBM_OK) return s;
-      if ((s = mlp_backward(c, rows)) != RBM_OK) return s;
+      if ((s = mlp_backward(c, rows, 1)) != RBM_OK) return s;
       HIPCHECK(launch_adam(L.nparam, L.P, L.G, L.Mo, L.Vo, (float)lr, 0.9f, 0.999f, 1e-8f, ++L.t,
                            L.Wb, st));
-      double lv;
-      if ((s = read_scalar(c, L.lsum, &lv)) != RBM_OK) return s;
-      acc += lv;
       ++nb;
     }
+    double acc;
+    rbm_status s;
+    if ((s = read_scalar(c, L.lsum + 1, &acc)) != RBM_OK) return s;
     last = acc / nb;
   }
   HIPCHECK(hipStreamSynchronize(st));
