@@ -221,10 +221,8 @@ template hipError_t launch_pack_sources<float>(int, int, const double*, const do
                                                const double*, const double*, int, double*, void*,
                                                hipStream_t);
 
-// out = ca*a + cb*(R_i b_body) + cp*sum_s part[s]   (fixed summation order).
-// One thread per (component, point): the slot sum over the split is the memory-bound
-// part, so it gets 3N threads and four independent accumulators (slots s = 4k + j go
-// to accumulator j, combined as ((j0 + j1) + (j2 + j3))).  out may be a, not b_body.
+// out = ca*a + cb*(R_i b_body) + cp*sum_s part[s]   (fixed summation order); out may be
+// a, not b_body.  The slot sum over the split is the memory-bound part.
 // 64 outputs per workgroup: wave q of the four sums slots s = q, q + 4, ... of them in
 // increasing s (each load a coalesced 512-byte segment), and wave 0 adds the four sums as
 // (s0 + s1) + (s2 + s3), so every output is the same as with one thread and four
