@@ -39,7 +39,7 @@ def test_setup_tables_match_oracle(n, p, seed, pu, kappa):
     assert np.abs(U - U_o).max() < 1e-13 * np.abs(U_o).max()
     prob = oracle_problem(w, with_ops=False, upsample=(pu, kappa))
     for k in range(len(w["shapes"])):
-        fo = prob.fine[k]
+        fo = prob.fine(k)
         fr = s.read("fr", 3 * Mu, offset=k * 3 * Mu * 8).reshape(3, Mu)
         fw = s.read("fw", Mu, offset=k * Mu * 8)
         rb = s.read("rb", 1, offset=k * 8)[0]
