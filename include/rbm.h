@@ -400,6 +400,22 @@ rbm_status rbm_far_stokeslet(rbm_ctx* ctx, int n_points, int M, const double* X,
 rbm_status rbm_far_traction_fmm(rbm_ctx* ctx, int n_points, int M, const double* X, const double* Nrm,
                                 const double* q, double d_max, double* y, int precision, int* level);
 
+/* rbm_far_traction_static: the sum of rbm_far_traction (same arguments, same kernels and
+ *   split rule, so the same result) for callers that cannot allocate device memory: code
+ *   under HIP graph capture, tight serving loops, harnesses that forbid allocation.  It needs
+ *   no context and calls no allocator: its scratch (packed sources, the split's partial
+ *   sums, float32 copies of X and Nrm) is a 64 MiB array in device memory that every GPU
+ *   the library runs on holds until the process ends.  At most about 762,000 points in
+ *   float64 (precision 0) and 838,000 in float32 (precision 1); more return RBM_E_NOMEM.
+ *   X, Nrm, q, add (may be NULL), y: device pointers, [3][n_points] float64; body of point k
+ *   is k / M.  Work is issued on `stream` (hipStream_t, NULL = the default stream) on the
+ *   current device and the call returns without waiting.  Every call on one GPU shares that
+ *   GPU's scratch, which keeps the last call's contents: calls that overlap on one GPU (other
+ *   streams, other host threads) race. */
+rbm_status rbm_far_traction_static(int n_points, int M, const double* X, const double* Nrm,
+                                   const double* q, const double* add, double* y, int precision,
+                                   void* stream);
+
 const char* rbm_last_error(void);
 
 #ifdef __cplusplus

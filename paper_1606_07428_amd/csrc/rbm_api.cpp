@@ -26,6 +26,11 @@ static rbm_status fail(rbm_status s, const std::string& msg) {
   return s;
 }
 
+// The thread-local message of rbm_last_error(), for the entry points of other translation units.
+namespace rbm {
+rbm_status set_last_error(rbm_status s, const char* msg) { return fail(s, msg); }
+}  // namespace rbm
+
 #define HIPCHECK(expr)                                                              \
   do {                                                                              \
     hipError_t e_ = (expr);                                                         \

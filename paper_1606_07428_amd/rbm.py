@@ -28,7 +28,7 @@ EXPORTED = [
     "rbm_learned_loss_grad_dev", "rbm_learned_features_dev", "rbm_learned_guess_dev", "rbm_set_guess",
     "rbm_apply_dev", "rbm_find_contacts", "rbm_solve_contacts", "rbm_magnetic_traction_dev",
     "rbm_solve_density_dev", "rbm_step_rk4_magnetic", "rbm_far_traction_fmm", "rbm_mobility_matrix",
-    "rbm_get_state", "rbm_set_state",
+    "rbm_get_state", "rbm_set_state", "rbm_far_traction_static",
 ]
 
 
@@ -120,6 +120,7 @@ def load():
         "rbm_mobility_matrix": (I, [P, P, P]),
         "rbm_get_state": (I, [P, P, P]),
         "rbm_set_state": (I, [P, P, S]),
+        "rbm_far_traction_static": (I, [I, I, P, P, P, P, P, I, P]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -461,6 +462,20 @@ class Solver:
             self.close()
         except Exception:
             pass
+
+
+def far_traction_static(X, Nrm, q, M, add=None, precision=0, stream=None):
+    """rbm_far_traction_static on float64 (3, n) CUDA tensors (no context, no allocation by the
+    library); returns y (3, n), allocated here by PyTorch, on `stream` (default: current)."""
+    import torch
+    n = X.shape[1]
+    y = torch.empty_like(X)
+    st = stream if stream is not None else torch.cuda.current_stream(X.device)
+    a = ctypes.c_void_p(add.data_ptr()) if add is not None else None
+    _check(load().rbm_far_traction_static(n, M, ctypes.c_void_p(X.data_ptr()), ctypes.c_void_p(Nrm.data_ptr()),
+                                          ctypes.c_void_p(q.data_ptr()), a, ctypes.c_void_p(y.data_ptr()),
+                                          precision, ctypes.c_void_p(st.cuda_stream)))
+    return y
 
 
 def solver_for(workload, **kw):
