@@ -483,6 +483,34 @@ PAPER_TABLE2 = {(32, 8): (1.09, 10.25), (64, 8): (2.26, 19.51), (128, 8): (4.75,
                 (32, 16): (10.7, 108.9), (64, 16): (21.5, 220.3), (128, 16): (42.9, 439.9)}
 
 
+def main_apply(args):
+    """Float64 operator applications y = A mu (the matvec of the hot path) at a workload, with
+    the near-singular upsampling its solves use: setup, then K timed applications of random
+    densities.  Short enough to run under hardware counters."""
+    import torch
+    from paper_1606_07428_amd import inputs, rbm
+
+    w = inputs.workload(args.workload)
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    p_up = WORKLOAD_DEFAULTS.get(args.workload, (0, 0, 4))[0] if args.p_up is None else args.p_up
+    s = rbm.solver_for(w, tol=args.tol, precision=rbm.FP64, p_up=p_up)
+    mu = torch.randn(3, s.N, dtype=torch.float64, device=dev, generator=torch.Generator(device=dev).manual_seed(0))
+    s.apply_dev(mu)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        s.apply_dev(mu)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / args.steps
+    N = s.N
+    pairs = float(N) * N - float(s.n) * s.M * s.M
+    print(json.dumps({"experiment": "float64 operator applications", "workload": args.workload, "points": N,
+                      "p_up": p_up, "applications": args.steps, "apply_ms": dt * 1e3,
+                      "pairs_per_apply": pairs}), flush=True)
+    s.close()
+
+
 def main_lattice(args):
     """Per-matvec and per-solve times on the paper's sphere lattice (float64, block-diagonal
     guess, tolerance 1e-6 as in the paper), next to the paper's Table 2."""
@@ -618,6 +646,8 @@ def main():
     ap.add_argument("--fmm", type=int, default=None,
                     help="fast multipole order of the inner far sums (default per workload); in compare "
                          "mode adds mixed forms whose inner iterations use it")
+    ap.add_argument("--apply", action="store_true",
+                    help="only time float64 operator applications (y = A mu) at the workload")
     ap.add_argument("--lattice", action="store_true",
                     help="per-matvec and per-solve times on the paper's sphere lattice (Table 2)")
     ap.add_argument("--mhd", action="store_true",
@@ -642,6 +672,10 @@ def main():
               "(bodies sharded across GPUs, sources all-gathered per matvec) is not implemented",
               file=sys.stderr)
         sys.exit(2)
+    if args.apply:
+        args.workload = args.workload or "dense4000"
+        main_apply(args)
+        return
     if args.compare:
         args.workload = args.workload or "ellipsoids1000"
         main_compare(args)

@@ -120,6 +120,9 @@ typedef struct {
                            ir_stall times the previous one counts as stalled, and the remaining
                            refinements run their GMRES cycles with float64 operators (exact far
                            sums, float64 preconditioner) to the tolerance; 0 -> 0.5 */
+  int velocity_fusion;  /* 1 (default): when a float64 residual is predicted to meet tol, its
+                           traction sum and the velocities' Stokeslet sum of the same density
+                           rho + mu come from one fused pass; 0: always a separate Stokeslet sum */
 } rbm_options;
 
 typedef struct {
@@ -149,11 +152,15 @@ typedef struct {
   double ms_traction32; /* their summed duration (ms) */
   int fp64_cycles;    /* precision form: GMRES cycles run with float64 operators after a stalled
                          refinement (see rbm_options.ir_stall) */
+  int n_fused;        /* float64 residuals evaluated by the fused traction + Stokeslet pass (when
+                         the residual was predicted to meet tol) */
+  int fused_used;     /* 1 if the velocities took the Stokeslet sum of such a pass */
+  double ms_fused;    /* summed duration of the fused pass launches (ms) */
 } rbm_solve_info;
 
 /* Default options: p = 8, p_sing = 0, eta = 1, tol = 1e-12, max_iter = 100,
  * max_restart = 4, RBM_FP64, RBM_GUESS_BLOCKDIAG, inner_tol = 1e-4, stream NULL,
- * ir_stall = 0.5. */
+ * ir_stall = 0.5, velocity_fusion = 1. */
 void rbm_default_options(rbm_options* opt);
 
 /* Create a context.  Validates opt; no device work. */

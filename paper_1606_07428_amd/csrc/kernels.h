@@ -95,6 +95,10 @@ hipError_t launch_pack_sources(int N, int M, const double* X, const double* W, c
 template <typename T>
 hipError_t launch_far(int kind, int N, int M, const T* tx, const T* nrm, const void* src,
                       double* part, int nsplit, hipStream_t st);
+// float64 traction (into part_t, as kind 0) and Stokeslet (into part_u, as kind 1) sums of the
+// same packed sources in one pass, nsplit partial sums each
+hipError_t launch_far_ts(int N, int M, const double* tx, const double* nrm, const void* src, double* part_t,
+                         double* part_u, int nsplit, hipStream_t st);
 // out[3][N] = ca * a[3][N] (optional) + cb * R_i b_body (optional) + cp * sum_s part[s];
 // out may be the same array as a, never as b_body
 hipError_t launch_combine(int N, int M, int nsplit, const double* part, double cp,

@@ -16,6 +16,7 @@
 
 #include "../../include/rbm.h"
 #include "kernels.h"
+#include "far_plan.h"
 
 using namespace rbm;
 
@@ -85,9 +86,12 @@ struct rbm_ctx {
   float* gZ = nullptr;   // shared-shape bf16 GEMM product (3N floats)
   // Krylov
   double *V, *H, *cs, *sn, *g, *y, *scal, *partial;
-  // far field
+  // far field; part_u holds the Stokeslet partial sums of a fused residual evaluation,
+  // valid for the current mu while vel_ready
   void* src;
   double* part;
+  double* part_u = nullptr;
+  bool vel_ready = false;
   // near-singular correction by upsampling (p_up > 0)
   int pu = 0, Mu = 0, near_pairs = 0;
   double kappa = 5.0;
@@ -169,6 +173,7 @@ extern "C" void rbm_default_options(rbm_options* o) {
   o->fmm_max_level = 5;
   o->gmres_lookahead = 1;
   o->ir_stall = 0.5;
+  o->velocity_fusion = 1;
 }
 
 extern "C" const char* rbm_last_error(void) { return g_err.c_str(); }
@@ -196,6 +201,7 @@ extern "C" rbm_status rbm_create(const rbm_options* opt, rbm_ctx** out) {
     return fail(RBM_E_INVAL, "fmm_max_level must be 0 or in [2, 6]");
   if (opt->gmres_lookahead < 0 || opt->gmres_lookahead > 2) return fail(RBM_E_INVAL, "gmres_lookahead in [0, 2]");
   if (!(opt->ir_stall >= 0.0 && opt->ir_stall < 1.0)) return fail(RBM_E_INVAL, "ir_stall in [0, 1)");
+  if (opt->velocity_fusion != 0 && opt->velocity_fusion != 1) return fail(RBM_E_INVAL, "velocity_fusion is 0 or 1");
   rbm_ctx* c = new rbm_ctx();
   c->opt = *opt;
   if (c->opt.fmm_max_level == 0) c->opt.fmm_max_level = 5;
@@ -280,25 +286,6 @@ extern "C" rbm_status rbm_set_bodies(rbm_ctx* c, int n, const int* shape_id, con
   return RBM_OK;
 }
 
-// Source-range split of the far sum for N points.  The grid has nbx = ceil(N/256)
-// target blocks (one target per lane) times `split` source chunks; 256 CUs hold 2048
-// resident 4-wave workgroups, and about six rounds of them balance the waves' finish
-// times (measured on MI355X: at 20k points six rounds are 5 % faster in float64 and
-// 12 % in float32 than one), so split = ceil(6 * 2048 / nbx), at most 96 and nbx.
-static int far_split(int N) {
-  const int nbx = (N + 255) / 256;
-  const int want = (6 * 2048 + nbx - 1) / nbx;
-  return std::max(1, std::min(want, std::min(96, nbx)));
-}
-
-// Bound, non-decreasing in N, of split * points over all sizes up to N: with nbx' target
-// blocks the product is at most min(96, nbx') N' and at most (6*2048/nbx' + 1) * 256 nbx'.
-// The partial-sum buffer holds that many points' worth of slots.
-static size_t far_part_cap(size_t N) {
-  const size_t nbx = (N + 255) / 256;
-  return std::min(std::min<size_t>(96, nbx) * N, (size_t)6 * 2048 * 256 + N + 256);
-}
-
 // Split of the source range for N points, bounded by the partial-sum buffer.
 static int split_for(const rbm_ctx* c, int N) {
   const size_t cap = far_part_cap((size_t)c->nmax * c->M);
@@ -357,6 +344,7 @@ static size_t layout(rbm_ctx* c, int nmax, bool assign) {
   take(srcd, 8 * N);
   if (assign) c->src = srcd;
   take(c->part, 3 * (far_part_cap(N) + (c->pu ? N : 0)));
+  take(c->part_u, 3 * (far_part_cap(N) + (c->pu ? N : 0)));
   take(c->ccand, 2 * (size_t)kContactCand * nm); take(c->cres, 5 * (size_t)kContactCand * nm);
   if (c->opt.magnetic) {
     take(c->SL0, ns * M * M); take(c->KL0, ns * M * M);
@@ -652,7 +640,8 @@ struct Timer {
 struct SolveState {
   // event index pairs: float64 traction sums, float32 (direct or fast multipole) traction
   // sums, Stokeslet sums, self applies, near corrections
-  std::vector<std::pair<int, int>> trac_ev, trac32_ev, stok_ev, self_ev, near_ev;
+  std::vector<std::pair<int, int>> trac_ev, trac32_ev, stok_ev, self_ev, near_ev, fused_ev;
+  bool fused_used = false;
   double far_pairs = 0.0;
   int matvecs = 0;
   int fmm_applies = 0;
@@ -667,10 +656,10 @@ static int far_slots(const rbm_ctx* c, int N) { return split_for(c, N) + (c->pu 
 // bodies, fine-minus-plain sums per work item, reduced per body into the slot after the
 // far split.
 static rbm_status near_correction(rbm_ctx* c, SolveState& S, int kind, const double* x,
-                                  int x_is_body, int prec) {
+                                  int x_is_body, int prec, double* part = nullptr) {
   if (!c->pu) return RBM_OK;
   const int n = c->n, M = c->M, N = n * M;
-  double* res = c->part + (size_t)c->far_base * 3 * N;
+  double* res = (part ? part : c->part) + (size_t)c->far_base * 3 * N;
   const int* ib = c->nitem;
   const int* ip = c->nitem + c->n_items;
   Timer t(c);
@@ -911,7 +900,7 @@ static rbm_status read_scalar(rbm_ctx* c, const double* d, double* h) {
 // V_0 = r/||r||; stops when the residual estimate <= abs_tol or after max_iter.
 // On exit mu += P~^{-1} V y (lab frame).  prec: 0 fp64, 1 fp32, 2 bf16 operators.
 static rbm_status gmres_cycle(rbm_ctx* c, SolveState& S, int prec, const double* r, double rnorm,
-                              double abs_tol, int* iters) {
+                              double abs_tol, int* iters, double* est = nullptr) {
   const size_t len = 3 * (size_t)c->n * c->M;
   const int m = c->opt.max_iter;
   const int ldh = m + 1;
@@ -938,6 +927,7 @@ static rbm_status gmres_cycle(rbm_ctx* c, SolveState& S, int prec, const double*
   // buffers; the solution over the first k+1 columns reads H and g up to row k only.
   if ((s = enqueue(0)) != RBM_OK) return s;
   double prev1 = rnorm, prev2 = -1.0;  // estimates after iterations k-1 and k-2
+  double last = rnorm;
   int k = 0;
   for (k = 0; k < m; ++k) {
     bool ahead = false;
@@ -948,6 +938,7 @@ static rbm_status gmres_cycle(rbm_ctx* c, SolveState& S, int prec, const double*
     double res;
     if ((s = wait_pinned(c, c->pinned + 16 + (k & 1), &res)) != RBM_OK) return s;
     if (!std::isfinite(res)) return fail(RBM_E_DEVICE, "non-finite GMRES residual");
+    last = res;
     if (res <= abs_tol) { ++k; break; }
     if (!ahead && k + 1 < m && (s = enqueue(k + 1)) != RBM_OK) return s;
     prev2 = prev1;
@@ -955,6 +946,7 @@ static rbm_status gmres_cycle(rbm_ctx* c, SolveState& S, int prec, const double*
   }
   if (k > m) k = m;
   *iters = k;
+  if (est) *est = last;
   HIPCHECK(launch_backsolve(k, ldh, c->H, c->g, c->y, c->st));
   HIPCHECK(launch_vupdate(k, len, c->V, len, c->y, c->t2, 1, c->st));
   if ((s = self_apply(c, S, 1, prec, c->t2, c->yb)) != RBM_OK) return s;
@@ -998,13 +990,33 @@ static rbm_status build_rhs(rbm_ctx* c, SolveState& S, const double* dFT, const 
 // Float64 residual r = b - A x without forming b: by linearity
 //   r = -(A_self (rho + x) - L rho) - K_far (rho + x),
 // one exact far sum of rho + x (tmp holds rho + x).
-static rbm_status residual_exact(rbm_ctx* c, SolveState& S, const double* x, double* r, double* tmp) {
+// With `velocity`, the traction and Stokeslet sums of rho + x come from one fused pass: the
+// Stokeslet partial sums stay in part_u (vel_ready) for the velocities, should this residual
+// end the solve.
+static rbm_status residual_exact(rbm_ctx* c, SolveState& S, const double* x, double* r, double* tmp,
+                                 bool velocity = false) {
   const int n = c->n, M = c->M, N = n * M;
   hipStream_t st = c->st;
   rbm_status s;
   HIPCHECK(launch_axpby(3 * (size_t)N, 1.0, c->rho, 1.0, x, tmp, st));
   if ((s = self_apply(c, S, 0, 0, tmp, c->yb)) != RBM_OK) return s;
-  if ((s = far_traction(c, S, tmp, 0, 0)) != RBM_OK) return s;
+  c->vel_ready = false;
+  if (velocity) {
+    const int nsp = split_for(c, N);
+    HIPCHECK(launch_pack_sources<double>(N, M, c->X, c->W, c->Rm, tmp, 0, nullptr, c->src, st));
+    Timer t(c);
+    HIPCHECK(launch_far_ts(N, M, c->X, c->Nn, c->src, c->part, c->part_u, nsp, st));
+    t.stop();
+    if (t.on) S.fused_ev.push_back({c->ev_used - 2, c->ev_used - 1});
+    S.far_pairs += 2.0 * ((double)N * N - (double)n * M * M);
+    c->far_base = nsp;
+    c->far_nslots = nsp + (c->pu ? 1 : 0);
+    if ((s = near_correction(c, S, 0, tmp, 0, 0)) != RBM_OK) return s;
+    if ((s = near_correction(c, S, 1, tmp, 0, 0, c->part_u)) != RBM_OK) return s;
+    c->vel_ready = true;
+  } else if ((s = far_traction(c, S, tmp, 0, 0)) != RBM_OK) {
+    return s;
+  }
   HIPCHECK(launch_combine(N, M, c->far_nslots, c->part, -1.0, nullptr, 0.0, c->yb, c->Rm, -1.0, r, st));
   HIPCHECK(launch_moments(n, M, c->rho, c->X, c->W, c->cen, c->mom, st));
   HIPCHECK(launch_add_rigid(n, M, c->mom, c->X, c->cen, 1.0, r, st));
@@ -1074,6 +1086,19 @@ static rbm_status solve_impl(rbm_ctx* c, const double* dFT, double* dVW, rbm_sol
   // float64 residual not below ir_stall times the previous one); then float64 operators
   int prec_in = prec;
   double rn_prev = -1.0;
+  // The exact residual that ends the solve is evaluated for sigma = rho + mu, the density
+  // whose Stokeslet sum gives the velocities: when the next residual is predicted to meet the
+  // tolerance, both sums come from one fused pass (a wrong prediction costs the Stokeslet
+  // part of that pass, about 0.4 of a traction sum).  Prediction: with float64 operators the
+  // GMRES estimate; in the precision form the estimate plus eps_op times the residual the
+  // cycle started from, eps_op the relative accuracy of the inner operators: at first 1e-4
+  // with fast multipole sums, 2^-22 with float32 direct sums and 2^-8 with bf16 blocks, then
+  // what the last refinement showed (its exact residual beyond its estimate).
+  bool fuse_next = false;
+  double eps_op = c->fmm_ready ? 1e-4 : prec == RBM_MIXED_BF16 ? std::ldexp(1.0, -8) : std::ldexp(1.0, -22);
+  double est_prev = -1.0, rn_cycle = -1.0;
+  int prec_cycle = prec;
+  c->vel_ready = false;
   for (int outer = 0; outer <= max_outer; ++outer) {
     // float64 residual r = b - A mu
     double rn;
@@ -1082,7 +1107,7 @@ static rbm_status solve_impl(rbm_ctx* c, const double* dFT, double* dVW, rbm_sol
       rn = bnorm;
       mu_zero = false;
     } else {
-      if ((s = residual_exact(c, S, c->mu, c->r, c->t1)) != RBM_OK) return s;
+      if ((s = residual_exact(c, S, c->mu, c->r, c->t1, fuse_next)) != RBM_OK) return s;
       if ((s = read_norm(c, c->r, &rn)) != RBM_OK) return s;
     }
     if (outer == 0 && bnorm > 0.0) {
@@ -1110,6 +1135,7 @@ static rbm_status solve_impl(rbm_ctx* c, const double* dFT, double* dVW, rbm_sol
     if (rn <= abs_tol || bnorm == 0.0) { converged = true; break; }
     if (outer == max_outer) break;
     if (prec_in != 0 && rn_prev > 0.0 && !(rn < c->opt.ir_stall * rn_prev)) prec_in = 0;
+    if (est_prev >= 0.0 && prec_cycle != 0) eps_op = std::max(1e-16, (rn - est_prev) / rn_cycle);
     rn_prev = rn;
     double inner_abs = prec_in == 0 ? abs_tol : std::max(c->opt.inner_tol * rn, 0.5 * abs_tol);
     // Float32 inner operators (direct far sum, float32 self blocks) are accurate to about
@@ -1119,15 +1145,26 @@ static rbm_status solve_impl(rbm_ctx* c, const double* dFT, double* dVW, rbm_sol
     if (prec_in == RBM_MIXED_FP32 && !c->fmm_ready && std::ldexp(rn, -22) <= 0.5 * abs_tol)
       inner_abs = 0.5 * abs_tol;
     int it = 0;
-    if ((s = gmres_cycle(c, S, prec_in, c->r, rn, inner_abs, &it)) != RBM_OK) return s;
+    double est = rn;
+    if ((s = gmres_cycle(c, S, prec_in, c->r, rn, inner_abs, &it, &est)) != RBM_OK) return s;
+    c->vel_ready = false;  // mu has changed
     total_iters += it;
     cycles++;
     if (prec != 0) refinements++;
     if (prec != 0 && prec_in == 0) fp64_cycles++;
+    fuse_next = c->opt.velocity_fusion && (prec_in == 0 ? est <= abs_tol : est + eps_op * rn <= abs_tol);
+    est_prev = est;
+    rn_cycle = rn;
+    prec_cycle = prec_in;
   }
-  // velocities u = S[rho + mu]: far Stokeslet sum + self functional, float64
+  // velocities u = S[rho + mu]: far Stokeslet sum (from the fused pass of the last residual
+  // when it was evaluated for this mu) + self functional, float64
   HIPCHECK(launch_axpby(len, 1.0, c->rho, 1.0, c->mu, c->t2, st));
-  {
+  if (c->vel_ready) {
+    S.fused_used = true;
+    HIPCHECK(launch_combine(N, M, far_slots(c, N), c->part_u, 1.0 / c->opt.eta, nullptr, 0.0, nullptr, nullptr,
+                            0.0, c->t1, st));
+  } else {
     HIPCHECK(launch_pack_sources<double>(N, M, c->X, c->W, c->Rm, c->t2, 0, nullptr, c->src, st));
     Timer t(c);
     HIPCHECK(launch_far<double>(1, N, M, c->X, nullptr, c->src, c->part, split_for(c, N), st));
@@ -1136,9 +1173,10 @@ static rbm_status solve_impl(rbm_ctx* c, const double* dFT, double* dVW, rbm_sol
     S.far_pairs += (double)N * N - (double)n * M * M;
     c->far_base = split_for(c, N);
     if ((s = near_correction(c, S, 1, c->t2, 0, 0)) != RBM_OK) return s;
+    HIPCHECK(launch_combine(N, M, far_slots(c, N), c->part, 1.0 / c->opt.eta, nullptr, 0.0, nullptr, nullptr,
+                            0.0, c->t1, st));
   }
-  HIPCHECK(launch_combine(N, M, far_slots(c, N), c->part, 1.0 / c->opt.eta, nullptr, 0.0, nullptr, nullptr,
-                          0.0, c->t1, st));
+  c->vel_ready = false;
   HIPCHECK(launch_moments(n, M, c->t1, c->X, c->W, c->cen, c->mom, st));
   HIPCHECK(launch_velocity_self(n, M, c->sid, c->V0, c->Rm, c->t2, c->vws, st));
   HIPCHECK(launch_velocity_final(n, c->mom, c->vws, c->tauinv, c->area_b, dVW, st));
@@ -1167,6 +1205,8 @@ static rbm_status solve_impl(rbm_ctx* c, const double* dFT, double* dVW, rbm_sol
     info->fmm_level = c->fmm_ready ? c->fmm_level : -1;
     info->fmm_applies = S.fmm_applies;
     info->fp64_cycles = fp64_cycles;
+    info->n_fused = (int)S.fused_ev.size();
+    info->fused_used = S.fused_used ? 1 : 0;
     if (total.on) {
       float ms = 0;
       (void)hipEventElapsedTime(&ms, total.a, total.b);
@@ -1183,7 +1223,11 @@ static rbm_status solve_impl(rbm_ctx* c, const double* dFT, double* dVW, rbm_sol
         (void)hipEventElapsedTime(&ms, c->ev[e.first], c->ev[e.second]);
         info->ms_stokeslet += ms;
       }
-      info->ms_far = info->ms_traction + info->ms_traction32 + info->ms_stokeslet;
+      for (auto& e : S.fused_ev) {
+        (void)hipEventElapsedTime(&ms, c->ev[e.first], c->ev[e.second]);
+        info->ms_fused += ms;
+      }
+      info->ms_far = info->ms_traction + info->ms_traction32 + info->ms_stokeslet + info->ms_fused;
       for (auto& e : S.self_ev) {
         (void)hipEventElapsedTime(&ms, c->ev[e.first], c->ev[e.second]);
         info->ms_self += ms;

@@ -11,6 +11,7 @@
 
 #include "../../include/rbm.h"
 #include "kernels.h"
+#include "far_plan.h"
 
 namespace rbm {
 rbm_status set_last_error(rbm_status s, const char* msg);
@@ -70,10 +71,8 @@ extern "C" rbm_status rbm_far_traction_static(int n_points, int M, const double*
   if (scratch_bytes(N, 1, precision) > kScratchBytes)
     return set_last_error(RBM_E_NOMEM, "more points than the 64 MiB static scratch holds (about 762,000 in "
                                        "float64, 838,000 in float32)");
-  // the split of the context path (about six rounds of the resident workgroups, at most 96
-  // chunks and one per 256 targets), lowered until the partial sums fit
-  const int nbx = (n_points + 255) / 256;
-  int split = std::max(1, std::min((6 * 2048 + nbx - 1) / nbx, std::min(96, nbx)));
+  // the split of the context path, lowered until the partial sums fit
+  int split = far_split(n_points);
   while (split > 1 && scratch_bytes(N, split, precision) > kScratchBytes) --split;
   unsigned char* base = nullptr;
   rbm_status s = scratch_address(&base);

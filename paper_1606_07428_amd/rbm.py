@@ -39,7 +39,8 @@ class Options(ctypes.Structure):
                 ("stream", ctypes.c_void_p), ("p_up", ctypes.c_int), ("near_factor", ctypes.c_double),
                 ("contact_delta", ctypes.c_double), ("magnetic", ctypes.c_int),
                 ("fmm_order", ctypes.c_int), ("fmm_max_level", ctypes.c_int),
-                ("gmres_lookahead", ctypes.c_int), ("ir_stall", ctypes.c_double)]
+                ("gmres_lookahead", ctypes.c_int), ("ir_stall", ctypes.c_double),
+                ("velocity_fusion", ctypes.c_int)]
 
 
 class SolveInfo(ctypes.Structure):
@@ -53,7 +54,8 @@ class SolveInfo(ctypes.Structure):
                 ("init_rel_residual", ctypes.c_double), ("near_pairs", ctypes.c_int),
                 ("ms_near", ctypes.c_double), ("fmm_level", ctypes.c_int),
                 ("fmm_applies", ctypes.c_int), ("n_traction32", ctypes.c_int),
-                ("ms_traction32", ctypes.c_double), ("fp64_cycles", ctypes.c_int)]
+                ("ms_traction32", ctypes.c_double), ("fp64_cycles", ctypes.c_int),
+                ("n_fused", ctypes.c_int), ("fused_used", ctypes.c_int), ("ms_fused", ctypes.c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -160,7 +162,7 @@ class Solver:
                  max_iter=100, max_restart=4, precision=FP64, guess=GUESS_BLOCKDIAG,
                  inner_tol=1e-4, n_max=None, stream=None, device="cuda", p_up=0, near_factor=5.0,
                  contact_delta=0.0, magnetic=0, fmm_order=0, fmm_max_level=5,
-                 gmres_lookahead=1, ir_stall=0.5):
+                 gmres_lookahead=1, ir_stall=0.5, velocity_fusion=1):
         import torch
         lib = load()
         self.torch = torch
@@ -175,6 +177,7 @@ class Solver:
         opt.fmm_order, opt.fmm_max_level = fmm_order, fmm_max_level
         opt.gmres_lookahead = gmres_lookahead
         opt.ir_stall = ir_stall
+        opt.velocity_fusion = velocity_fusion
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
         opt.stream = ctypes.c_void_p(self.stream.cuda_stream)
         self.opt = opt

@@ -40,7 +40,7 @@ def test_default_options():
     o = _opts()
     assert (o.p, o.eta, o.tol, o.max_iter, o.precision, o.guess) == (8, 1.0, 1e-12, 100, 0, 1)
     assert (o.p_up, o.near_factor, o.contact_delta, o.magnetic, o.fmm_order, o.fmm_max_level,
-            o.gmres_lookahead, o.ir_stall) == (0, 5.0, 0.0, 0, 0, 5, 1, 0.5)
+            o.gmres_lookahead, o.ir_stall, o.velocity_fusion) == (0, 5.0, 0.0, 0, 0, 5, 1, 0.5, 1)
 
 
 def test_fmm_level_bound_checked_only_with_an_order():
@@ -58,7 +58,7 @@ def test_fmm_level_bound_checked_only_with_an_order():
                                          ("guess", 9), ("p_sing", 3), ("p_up", 3),
                                          ("near_factor", -1.0), ("contact_delta", -0.5),
                                          ("fmm_order", 1), ("fmm_order", 17), ("ir_stall", 1.0),
-                                         ("ir_stall", -0.1),
+                                         ("ir_stall", -0.1), ("velocity_fusion", 2),
                                          ("gmres_lookahead", -1), ("gmres_lookahead", 3)])
 def test_create_rejects_bad_options(field, value):
     lib = rbm.load()

@@ -40,7 +40,17 @@ int main() {
   const int big[] = {19968, 59904, 73728, 160000, 544000, 1248000, 4000000};
   for (int N : big)
     for (int ns = 1; ns <= 96; ++ns) check(N, ns);
-  std::printf("%ld %ld %ld\n", cases, bad, ordered_bad);
+  // the slot buffer bound covers the split of every size up to N, and the chosen split's
+  // chunks stay within the L2 share once the split is not capped at 96
+  long cap_bad = 0, l2_bad = 0;
+  for (long N = 1; N <= 4000000; N += (N < 100000 ? 1 : 997)) {
+    const int ns = rbm::far_split((int)N);
+    if ((size_t)ns * N > rbm::far_part_cap(N)) ++cap_bad;
+    if (rbm::far_part_cap(N) < rbm::far_part_cap(N - 1 > 0 ? N - 1 : 1)) ++cap_bad;
+    const rbm::FarChunks fc = rbm::far_chunks((int)N, ns);
+    if (ns < 96 && ns < (N + 255) / 256 && fc.c1 > rbm::kChunkSources) ++l2_bad;
+  }
+  std::printf("%ld %ld %ld %ld %ld\n", cases, bad, ordered_bad, cap_bad, l2_bad);
   return 0;
 }
 """
@@ -54,9 +64,10 @@ def test_far_chunks_cover_every_source_once(tmp_path):
     src.write_text(CHECK)
     exe = tmp_path / "check"
     subprocess.run([gxx, "-O2", "-std=c++17", "-I", CSRC, str(src), "-o", str(exe)], check=True)
-    cases, bad, ordered_bad = map(int, subprocess.run([str(exe)], check=True, capture_output=True,
-                                                      text=True).stdout.split())
+    cases, bad, ordered_bad, cap_bad, l2_bad = map(int, subprocess.run(
+        [str(exe)], check=True, capture_output=True, text=True).stdout.split())
     assert cases > 280000
     assert bad == 0
     # at the slot counts the library uses, the first half of the slots take the long chunks
     assert ordered_bad == 0
+    assert cap_bad == 0 and l2_bad == 0

@@ -61,7 +61,8 @@ def _gpu_solve(name):
     info = s.solve_dev(FT, VW)
     torch.cuda.synchronize()
     print(f"[case] {name}: block-diagonal {i_bd['iters']} it ({i_bd['ms_total']:.0f} ms), learned "
-          f"{info['iters']} it ({info['ms_total']:.0f} ms), near pairs {info['near_pairs']}, init residual "
+          f"{info['iters']} it ({info['ms_total']:.0f} ms, fused pass used {info['fused_used']}), near pairs "
+          f"{info['near_pairs']}, init residual "
           f"{i_bd['init_rel_residual']:.3f} -> {info['init_rel_residual']:.3f}, fallback {info['fallback_used']}, "
           f"rel residual {info['rel_residual']:.2e}", flush=True)
     mu, rho = s.density()

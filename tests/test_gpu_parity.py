@@ -135,6 +135,8 @@ def test_two_spheres_match_oracle_dense_solve():
     prob = oracle_problem(w)
     rho, mu, VW_o = __import__("oracle.system", fromlist=["x"]).solve_dense(prob, w["FT"])
     assert info["rel_residual"] < 1e-13
+    # the converging residual was predicted, so its pass also gave the velocities' Stokeslet sum
+    assert info["fused_used"] == 1 and info["n_fused"] == 1 and info["n_stokeslet"] == 0
     assert rel_err(VW, VW_o) < 1e-11
     mu_g, rho_g = s.density()
     assert rel_err(rho_g.T, rho) < 1e-13
@@ -159,6 +161,29 @@ def test_random_bodies_match_oracle(n, p, seed, guess):
     mu_g, _ = s.density()
     assert rel_err(mu_g.T, mu_o) < 1e-9
     s.close()
+
+
+@pytest.mark.parametrize("prec", [rbm.FP64, rbm.MIXED_FP32])
+def test_velocities_with_and_without_the_fused_pass_match(prec):
+    """The same solve with the fused traction + Stokeslet pass for the converging residual and
+    with a separate Stokeslet sum (velocity_fusion = 0): the same iterations, the same density
+    and the same velocities to rounding, both matching the oracle."""
+    _case(f"fused vs separate velocity sums, tiny n=5 p=6, precision={prec}")
+    from oracle import system as sy
+    w = inputs.tiny(5, 6, seed=8)
+    s1 = rbm.solver_for(w, tol=1e-11, precision=prec)
+    VW1, i1 = s1.solve(w["FT"])
+    s2 = rbm.solver_for(w, tol=1e-11, precision=prec, velocity_fusion=0)
+    VW2, i2 = s2.solve(w["FT"])
+    print(f"[case] fused {i1['n_fused']} (used {i1['fused_used']}), separate {i2['n_stokeslet']}", flush=True)
+    assert i1["fused_used"] == 1 and i1["n_stokeslet"] == 0
+    assert i2["n_fused"] == 0 and i2["fused_used"] == 0 and i2["n_stokeslet"] == 1
+    assert i1["iters"] == i2["iters"]
+    assert rel_err(VW1, VW2) < 1e-12
+    _, _, VW_o = sy.solve_dense(oracle_problem(w), w["FT"])
+    assert rel_err(VW1, VW_o) < 1e-9
+    s1.close()
+    s2.close()
 
 
 @pytest.mark.parametrize("prec", [rbm.MIXED_FP32, rbm.MIXED_BF16])
