@@ -11,7 +11,7 @@ Default mode (one JSON line), on the 4000-body suspension at 20 % volume fractio
 surfaces 0.1 apart (p = 12, 1.25 M points, near-singular upsampling of order 24 for near
 body pairs):
   1. a precision-form context (float32 inner far sums by the fast multipole method of
-     order 10, float32 block preconditioner, float64 refinement residuals) runs a short RK4
+     order 12, float32 block preconditioner, float64 refinement residuals) runs a short RK4
      trajectory from the configuration, capturing every stage solve, and trains its warm
      start network on them;
   2. at the configuration the trajectory reached (not in the training data) it times K
@@ -47,9 +47,9 @@ TRACTION_FLOPS_PER_PAIR = 30
 # Per workload: near-singular upsampling order (0 = plain smooth rule), fast multipole order
 # of the inner far sums (0 = direct float32 sums) and RK4 steps of the training trajectory.
 WORKLOAD_DEFAULTS = {
-    "dense4000": (24, 10, 2),
+    "dense4000": (24, 12, 2),
     "dense512": (24, 0, 4),
-    "ellipsoids1000": (0, 10, 2),
+    "ellipsoids1000": (0, 12, 2),
     "sediment512": (0, 0, 4),
     "random64": (0, 0, 8),
 }

@@ -68,7 +68,8 @@ typedef enum {
 
 typedef enum {
   RBM_FP64 = 0,        /* everything in float64 */
-  RBM_MIXED_FP32 = 1,  /* GMRES-IR: fp32 far sum + fp32 preconditioner, fp64 residuals */
+  RBM_MIXED_FP32 = 1,  /* GMRES-IR: fp32 far sum + fp32 preconditioner, fp64 residuals after the
+                          first refinement (which starts from the fp32 / FMM residual) */
   RBM_MIXED_BF16 = 2   /* GMRES-IR: fp32 far sum + bf16 preconditioner (fp32 accumulate) */
 } rbm_precision;
 
@@ -143,7 +144,8 @@ typedef struct {
   double pairs_per_launch; /* off-body pairs of one launch: N^2 - n M^2 */
   int guess_used;     /* rbm_guess actually used for mu_0 */
   int fallback_used;  /* 1 if the learned guess was rejected for the block-diagonal one */
-  double init_rel_residual; /* ||b - A mu_0|| / ||b|| */
+  double init_rel_residual; /* ||b - A mu_0|| / ||b|| (precision form: with the far sum of its inner
+                               operators, the residual its first refinement starts from) */
   int near_pairs;     /* ordered near body pairs of the upsampled rule (0 when off) */
   double ms_near;     /* device time of the near-singular corrections (interpolation, sums) */
   int fmm_level;      /* leaf level of the fast multipole tree of this solve (-1: not used) */

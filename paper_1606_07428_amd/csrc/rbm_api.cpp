@@ -10,6 +10,7 @@
 #include <type_traits>
 #include <cstdint>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -147,6 +148,7 @@ struct rbm_ctx {
     std::vector<uint16_t*> Hb, dZb;
   } L;
   double bd_ratio = -1.0;
+  bool verbose = false;  // RBM_VERBOSE set: one stderr line per refinement and GMRES cycle
   // events for timing
   std::vector<hipEvent_t> ev;
   int ev_used = 0;
@@ -218,6 +220,7 @@ extern "C" rbm_status rbm_create(const rbm_options* opt, rbm_ctx** out) {
   c->pu = opt->p_up;
   c->Mu = c->pu ? (c->pu + 1) * 2 * c->pu : 0;
   c->kappa = opt->near_factor > 0.0 ? opt->near_factor : 5.0;
+  c->verbose = std::getenv("RBM_VERBOSE") != nullptr;
   *out = c;
   return RBM_OK;
 }
@@ -992,9 +995,11 @@ static rbm_status build_rhs(rbm_ctx* c, SolveState& S, const double* dFT, const 
 // one exact far sum of rho + x (tmp holds rho + x).
 // With `velocity`, the traction and Stokeslet sums of rho + x come from one fused pass: the
 // Stokeslet partial sums stay in part_u (vel_ready) for the velocities, should this residual
-// end the solve.
+// end the solve.  With `inner`, the far sum is the inner operators' (float32 direct or fast
+// multipole) instead of the float64 one: the starting residual of the precision form's first
+// refinement, which decides nothing.
 static rbm_status residual_exact(rbm_ctx* c, SolveState& S, const double* x, double* r, double* tmp,
-                                 bool velocity = false) {
+                                 bool velocity = false, bool inner = false) {
   const int n = c->n, M = c->M, N = n * M;
   hipStream_t st = c->st;
   rbm_status s;
@@ -1014,7 +1019,7 @@ static rbm_status residual_exact(rbm_ctx* c, SolveState& S, const double* x, dou
     if ((s = near_correction(c, S, 0, tmp, 0, 0)) != RBM_OK) return s;
     if ((s = near_correction(c, S, 1, tmp, 0, 0, c->part_u)) != RBM_OK) return s;
     c->vel_ready = true;
-  } else if ((s = far_traction(c, S, tmp, 0, 0)) != RBM_OK) {
+  } else if ((s = far_traction(c, S, tmp, 0, inner ? 1 : 0)) != RBM_OK) {
     return s;
   }
   HIPCHECK(launch_combine(N, M, c->far_nslots, c->part, -1.0, nullptr, 0.0, c->yb, c->Rm, -1.0, r, st));
@@ -1091,30 +1096,38 @@ static rbm_status solve_impl(rbm_ctx* c, const double* dFT, double* dVW, rbm_sol
   // tolerance, both sums come from one fused pass (a wrong prediction costs the Stokeslet
   // part of that pass, about 0.4 of a traction sum).  Prediction: with float64 operators the
   // GMRES estimate; in the precision form the estimate plus eps_op times the residual the
-  // cycle started from, eps_op the relative accuracy of the inner operators: at first 1e-4
+  // cycle started from (plus ||b|| when that residual was the inner operators' own), eps_op
+  // the relative accuracy of the inner operators: at first 1e-4
   // with fast multipole sums, 2^-22 with float32 direct sums and 2^-8 with bf16 blocks, then
   // what the last refinement showed (its exact residual beyond its estimate).
   bool fuse_next = false;
   double eps_op = c->fmm_ready ? 1e-4 : prec == RBM_MIXED_BF16 ? std::ldexp(1.0, -8) : std::ldexp(1.0, -22);
   double est_prev = -1.0, rn_cycle = -1.0;
   int prec_cycle = prec;
+  bool cycle_from_inner = false, last_exact = true;
   c->vel_ready = false;
   for (int outer = 0; outer <= max_outer; ++outer) {
-    // float64 residual r = b - A mu
+    // residual r = b - A mu: float64, except that the precision form starts its first
+    // refinement from the residual of its inner operators (every residual that decides
+    // convergence is float64; the first comes after the first refinement, which the inner
+    // operators' accuracy bounds alike from either starting residual)
     double rn;
+    bool exact = true;
     if (mu_zero) {
       HIPCHECK(hipMemcpyAsync(c->r, c->b, len * sizeof(double), hipMemcpyDeviceToDevice, st));
       rn = bnorm;
       mu_zero = false;
     } else {
-      if ((s = residual_exact(c, S, c->mu, c->r, c->t1, fuse_next)) != RBM_OK) return s;
+      exact = !(outer == 0 && prec != 0);
+      if ((s = residual_exact(c, S, c->mu, c->r, c->t1, exact && fuse_next, !exact)) != RBM_OK) return s;
       if ((s = read_norm(c, c->r, &rn)) != RBM_OK) return s;
     }
     if (outer == 0 && bnorm > 0.0) {
       if (learned_active) {
-        // fallback test against the block-diagonal guess's residual ratio
+        // fallback test against the block-diagonal guess's residual ratio (residuals of the
+        // same kind as this one)
         if (c->bd_ratio < 0.0) {
-          if ((s = residual_exact(c, S, c->t2, c->t1, c->V)) != RBM_OK) return s;  // V is free before GMRES
+          if ((s = residual_exact(c, S, c->t2, c->t1, c->V, false, !exact)) != RBM_OK) return s;  // V is free before GMRES
           double rbd;
           if ((s = read_norm(c, c->t1, &rbd)) != RBM_OK) return s;
           c->bd_ratio = rbd / bnorm;
@@ -1122,7 +1135,7 @@ static rbm_status solve_impl(rbm_ctx* c, const double* dFT, double* dVW, rbm_sol
         if (!(rn <= c->bd_ratio * bnorm)) {
           fallback = 1;
           HIPCHECK(hipMemcpyAsync(c->mu, c->t2, len * sizeof(double), hipMemcpyDeviceToDevice, st));
-          if ((s = residual_exact(c, S, c->mu, c->r, c->t1)) != RBM_OK) return s;
+          if ((s = residual_exact(c, S, c->mu, c->r, c->t1, false, !exact)) != RBM_OK) return s;
           if ((s = read_norm(c, c->r, &rn)) != RBM_OK) return s;
           c->bd_ratio = rn / bnorm;
         }
@@ -1131,11 +1144,28 @@ static rbm_status solve_impl(rbm_ctx* c, const double* dFT, double* dVW, rbm_sol
       }
       init_rel = rn / bnorm;
     }
-    rel = bnorm > 0.0 ? rn / bnorm : 0.0;
-    if (rn <= abs_tol || bnorm == 0.0) { converged = true; break; }
+    last_exact = exact;
+    if (c->verbose)
+      std::fprintf(stderr, "[rbm] refinement %d: %s residual %.3e (relative), inner precision %d, fused %d\n",
+                   outer, exact ? "float64" : "inner", bnorm > 0.0 ? rn / bnorm : 0.0, prec_in,
+                   exact && fuse_next ? 1 : 0);
+    if (!exact) {
+      // an inner-operator residual already at the tolerance: go to the float64 one
+      if (rn <= abs_tol) {
+        fuse_next = c->opt.velocity_fusion != 0;
+        continue;
+      }
+    } else {
+      rel = bnorm > 0.0 ? rn / bnorm : 0.0;
+      if (rn <= abs_tol || bnorm == 0.0) { converged = true; break; }
+    }
     if (outer == max_outer) break;
     if (prec_in != 0 && rn_prev > 0.0 && !(rn < c->opt.ir_stall * rn_prev)) prec_in = 0;
-    if (est_prev >= 0.0 && prec_cycle != 0) eps_op = std::max(1e-16, (rn - est_prev) / rn_cycle);
+    // the inner operators' relative accuracy as the last refinement showed it: its float64
+    // residual beyond its estimate, over the residual it started from (plus ||b|| when that
+    // was the inner operators' own residual, whose error does not recur)
+    if (est_prev >= 0.0 && prec_cycle != 0)
+      eps_op = std::max(1e-16, (rn - est_prev) / (rn_cycle + (cycle_from_inner ? bnorm : 0.0)));
     rn_prev = rn;
     double inner_abs = prec_in == 0 ? abs_tol : std::max(c->opt.inner_tol * rn, 0.5 * abs_tol);
     // Float32 inner operators (direct far sum, float32 self blocks) are accurate to about
@@ -1152,10 +1182,15 @@ static rbm_status solve_impl(rbm_ctx* c, const double* dFT, double* dVW, rbm_sol
     cycles++;
     if (prec != 0) refinements++;
     if (prec != 0 && prec_in == 0) fp64_cycles++;
-    fuse_next = c->opt.velocity_fusion && (prec_in == 0 ? est <= abs_tol : est + eps_op * rn <= abs_tol);
+    fuse_next = c->opt.velocity_fusion &&
+                (prec_in == 0 ? est <= abs_tol : est + eps_op * (rn + (last_exact ? 0.0 : bnorm)) <= abs_tol);
+    if (c->verbose)
+      std::fprintf(stderr, "[rbm]   cycle: %d iterations, estimate %.3e (relative), eps_op %.2e, next fused %d\n", it,
+                   bnorm > 0.0 ? est / bnorm : 0.0, eps_op, fuse_next ? 1 : 0);
     est_prev = est;
     rn_cycle = rn;
     prec_cycle = prec_in;
+    cycle_from_inner = !last_exact;
   }
   // velocities u = S[rho + mu]: far Stokeslet sum (from the fused pass of the last residual
   // when it was evaluated for this mu) + self functional, float64

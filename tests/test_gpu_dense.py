@@ -1,7 +1,7 @@
 """Full-size solves in the configuration the benchmark times, checked against the oracle:
 the 4000-body suspension at 20 % with a true surface gap of 0.1 (p = 12, 1.25 M points) and
 the 1000-ellipsoid suspension (p = 16, 544 k points).  The GPU solves in the precision form
-(float32 far sums with fast multipole inner iterations of order 10, float32 block
+(float32 far sums with fast multipole inner iterations of order 12, float32 block
 preconditioner, float64 refinement residuals) with the learned warm start, to a relative
 residual of 1e-8, with near-singular upsampling where bodies are closer than a node
 spacing.  On sampled bodies the oracle then applies its own float64 operator to the
@@ -48,7 +48,7 @@ P_UP = {"dense4000": 24, "ellipsoids1000": 0}
 def _gpu_solve(name):
     w = inputs.workload(name)
     _case(f"{name}: setup, block-diagonal mixed solve (captured), training, learned mixed solve")
-    s = rbm.solver_for(w, tol=1e-8, precision=rbm.MIXED_FP32, guess=rbm.GUESS_BLOCKDIAG, fmm_order=10,
+    s = rbm.solver_for(w, tol=1e-8, precision=rbm.MIXED_FP32, guess=rbm.GUESS_BLOCKDIAG, fmm_order=12,
                        p_up=P_UP[name])
     s.learned_bind(k_nbr=8, hidden=256, n_hidden=3, capacity=s.n, batch_max=1024, seed=7)
     FT = torch.as_tensor(np.asarray(w["FT"], dtype=np.float64), device="cuda")

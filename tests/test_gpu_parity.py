@@ -196,6 +196,9 @@ def test_mixed_precision_reaches_fp64_answer(prec):
     _, _, VW_o = sy.solve_dense(oracle_problem(w), w["FT"])
     assert info["rel_residual"] < 1e-11
     assert info["refinements"] >= 1
+    # one float64 residual per refinement: the first refinement starts from the inner
+    # operators' residual
+    assert info["n_traction"] + info["n_fused"] == info["refinements"]
     assert rel_err(VW, VW_o) < 1e-9
     s.close()
 
