@@ -408,7 +408,8 @@ def main_compare(args):
         _log(f"training workload {args.learned_from} generated")
         FTs = torch.as_tensor(np.asarray(ws["FT"], dtype=np.float64), device=dev)
         st, _, learned = _train_on_trajectory(rbm, torch, ws, FTs, args.tol, args.train_steps or 25,
-                                              args.epochs, 1e-3, rbm.MIXED_FP32, args.p_up or 0, args.near_factor)
+                                              args.epochs, 1e-3, rbm.MIXED_FP32, args.p_up or 0, args.near_factor,
+                                              fmm_order=args.fmm or 0)
         params = st.learned_params()
         out["learned_transfer"] = dict(learned, trained_on=args.learned_from)
         st.close()
@@ -422,18 +423,21 @@ def main_compare(args):
     if params is not None:
         forms.append(("mixed_fp32_learned", rbm.MIXED_FP32, True, pu, 0, bd))
     if args.fmm:
-        # with cheap inner iterations the zero initial guess saves the first float64 residual
         forms += [("mixed_fp32_fmm", rbm.MIXED_FP32, False, pu, args.fmm, bd),
                   ("mixed_fp32_fmm_zero", rbm.MIXED_FP32, False, pu, args.fmm, zero),
                   ("mixed_bf16_fmm", rbm.MIXED_BF16, False, pu, args.fmm, bd)]
+        if params is not None:
+            forms.append(("mixed_fp32_fmm_learned", rbm.MIXED_FP32, True, pu, args.fmm, bd))
         out["fmm_order"] = args.fmm
-    if args.forms:
-        keep = set(args.forms.split(","))
+    keep = set(args.forms.split(",")) if args.forms else None
+    if keep is not None:
         forms = [f for f in forms if f[0] in keep]
     if pu:
-        # the plain smooth rule first: the upsampled float64 solve is then the reference
-        forms.insert(0, ("fp64_plain", rbm.FP64, False, 0, 0, bd))
         out["p_up"], out["near_factor"] = pu, args.near_factor
+        if keep is None or "fp64_plain" in keep:
+            # the plain smooth rule first: the upsampled float64 solve is then the reference
+            # (at surface gaps far below the node spacing it may not converge)
+            forms.insert(0, ("fp64_plain", rbm.FP64, False, 0, 0, bd))
     ref = None
     plain = None
     for name, prec, use_net, form_pu, fmm_order, guess in forms:
@@ -453,6 +457,7 @@ def main_compare(args):
             plain = v
         elif ref is None:
             ref = v
+            out["reference_form"] = name
         i = infos[-1]
         out["forms"][name] = {
             "setup_s": setup, "solve_ms": dt / args.steps * 1e3, "iters": i["iters"],
@@ -462,7 +467,7 @@ def main_compare(args):
             "n_traction64": i["n_traction"], "n_traction32": i["n_traction32"],
             "stokeslet_ms": i["ms_stokeslet"], "self_ms": i["ms_self"],
             "pairs_per_launch": i["pairs_per_launch"],
-            "velocity_rel_err_vs_fp64": float(np.abs(v - ref).max() / np.abs(ref).max()) if ref is not None else 0.0,
+            "velocity_rel_err_vs_reference": float(np.abs(v - ref).max() / np.abs(ref).max()) if ref is not None else 0.0,
             "init_rel_residual": i["init_rel_residual"], "fallback": i["fallback_used"],
             "near_pairs": i["near_pairs"], "near_ms": i["ms_near"],
             "fmm_level": i["fmm_level"], "fmm_applies": i["fmm_applies"],
@@ -629,7 +634,9 @@ def main():
     ap.add_argument("--compare", action="store_true",
                     help="time fp64 / mixed fp32 / mixed bf16 solves of one workload")
     ap.add_argument("--forms", default=None,
-                    help="with --compare: comma list among fp64,mixed_fp32,mixed_bf16,mixed_fp32_learned")
+                    help="with --compare: comma list among fp64_plain,fp64,mixed_fp32,mixed_bf16,"
+                         "mixed_fp32_learned,mixed_fp32_fmm,mixed_fp32_fmm_zero,mixed_bf16_fmm,"
+                         "mixed_fp32_fmm_learned (velocity differences against the first)")
     ap.add_argument("--learned-from", default=None,
                     help="with --compare: train the warm start on this workload's trajectory and "
                          "add a mixed fp32 + learned solve (same p and feature layout)")
