@@ -1169,10 +1169,13 @@ static rbm_status solve_impl(rbm_ctx* c, const double* dFT, double* dVW, rbm_sol
     rn_prev = rn;
     double inner_abs = prec_in == 0 ? abs_tol : std::max(c->opt.inner_tol * rn, 0.5 * abs_tol);
     // Float32 inner operators (direct far sum, float32 self blocks) are accurate to about
-    // 2^-22: when that accuracy times this residual already meets the tolerance, solve the
-    // correction to the tolerance itself and finish in this refinement (the exact residual
-    // still decides; a miss costs one more refinement, never accuracy).
-    if (prec_in == RBM_MIXED_FP32 && !c->fmm_ready && std::ldexp(rn, -22) <= 0.5 * abs_tol)
+    // 2^-22: when that accuracy times the error this refinement can leave (the residual it
+    // starts from, plus ||b|| when that residual is the inner operators' own, whose right-
+    // hand side carries their error too) already meets the tolerance, solve the correction
+    // to the tolerance itself and finish in this refinement (the exact residual still
+    // decides; a miss costs one more refinement, never accuracy).
+    if (prec_in == RBM_MIXED_FP32 && !c->fmm_ready &&
+        std::ldexp(rn + (last_exact ? 0.0 : bnorm), -22) <= 0.5 * abs_tol)
       inner_abs = 0.5 * abs_tol;
     int it = 0;
     double est = rn;
@@ -2376,7 +2379,7 @@ size_t state_bytes(const rbm_ctx* c, const StateHeader& h) {
   size_t b = sizeof(StateHeader) + (size_t)h.n * (sizeof(int32_t) + 7 * sizeof(double));
   if (h.have_solution) b += 6 * N * sizeof(double);
   if (h.learned)
-    b += (3 * h.nparam + 2 * (size_t)h.F + 2 + (size_t)h.count * (h.F + h.O)) * sizeof(float);
+    b += (3 * h.nparam + 2 * (size_t)h.F + 2 + (size_t)h.count * ((size_t)h.F + (size_t)h.O)) * sizeof(float);
   (void)c;
   return b;
 }
@@ -2461,11 +2464,14 @@ extern "C" rbm_status rbm_set_state(rbm_ctx* c, const void* buf, size_t bytes) {
   StateHeader h;
   std::memcpy(&h, buf, sizeof(h));
   if (std::memcmp(h.magic, kStateMagic, 8) != 0) return fail(RBM_E_INVAL, "not a state record");
-  if (h.bytes != bytes || state_bytes(c, h) != bytes) return fail(RBM_E_INVAL, "state record size mismatch");
+  // every field the record's size depends on is checked before the size is computed
   if (h.p != c->p || h.M != c->M || h.ns != c->ns || h.shape_hash != shape_hash(c))
     return fail(RBM_E_INVAL, "state record belongs to other shapes or another order p");
-  if (h.n < 1 || h.n > c->nmax) return fail(RBM_E_NOMEM, "more bodies than the workspace holds");
+  if (h.n < 1) return fail(RBM_E_INVAL, "bad body count in the state record");
+  if (h.n > c->nmax) return fail(RBM_E_NOMEM, "more bodies than the workspace holds");
   if (h.guess < 0 || h.guess > 3) return fail(RBM_E_INVAL, "bad guess mode in the state record");
+  if ((h.have_solution != 0 && h.have_solution != 1) || (h.learned != 0 && h.learned != 1))
+    return fail(RBM_E_INVAL, "bad flags in the state record");
   auto& L = c->L;
   if (h.learned) {
     if (!L.bound) return fail(RBM_E_STATE, "the record has a learned warm start: bind the learned workspace first");
@@ -2474,6 +2480,7 @@ extern "C" rbm_status rbm_set_state(rbm_ctx* c, const void* buf, size_t bytes) {
     if (h.count < 0 || h.count > h.capacity || h.head < 0 || h.head > h.capacity)
       return fail(RBM_E_INVAL, "bad sample counts in the state record");
   }
+  if (h.bytes != bytes || state_bytes(c, h) != bytes) return fail(RBM_E_INVAL, "state record size mismatch");
   const char* in = static_cast<const char*>(buf) + sizeof(h);
   const int n = h.n;
   const size_t N = (size_t)n * c->M;
