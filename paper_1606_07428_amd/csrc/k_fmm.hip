@@ -83,13 +83,18 @@ __device__ void regular_table(int P, S x, S y, S z, Cx<T>* out, bool conj) {
   }
 }
 
-// I_n^m(x, y, z) for 0 <= m <= n <= Q into out[tri(n, m)]:
+// I_n^m(x, y, z) for 0 <= m <= n <= Q into out[n^2 + n + m] and, by I_n^{-m} =
+// (-1)^m conj(I_n^m), out[n^2 + n - m] (all m, (Q + 1)^2 entries):
 //   I_0^0 = 1/r,  I_m^m = I_{m-1}^{m-1} (2m - 1)(x + iy) / r^2,  I_{m+1}^m = (2m + 1) z I_m^m / r^2,
 //   I_n^m = ((2n - 1) z I_{n-1}^m - (n + m - 1)(n - m - 1) I_{n-2}^m) / r^2.
 template <typename T>
 __device__ void irregular_table(int Q, double x, double y, double z, Cx<T>* out) {
   const double r2 = x * x + y * y + z * z, ir2 = 1.0 / r2;
   double dre = 1.0 / sqrt(r2), dim = 0.0;
+  auto put = [&](int n, int m, double re, double im) {
+    out[n * n + n + m] = Cx<T>{(T)re, (T)im};
+    if (m > 0) out[n * n + n - m] = (m & 1) ? Cx<T>{(T)-re, (T)im} : Cx<T>{(T)re, (T)-im};
+  };
   for (int m = 0; m <= Q; ++m) {
     if (m > 0) {
       const double c = (2 * m - 1) * ir2;
@@ -97,17 +102,17 @@ __device__ void irregular_table(int Q, double x, double y, double z, Cx<T>* out)
       dre = nre;
       dim = nim;
     }
-    out[tri(m, m)] = Cx<T>{(T)dre, (T)dim};
+    put(m, m, dre, dim);
     if (m + 1 > Q) continue;
     double are = dre, aim = dim;
     double bre = (2 * m + 1) * z * ir2 * dre, bim = (2 * m + 1) * z * ir2 * dim;
-    out[tri(m + 1, m)] = Cx<T>{(T)bre, (T)bim};
+    put(m + 1, m, bre, bim);
     for (int n = m + 2; n <= Q; ++n) {
       const double c1 = (2.0 * n - 1.0) * z, c2 = (double)(n + m - 1) * (double)(n - m - 1);
       const double vre = (c1 * bre - c2 * are) * ir2, vim = (c1 * bim - c2 * aim) * ir2;
       are = bre; aim = bim;
       bre = vre; bim = vim;
-      out[tri(n, m)] = Cx<T>{(T)vre, (T)vim};
+      put(n, m, vre, vim);
     }
   }
 }
@@ -241,13 +246,14 @@ __global__ void k_fmm_level_count(int np, const int* __restrict__ cc, int* __res
 // Translation tables of levels 2..L (child width w = D / 2^lev):
 //   tabR[lev][o] = conj(R(t_o)), t_o = ((o_x - 1/2) w, (o_y - 1/2) w, (o_z - 1/2) w) (child
 //   centre minus parent centre, used by M2M into level lev - 1 and by L2L into level lev);
-//   tabI[lev][v] = I(v w) for v in [-3, 3]^3 with max |v_i| >= 2 (M2L), degree 2P.
+//   tabI[lev][v] = I(v w) for v in [-3, 3]^3 with max |v_i| >= 2 (M2L), degree 2P, all m
+//   ((2P + 1)^2 entries, n^2 + n + m).
 template <typename T>
 __global__ void k_fmm_tables(int P, int L, double D, Cx<T>* __restrict__ tabR, Cx<T>* __restrict__ tabI) {
   const int lev = 2 + blockIdx.y;
   const int e = blockIdx.x * blockDim.x + threadIdx.x;
   if (lev > L || e >= 8 + kFmmVecs) return;
-  const int Kc = tri(P + 1, 0), Kc2 = tri(2 * P + 1, 0);
+  const int Kc = tri(P + 1, 0), F2 = (2 * P + 1) * (2 * P + 1);
   const double w = ldexp(D, -lev);
   if (e < 8) {
     const double tx = ((e & 1) - 0.5) * w, ty = (((e >> 1) & 1) - 0.5) * w, tz = ((e >> 2) - 0.5) * w;
@@ -256,12 +262,21 @@ __global__ void k_fmm_tables(int P, int L, double D, Cx<T>* __restrict__ tabR, C
     const int v = e - 8;
     const int vx = v % 7 - 3, vy = (v / 7) % 7 - 3, vz = v / 49 - 3;
     if (abs(vx) <= 1 && abs(vy) <= 1 && abs(vz) <= 1) return;
-    irregular_table<T>(2 * P, vx * w, vy * w, vz * w, tabI + ((size_t)(lev - 2) * kFmmVecs + v) * Kc2);
+    irregular_table<T>(2 * P, vx * w, vy * w, vz * w, tabI + ((size_t)(lev - 2) * kFmmVecs + v) * F2);
   }
 }
 
 // ---------------------------------------------------------------------------------
-// Expansions: [box][density 0..3][Kc] complex, density 3 = psi.
+// Expansions: [box][Kc][density 0..3] complex (the four densities of one coefficient are
+// adjacent, so a wave-uniform reader takes them in one scalar load), density 3 = psi.
+
+// Entry (n, m), any sign of m, of density d of an interleaved expansion.
+template <typename T>
+__device__ __forceinline__ Cx<T> cget4(const Cx<T>* a, int n, int m, int d) {
+  if (m >= 0) return a[tri(n, m) * 4 + d];
+  const Cx<T> v = a[tri(n, -m) * 4 + d];
+  return (m & 1) ? Cx<T>{-v.re, v.im} : Cx<T>{v.re, -v.im};
+}
 
 __device__ __forceinline__ void tri_inv(int c, int& n, int& m) {
   n = (int)((sqrtf(8.0f * c + 1.0f) - 1.0f) * 0.5f);
@@ -274,7 +289,7 @@ constexpr int kP2mChunk = 16;
 
 // Leaf multipoles: M_d[c] = sum_p charge_d(p) conj(R_c(y_p - centre)), charges
 // (q_x, q_y, q_z, (y - centre).q), sources in leaf order.  One workgroup per leaf, 4 Kc
-// threads (one output each).
+// threads (one output each, density fastest).
 template <typename T>
 __global__ void __launch_bounds__(1024) k_fmm_p2m(int P, int nb, double lox, double loy, double loz, double w,
                                                   const int* __restrict__ start, const int* __restrict__ perm,
@@ -288,7 +303,8 @@ __global__ void __launch_bounds__(1024) k_fmm_p2m(int P, int nb, double lox, dou
   const double cx = lox + (i + 0.5) * w, cy = loy + (j + 0.5) * w, cz = loz + (k + 0.5) * w;
   const int s0 = start[b], n = start[b + 1] - s0;
   const int o = threadIdx.x;
-  const int d = o / Kc, c = o % Kc;
+  const int d = o & 3, c = min(o >> 2, Kc - 1);
+  const bool live = o < 4 * Kc;
   Cx<T> acc{0, 0};
   for (int base = 0; base < n; base += kP2mChunk) {
     const int cnt = min(kP2mChunk, n - base);
@@ -304,14 +320,14 @@ __global__ void __launch_bounds__(1024) k_fmm_p2m(int P, int nb, double lox, dou
       regular_table<T, T>(P, sx, sy, sz, Rt[o], true);
     }
     __syncthreads();
-    if (d < 4)
+    if (live)
       for (int q = 0; q < cnt; ++q) {
         acc.re = fma(ch[q][d], Rt[q][c].re, acc.re);
         acc.im = fma(ch[q][d], Rt[q][c].im, acc.im);
       }
     __syncthreads();
   }
-  if (d < 4) Mout[((size_t)b * 4 + d) * Kc + c] = acc;
+  if (live) Mout[((size_t)b * Kc + c) * 4 + d] = acc;
 }
 
 // Multipoles of level lev - 1 from their eight children at level lev (side nc).
@@ -324,7 +340,8 @@ __global__ void __launch_bounds__(1024) k_fmm_m2m(int P, int nc, double wc, cons
   const int np = nc / 2, b = blockIdx.x;
   const int Kc = tri(P + 1, 0);
   const int i = b % np, j = (b / np) % np, k = b / (np * np);
-  const int o = threadIdx.x, d = o / Kc, c = o % Kc;
+  const int o = threadIdx.x, d = o & 3, c = min(o >> 2, Kc - 1);
+  const bool live = o < 4 * Kc;
   int n = 0, m = 0;
   tri_inv(c, n, m);
   Cx<T> acc{0, 0};
@@ -335,7 +352,7 @@ __global__ void __launch_bounds__(1024) k_fmm_m2m(int P, int nc, double wc, cons
     const T tx = (T)(((e & 1) - 0.5) * wc), ty = (T)((((e >> 1) & 1) - 0.5) * wc), tz = (T)(((e >> 2) - 0.5) * wc);
     const Cx<T>* src = Mc + (size_t)cb * 4 * Kc;
     for (int q = threadIdx.x; q < Kc; q += blockDim.x) {
-      const Cx<T> a = src[q], bb = src[Kc + q], cc = src[2 * Kc + q], dd = src[3 * Kc + q];
+      const Cx<T> a = src[4 * q], bb = src[4 * q + 1], cc = src[4 * q + 2], dd = src[4 * q + 3];
       Mch[0][q] = a;
       Mch[1][q] = bb;
       Mch[2][q] = cc;
@@ -344,55 +361,59 @@ __global__ void __launch_bounds__(1024) k_fmm_m2m(int P, int nc, double wc, cons
       Rt[q] = tabR[(size_t)e * Kc + q];
     }
     __syncthreads();
-    if (d < 4)
+    if (live)
       for (int kk = 0; kk <= n; ++kk)
         for (int l = max(-kk, m - (n - kk)); l <= min(kk, m + (n - kk)); ++l)
           cfma(acc, cget(Mch[d], kk, l), cget(Rt, n - kk, m - l));
     __syncthreads();
   }
-  if (d < 4) Mp[((size_t)b * 4 + d) * Kc + c] = acc;
+  if (live) Mp[((size_t)b * Kc + c) * 4 + d] = acc;
 }
 
-// Locals of level lev (side nl, width w): L2L from the parent (lev > 2) plus M2L from the
-// interaction list.  Boxes without points are skipped.  The M2L operands are expanded in
-// LDS to all m (n^2 + n + m indexing), so the inner sum has no sign cases.
+// Locals from the interaction lists (M2L), every level 2..L in one launch: workgroup g
+// takes box g - first[lev] of level lev (side nl = 2^lev, width w = D / 2^lev), boxes
+// without points are skipped.  One thread per local coefficient (k, l), l >= 0, for all four
+// densities, so every table entry a thread reads serves four products.  The source
+// multipoles are the same for the whole workgroup: they are read in their stored half
+// (m >= 0) with wave-uniform (scalar) loads, the four densities of a coefficient in one, and
+// the m < 0 half enters through X_n^{-m} = (-1)^m conj(X_n^m), which pairs the terms of +m
+// and -m:  M I_a + (-1)^m conj(M) I_b = M.re (I_a.re + s I_b.re) + ..., four real FMAs per
+// density and stored coefficient instead of eight.  The irregular table of the
+// displacement (all m) is staged in LDS.  The psi shift from the source centre to the
+// target's (- a . phi) is applied after the translation, by linearity:
+// T(psi - a.phi) = T(psi) - a . T(phi).  The parents' locals are added afterwards (L2L).
+// Per level: points per box, first box in the expansion arrays, first workgroup of the
+// level in the fused M2L launch (levels 2..L, ascending).
+struct FmmLevels {
+  const int* cnt[8];
+  size_t off[8];
+  int first[9];
+};
+
 template <typename T>
-__global__ void __launch_bounds__(1024) k_fmm_m2l(int P, int nl, double w, const int* __restrict__ cnt,
-                                                  const Cx<T>* __restrict__ tabR, const Cx<T>* __restrict__ tabI,
-                                                  const Cx<T>* __restrict__ Mlev, const Cx<T>* __restrict__ Lpar,
-                                                  Cx<T>* __restrict__ Llev) {
-  constexpr int kFull = (kFmmPMax + 1) * (kFmmPMax + 1), kFull2 = (2 * kFmmPMax + 1) * (2 * kFmmPMax + 1);
-  __shared__ Cx<T> Ms[4][kFull];
+__global__ void __launch_bounds__(256) k_fmm_m2l(int P, int L, double D, FmmLevels lv,
+                                                 const Cx<T>* __restrict__ tabI, const Cx<T>* __restrict__ Mexp,
+                                                 Cx<T>* __restrict__ Lexp) {
+  constexpr int kFull2 = (2 * kFmmPMax + 1) * (2 * kFmmPMax + 1);
   __shared__ Cx<T> It[kFull2];
-  const int b = blockIdx.x;
+  int lev = 2;
+  while (lev < L && (int)blockIdx.x >= lv.first[lev + 1]) ++lev;
+  const int b = (int)blockIdx.x - lv.first[lev];
+  const int* cnt = lv.cnt[lev];
   if (cnt[b] == 0) return;
-  const int Kc = tri(P + 1, 0), F = (P + 1) * (P + 1), F2 = (2 * P + 1) * (2 * P + 1);
+  const int nl = 1 << lev;
+  const double w = ldexp(D, -lev);
+  const int Kc = tri(P + 1, 0), F2 = (2 * P + 1) * (2 * P + 1);
+  const Cx<T>* Mlev = Mexp + lv.off[lev] * 4 * Kc;
+  const Cx<T>* tabl = tabI + (size_t)(lev - 2) * kFmmVecs * F2;
   const int i = b % nl, j = (b / nl) % nl, k = b / (nl * nl);
-  const int o = threadIdx.x, d = o / Kc, c = o % Kc;
+  const int c = threadIdx.x;
+  const bool act = c < Kc;
   int kk = 0, ll = 0;
-  tri_inv(c, kk, ll);
-  Cx<T> acc{0, 0};
-  if (Lpar) {
-    const int np = nl / 2;
-    const int e = (i & 1) | ((j & 1) << 1) | ((k & 1) << 2);
-    const T tx = (T)(((e & 1) - 0.5) * w), ty = (T)((((e >> 1) & 1) - 0.5) * w), tz = (T)(((e >> 2) - 0.5) * w);
-    const Cx<T>* src = Lpar + (size_t)(((k / 2) * np + j / 2) * np + i / 2) * 4 * Kc;
-    for (int q = threadIdx.x; q < Kc; q += blockDim.x) {
-      const Cx<T> a = src[q], bb = src[Kc + q], cc = src[2 * Kc + q], dd = src[3 * Kc + q];
-      Ms[0][q] = a;
-      Ms[1][q] = bb;
-      Ms[2][q] = cc;
-      // psi moves from the parent centre to the child's: - (c' - c) . phi
-      Ms[3][q] = Cx<T>{dd.re - tx * a.re - ty * bb.re - tz * cc.re, dd.im - tx * a.im - ty * bb.im - tz * cc.im};
-      It[q] = tabR[(size_t)e * Kc + q];
-    }
-    __syncthreads();
-    if (d < 4)
-      for (int n = kk; n <= P; ++n)
-        for (int l = max(-n, ll - (n - kk)); l <= min(n, ll + (n - kk)); ++l)
-          cfma(acc, cget(Ms[d], n, l), cget(It, n - kk, l - ll));
-    __syncthreads();
-  }
+  if (act) tri_inv(c, kk, ll);
+  Cx<T> acc[4];
+  for (int d = 0; d < 4; ++d) acc[d] = Cx<T>{0, 0};
+  const T sk_sign = (kk & 1) ? T(-1) : T(1);
   const int pi = i / 2, pj = j / 2, pk = k / 2;
   for (int sk = max(0, 2 * pk - 2); sk <= min(nl - 1, 2 * pk + 3); ++sk)
     for (int sj = max(0, 2 * pj - 2); sj <= min(nl - 1, 2 * pj + 3); ++sj)
@@ -401,59 +422,100 @@ __global__ void __launch_bounds__(1024) k_fmm_m2l(int P, int nl, double w, const
         if (abs(vx) <= 1 && abs(vy) <= 1 && abs(vz) <= 1) continue;
         const int sb = (sk * nl + sj) * nl + si;
         if (cnt[sb] == 0) continue;
-        // psi moves from the source centre to the target's: + (c_s - c_t) . phi = - a . phi
-        const T ax = (T)(vx * w), ay = (T)(vy * w), az = (T)(vz * w);
-        const Cx<T>* src = Mlev + (size_t)sb * 4 * Kc;
-        for (int q = threadIdx.x; q < F; q += blockDim.x) {
-          int n = 0, m = 0;
-          n = (int)sqrtf((float)q);
-          while (n * n > q) --n;
-          while ((n + 1) * (n + 1) <= q) ++n;
-          m = q - n * n - n;
-          const int h = tri(n, m < 0 ? -m : m);
-          Cx<T> a = src[h], bb = src[Kc + h], cc = src[2 * Kc + h], dd = src[3 * Kc + h];
-          Cx<T> dpsi{dd.re - ax * a.re - ay * bb.re - az * cc.re, dd.im - ax * a.im - ay * bb.im - az * cc.im};
-          if (m < 0) {
-            // X_n^{-m} = (-1)^m conj(X_n^m)
-            const T sg = (m & 1) ? T(-1) : T(1);
-            a = Cx<T>{sg * a.re, -sg * a.im};
-            bb = Cx<T>{sg * bb.re, -sg * bb.im};
-            cc = Cx<T>{sg * cc.re, -sg * cc.im};
-            dpsi = Cx<T>{sg * dpsi.re, -sg * dpsi.im};
-          }
-          Ms[0][q] = a;
-          Ms[1][q] = bb;
-          Ms[2][q] = cc;
-          Ms[3][q] = dpsi;
-        }
-        const Cx<T>* tv = tabI + (size_t)(((vz + 3) * 7 + (vy + 3)) * 7 + (vx + 3)) * tri(2 * P + 1, 0);
-        for (int q = threadIdx.x; q < F2; q += blockDim.x) {
-          int n = (int)sqrtf((float)q);
-          while (n * n > q) --n;
-          while ((n + 1) * (n + 1) <= q) ++n;
-          const int m = q - n * n - n;
-          It[q] = cget(tv, n, m);
-        }
+        const Cx<T>* tv = tabl + (size_t)(((vz + 3) * 7 + (vy + 3)) * 7 + (vx + 3)) * F2;
+        __syncthreads();  // the previous source's table has been read
+        for (int q = threadIdx.x; q < F2; q += blockDim.x) It[q] = tv[q];
         __syncthreads();
-        if (d < 4) {
-          Cx<T> part{0, 0};
-          const Cx<T>* md = Ms[d];
+        if (act) {
+          Cx<T> pt[4];
+          for (int d = 0; d < 4; ++d) pt[d] = Cx<T>{0, 0};
+          // M I_a + sg conj(M) I_b for the stored coefficient M (four densities at v)
+          auto pair = [&](const Cx<T>* v, int ia, int ib, T sg) {
+            const Cx<T> ip = It[ia], im = It[ib];
+            const T s1 = fma(sg, im.re, ip.re), s2 = fma(sg, im.im, -ip.im);
+            const T s3 = fma(sg, im.im, ip.im), s4 = fma(-sg, im.re, ip.re);
+            for (int d = 0; d < 4; ++d) {
+              const Cx<T> a = v[d];
+              pt[d].re = fma(a.re, s1, fma(a.im, s2, pt[d].re));
+              pt[d].im = fma(a.re, s3, fma(a.im, s4, pt[d].im));
+            }
+          };
+          // the source's coefficients in stored order: (n, 0), (n, 1), ..., (n, n), (n + 1, 0), ...
+          const Cx<T>* v = Mlev + (size_t)sb * 4 * Kc;
           for (int n = 0; n <= P; ++n) {
-            const int bm = n * n + n, nk = n + kk;
+            const int nk = n + kk;
             const int bi = nk * nk + nk + ll;
-            for (int m = -n; m <= n; ++m) cfma(part, md[bm + m], It[bi + m]);
+            {
+              const Cx<T> ip = It[bi];
+              for (int d = 0; d < 4; ++d) cfma(pt[d], v[d], ip);
+              v += 4;
+            }
+            int m = 1;
+            for (; m + 1 <= n; m += 2, v += 8) {
+              pair(v, bi + m, bi - m, T(-1));
+              pair(v + 4, bi + m + 1, bi - m - 1, T(1));
+            }
+            if (m <= n) {
+              pair(v, bi + m, bi - m, T(-1));
+              v += 4;
+            }
           }
-          if (kk & 1) {
-            acc.re -= part.re;
-            acc.im -= part.im;
-          } else {
-            acc.re += part.re;
-            acc.im += part.im;
+          // psi about the target centre: T(psi) - a . T(phi), a = c_t - c_s
+          const T ax = (T)(vx * w), ay = (T)(vy * w), az = (T)(vz * w);
+          pt[3].re -= ax * pt[0].re + ay * pt[1].re + az * pt[2].re;
+          pt[3].im -= ax * pt[0].im + ay * pt[1].im + az * pt[2].im;
+          for (int d = 0; d < 4; ++d) {
+            acc[d].re = fma(sk_sign, pt[d].re, acc[d].re);
+            acc[d].im = fma(sk_sign, pt[d].im, acc[d].im);
           }
         }
-        __syncthreads();
       }
-  if (d < 4) Llev[((size_t)b * 4 + d) * Kc + c] = acc;
+  if (act) {
+    Cx<T>* out = Lexp + (lv.off[lev] + (size_t)b) * 4 * Kc + (size_t)c * 4;
+    for (int d = 0; d < 4; ++d) out[d] = acc[d];
+  }
+}
+
+// Locals of level lev (side nl, width w) += the parent's locals translated to the box
+// centre (L2L); the psi expansion moves from the parent centre to the child's by
+// - (c' - c) . phi.  One workgroup per box, one thread per coefficient, four densities.
+template <typename T>
+__global__ void __launch_bounds__(256) k_fmm_l2l(int P, int nl, double w, const int* __restrict__ cnt,
+                                                 const Cx<T>* __restrict__ tabR, const Cx<T>* __restrict__ Lpar,
+                                                 Cx<T>* __restrict__ Llev) {
+  __shared__ Cx<T> Ps[4][kFmmKc];
+  __shared__ Cx<T> Rt[kFmmKc];
+  const int b = blockIdx.x;
+  if (cnt[b] == 0) return;
+  const int Kc = tri(P + 1, 0);
+  const int i = b % nl, j = (b / nl) % nl, k = b / (nl * nl);
+  const int c = threadIdx.x;
+  const bool act = c < Kc;
+  int kk = 0, ll = 0;
+  if (act) tri_inv(c, kk, ll);
+  const int np = nl / 2;
+  const int e = (i & 1) | ((j & 1) << 1) | ((k & 1) << 2);
+  const T tx = (T)(((e & 1) - 0.5) * w), ty = (T)((((e >> 1) & 1) - 0.5) * w), tz = (T)(((e >> 2) - 0.5) * w);
+  const Cx<T>* src = Lpar + (size_t)(((k / 2) * np + j / 2) * np + i / 2) * 4 * Kc;
+  for (int q = threadIdx.x; q < Kc; q += blockDim.x) {
+    const Cx<T> a = src[4 * q], bb = src[4 * q + 1], cc = src[4 * q + 2], dd = src[4 * q + 3];
+    Ps[0][q] = a;
+    Ps[1][q] = bb;
+    Ps[2][q] = cc;
+    Ps[3][q] = Cx<T>{dd.re - tx * a.re - ty * bb.re - tz * cc.re, dd.im - tx * a.im - ty * bb.im - tz * cc.im};
+    Rt[q] = tabR[(size_t)e * Kc + q];
+  }
+  __syncthreads();
+  if (!act) return;
+  Cx<T>* out = Llev + ((size_t)b * Kc + c) * 4;
+  Cx<T> acc[4];
+  for (int d = 0; d < 4; ++d) acc[d] = out[d];
+  for (int n = kk; n <= P; ++n)
+    for (int l = max(-n, ll - (n - kk)); l <= min(n, ll + (n - kk)); ++l) {
+      const Cx<T> r = cget(Rt, n - kk, l - ll);
+      for (int d = 0; d < 4; ++d) cfma(acc[d], cget(Ps[d], n, l), r);
+    }
+  for (int d = 0; d < 4; ++d) out[d] = acc[d];
 }
 
 // Work items of the leaf kernel: (leaf, first target) for every 64 targets of a leaf.
@@ -518,15 +580,15 @@ __global__ void __launch_bounds__(256) k_fmm_leaf(int P, int nb, double lox, dou
     for (int dd = 0; dd < 4; ++dd) A[dd] = B[dd] = C[dd] = Cx<T>{0, 0};
     auto term = [&](int kk, int l, Cx<T> v) {
       if (kk <= P - 1) {
-        cfma(g0, cget(Lb, kk + 1, l + 1), v);
-        cfma(g1, cget(Lb + Kc, kk + 1, l + 1), v);
-        cfma(g2, cget(Lb + 2 * Kc, kk + 1, l), v);
+        cfma(g0, cget4(Lb, kk + 1, l + 1, 0), v);
+        cfma(g1, cget4(Lb, kk + 1, l + 1, 1), v);
+        cfma(g2, cget4(Lb, kk + 1, l, 2), v);
       }
       if (kk <= P - 2)
         for (int dd = 0; dd < 4; ++dd) {
-          cfma(A[dd], cget(Lb + dd * Kc, kk + 2, l + 2), v);
-          cfma(B[dd], cget(Lb + dd * Kc, kk + 2, l + 1), v);
-          cfma(C[dd], cget(Lb + dd * Kc, kk + 2, l), v);
+          cfma(A[dd], cget4(Lb, kk + 2, l + 2, dd), v);
+          cfma(B[dd], cget4(Lb, kk + 2, l + 1, dd), v);
+          cfma(C[dd], cget4(Lb, kk + 2, l, dd), v);
         }
     };
     // R_kk^l(s) column by column (l >= 0): conj(R^l) for +l and (-1)^l R^l for -l
@@ -568,25 +630,37 @@ __global__ void __launch_bounds__(256) k_fmm_leaf(int P, int nb, double lox, dou
     fy = sc * (div * ny + Hs[3] * nx + Hs[1] * ny + Hs[5] * nz);
     fz = sc * (div * nz + Hs[4] * nx + Hs[5] * ny + Hs[2] * nz);
   }
-  // near field: for each (nk, nj) the leaves ni - 1 .. ni + 1 are consecutive in leaf order
+  // near field: traction of the other bodies' points in the 27 adjacent leaves
+  // (same-body pairs: weight 0, and |d|^2 + 1 keeps the point's own pair finite; the
+  // arithmetic mask keeps the loop free of branches)
+  auto near = [&](const Src8<T>& s) {
+    const T dx = xa - s.v[0], dy = ya - s.v[1], dz = za - s.v[2];
+    const T other = s.v[6] == bt ? T(0) : T(1);
+    const T r2 = fma(dx, dx, fma(dy, dy, fma(dz, dz, T(1) - other)));
+    const T dn = dx * nx + dy * ny + dz * nz;
+    const T dq = dx * s.v[3] + dy * s.v[4] + dz * s.v[5];
+    const T f = ((dn * dq) * other) * rinv5_t(r2);
+    fx += f * dx;
+    fy += f * dy;
+    fz += f * dz;
+  };
+  // for each (nk, nj) the leaves ni - 1 .. ni + 1 are consecutive in leaf order
   const int i0 = max(0, i - 1), i1 = min(nb - 1, i + 1);
   for (int nk = max(0, k - 1); nk <= min(nb - 1, k + 1); ++nk)
     for (int nj = max(0, j - 1); nj <= min(nb - 1, j + 1); ++nj) {
       const int row = (nk * nb + nj) * nb;
       const int a0 = __builtin_amdgcn_readfirstlane(start[row + i0]);
       const int a1 = __builtin_amdgcn_readfirstlane(start[row + i1 + 1]);
-      for (int q = a0; q < a1; ++q) {
-        const Src8<T> s = srt[q];
-        const T dx = xa - s.v[0], dy = ya - s.v[1], dz = za - s.v[2];
-        const bool same = s.v[6] == bt;
-        const T r2 = same ? T(1) : dx * dx + dy * dy + dz * dz;
-        const T dn = dx * nx + dy * ny + dz * nz;
-        const T dq = dx * s.v[3] + dy * s.v[4] + dz * s.v[5];
-        const T f = same ? T(0) : (dn * dq) * rinv5_t(r2);
-        fx += f * dx;
-        fy += f * dy;
-        fz += f * dz;
+      // four sources per step: their scalar loads are issued together
+      int q = a0;
+      for (; q + 4 <= a1; q += 4) {
+        const Src8<T> s0 = srt[q], s1 = srt[q + 1], s2 = srt[q + 2], s3 = srt[q + 3];
+        near(s0);
+        near(s1);
+        near(s2);
+        near(s3);
       }
+      for (; q < a1; ++q) near(srt[q]);
     }
   if (live) {
     const int g = perm[s0 + t];
@@ -656,7 +730,7 @@ hipError_t launch_fmm_apply(int P, int L, const double* lo, double D, int N, con
                             int ntask, const int2* task, const void* tabR, const void* tabI, const void* src,
                             void* srt, void* Mexp, void* Lexp, double* out, hipStream_t st) {
   if (P < 2 || P > kFmmPMax || L < 0) return hipErrorInvalidValue;
-  const int nb = 1 << L, Kc = tri(P + 1, 0), Kc2 = tri(2 * P + 1, 0);
+  const int nb = 1 << L, Kc = tri(P + 1, 0);
   const double w = ldexp(D, -L);
   Src8<T>* so = static_cast<Src8<T>*>(srt);
   Cx<T>* Mx = static_cast<Cx<T>*>(Mexp);
@@ -675,14 +749,22 @@ hipError_t launch_fmm_apply(int P, int L, const double* lo, double D, int N, con
                                                 tR + (size_t)(lev - 2) * 8 * Kc, Mx + lev_off[lev] * 4 * Kc,
                                                 Mx + lev_off[lev - 1] * 4 * Kc);
     }
+    if (L > 6) return hipErrorInvalidValue;
+    FmmLevels lv{};
+    int nwg = 0;
     for (int lev = 2; lev <= L; ++lev) {
+      lv.cnt[lev] = cnt_lev[lev];
+      lv.off[lev] = lev_off[lev];
+      lv.first[lev] = nwg;
+      nwg += 1 << (3 * lev);
+    }
+    lv.first[L + 1] = nwg;
+    const int thl = (Kc + 63) / 64 * 64;
+    k_fmm_m2l<T><<<nwg, thl, 0, st>>>(P, L, D, lv, tI, Mx, Lx);
+    for (int lev = 3; lev <= L; ++lev) {
       const int nl = 1 << lev;
-      k_fmm_m2l<T><<<nl * nl * nl, th, 0, st>>>(P, nl, ldexp(D, -lev), cnt_lev[lev],
-                                                tR + (size_t)(lev - 2) * 8 * Kc,
-                                                tI + (size_t)(lev - 2) * kFmmVecs * Kc2,
-                                                Mx + lev_off[lev] * 4 * Kc,
-                                                lev > 2 ? Lx + lev_off[lev - 1] * 4 * Kc : nullptr,
-                                                Lx + lev_off[lev] * 4 * Kc);
+      k_fmm_l2l<T><<<nl * nl * nl, thl, 0, st>>>(P, nl, ldexp(D, -lev), cnt_lev[lev], tR + (size_t)(lev - 2) * 8 * Kc,
+                                                Lx + lev_off[lev - 1] * 4 * Kc, Lx + lev_off[lev] * 4 * Kc);
     }
   }
   if (ntask > 0)

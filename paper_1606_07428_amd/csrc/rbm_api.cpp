@@ -360,7 +360,8 @@ static size_t layout(rbm_ctx* c, int nmax, bool assign) {
     const size_t nleaf = (size_t)1 << (3 * Lm);
     size_t btot = 0;
     for (int l = 2; l <= Lm; ++l) btot += (size_t)1 << (3 * l);
-    const size_t kc = (size_t)(P + 1) * (P + 2) / 2, kc2 = (size_t)(2 * P + 1) * (2 * P + 2) / 2;
+    // expansions keep m >= 0 ((P+1)(P+2)/2 coefficients); the M2L tables hold all m, (2P+1)^2
+    const size_t kc = (size_t)(P + 1) * (P + 2) / 2, kc2 = (size_t)(2 * P + 1) * (2 * P + 1);
     take(c->fleaf, N); take(c->fperm, N); take(c->fstart, nleaf + 1); take(c->ffill, nleaf);
     take(c->fcnt, std::max(btot, nleaf)); take(c->fmax, 64);
     take(c->fXs, N); take(c->fNs, N); take(c->fbounds, 64);
