@@ -248,13 +248,14 @@ __global__ __launch_bounds__(256) void k_interp_pack(int n, int M, int Mu, int n
 }
 
 // Correction of the all-pairs sum for near pairs.  The concatenated source list of body
-// i (for each near body j: its M_u fine sources, then its M plain sources with negated
-// strength, since the all-pairs sum already counted them and both kernels are linear in
-// q) is cut into items of ch positions; item t = (body item_body[t], positions
-// [item_pos[t], item_pos[t] + ch) clipped to the list).  The workgroup of item t holds
-// body i's targets (one per thread), stages its positions in LDS (one source per
-// thread, vector loads) and sweeps them as LDS broadcasts; it writes the scaled sums
-// of its targets to slot t ([items][3][M]).
+// i (for each near body j: its M_u fine sources, then its M plain sources, which the
+// all-pairs sum already counted and are subtracted here; both sums are linear in q) is
+// cut into items of ch positions; item t = (body item_body[t], positions [item_pos[t],
+// item_pos[t] + ch) clipped to the list).  The workgroup of item t holds body i's targets
+// (one per thread); the item's sources are the same for every thread, so they are read
+// with wave-uniform (scalar) loads, four at a time, as in the all-pairs sum.  Fine and
+// plain sources go to separate accumulators, subtracted at the end.  The scaled sums of
+// the item's targets go to slot t ([items][3][M]).
 template <typename T, int KIND>
 __global__ __launch_bounds__(1024) void k_near_corr(int N, int M, int Mu, int kmax, int ch,
                                                     const int* __restrict__ item_body,
@@ -265,9 +266,6 @@ __global__ __launch_bounds__(1024) void k_near_corr(int N, int M, int Mu, int km
                                                     const int* __restrict__ nbr,
                                                     const int* __restrict__ cnt,
                                                     double* __restrict__ slots) {
-  extern __shared__ __align__(16) unsigned char lds_raw[];
-  T* sh = reinterpret_cast<T*>(lds_raw);  // [6][blockDim]
-  const int B = blockDim.x;
   const int t = blockIdx.x, i = item_body[t];
   const int a = threadIdx.x;
   const int g = i * M + min(a, M - 1);
@@ -278,38 +276,34 @@ __global__ __launch_bounds__(1024) void k_near_corr(int N, int M, int Mu, int km
     ny = tn[N + g];
     nz = tn[2 * (size_t)N + g];
   }
-  T ax = 0, ay = 0, az = 0;
+  T fx = 0, fy = 0, fz = 0, px = 0, py = 0, pz = 0;
+  auto sweep = [&](const Src8<T>* q, int n, T& ax, T& ay, T& az) {
+    int k = 0;
+    for (; k + 4 <= n; k += 4) {
+      const Src8<T> q0 = q[k], q1 = q[k + 1], q2 = q[k + 2], q3 = q[k + 3];
+      Pair<T, KIND>::add(xa, ya, za, nx, ny, nz, q0, ax, ay, az);
+      Pair<T, KIND>::add(xa, ya, za, nx, ny, nz, q1, ax, ay, az);
+      Pair<T, KIND>::add(xa, ya, za, nx, ny, nz, q2, ax, ay, az);
+      Pair<T, KIND>::add(xa, ya, za, nx, ny, nz, q3, ax, ay, az);
+    }
+    for (; k < n; ++k) Pair<T, KIND>::add(xa, ya, za, nx, ny, nz, q[k], ax, ay, az);
+  };
   const int seg = Mu + M, L = min(cnt[i], kmax) * seg;
   const int lo = item_pos[t], hi = min(L, lo + ch);
-  for (int t0 = lo; t0 < hi; t0 += B) {
-    const int m = min(B, hi - t0);
-    __syncthreads();
-    if (a < m) {
-      const int u = t0 + a, k = u / seg, r = u - k * seg;
-      const int j = nbr[(size_t)i * kmax + k];
-      Src8<T> q;
-      T sg = (T)1;
-      if (r < Mu) {
-        q = srcf[(size_t)j * Mu + r];
-      } else {
-        q = src[(size_t)j * M + (r - Mu)];
-        sg = (T)-1;
-      }
-#pragma unroll
-      for (int e = 0; e < 3; ++e) sh[e * B + a] = q.v[e];
-#pragma unroll
-      for (int e = 3; e < 6; ++e) sh[e * B + a] = sg * q.v[e];
-    }
-    __syncthreads();
-    Src8<T> q;
-    q.v[6] = q.v[7] = 0;
-#pragma unroll 4
-    for (int e2 = 0; e2 < m; ++e2) {
-#pragma unroll
-      for (int e = 0; e < 6; ++e) q.v[e] = sh[e * B + e2];
-      Pair<T, KIND>::add(xa, ya, za, nx, ny, nz, q, ax, ay, az);
+  for (int u = lo; u < hi;) {
+    const int k = u / seg, r = u - k * seg;
+    const int j = nbr[(size_t)i * kmax + k];
+    if (r < Mu) {
+      const int n = min(hi - u, Mu - r);
+      sweep(srcf + (size_t)j * Mu + r, n, fx, fy, fz);
+      u += n;
+    } else {
+      const int n = min(hi - u, seg - r);
+      sweep(src + (size_t)j * M + (r - Mu), n, px, py, pz);
+      u += n;
     }
   }
+  const T ax = fx - px, ay = fy - py, az = fz - pz;
   if (a < M) {
     const double scale = (KIND == 0 ? -3.0 / (4.0 * RBM_PI) : 1.0 / (8.0 * RBM_PI)) * Pair<T, KIND>::kPost;
     double* o = slots + (size_t)t * 3 * M;
@@ -359,7 +353,7 @@ hipError_t launch_near_corr(int kind, int n, int M, int Mu, int kmax, int nneed,
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     const int bs = ((M + 63) / 64) * 64;
-    const size_t lds = 6 * (size_t)bs * sizeof(T);
+    const size_t lds = 0;
     const Src8<T>* ps = reinterpret_cast<const Src8<T>*>(src);
     const Src8<T>* pf = reinterpret_cast<const Src8<T>*>(srcf);
     if (kind == 0)
