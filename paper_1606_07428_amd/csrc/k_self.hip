@@ -35,7 +35,6 @@ __global__ __launch_bounds__(64 * WAVES) void k_self_apply(int M, int N, const i
                                                            double* __restrict__ y_body) {
   using TA = typename AccOf<TM>::T;
   using V = RowVec<TM, RPL>;
-  static_assert(!NT || RPL == 1, "non-temporal loads of single entries only");
   extern __shared__ double smem[];
   const int M3 = 3 * M;
   TA* xs = reinterpret_cast<TA*>(smem);               // [3M] body-frame input
@@ -61,9 +60,16 @@ __global__ __launch_bounds__(64 * WAVES) void k_self_apply(int M, int N, const i
 #pragma unroll
     for (int r = 0; r < RPL; ++r) acc[u][r] = 0;
   auto load = [&](const TM* p) -> V {
-    if constexpr (NT) {
+    if constexpr (NT && RPL == 1) {
       V v;
       v.v[0] = __builtin_nontemporal_load(p);
+      return v;
+    } else if constexpr (NT) {
+      typedef TM VT __attribute__((ext_vector_type(RPL)));
+      const VT x = __builtin_nontemporal_load(reinterpret_cast<const VT*>(p));
+      V v;
+#pragma unroll
+      for (int r = 0; r < RPL; ++r) v.v[r] = x[r];
       return v;
     } else {
       return *reinterpret_cast<const V*>(p);
@@ -121,7 +127,13 @@ hipError_t launch_self_apply(int n, int M, const int* sid, const TM* A, const do
   if constexpr (sizeof(TM) == 8) {
     return self_apply_rpl<TM, 1, 16, true>(n, M, sid, A, Rm, x_lab, y_body, st);
   } else {
-    if (M3 % 4 == 0 && M3 >= 768) return self_apply_rpl<TM, 4, 4, false>(n, M, sid, A, Rm, x_lab, y_body, st);
+    // blocks beyond the 256 MB Infinity Cache are streamed once per apply: non-temporal loads
+    // and 8 waves per workgroup (4000 bodies x 936 rows in float32: 7 % less time per apply)
+    const bool stream = (double)n * M3 * M3 * sizeof(TM) > 256.0 * (1 << 20);
+    if (M3 % 4 == 0 && M3 >= 768) {
+      if (stream) return self_apply_rpl<TM, 4, 8, true>(n, M, sid, A, Rm, x_lab, y_body, st);
+      return self_apply_rpl<TM, 4, 4, false>(n, M, sid, A, Rm, x_lab, y_body, st);
+    }
     if (M3 % 2 == 0) return self_apply_rpl<TM, 2, 4, false>(n, M, sid, A, Rm, x_lab, y_body, st);
     return self_apply_rpl<TM, 1, 4, false>(n, M, sid, A, Rm, x_lab, y_body, st);
   }
