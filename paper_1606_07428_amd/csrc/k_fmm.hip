@@ -9,14 +9,15 @@
 //
 // Complex solid harmonics with factorial normalisation (no Condon-Shortley phase):
 //   R_n^m = r^n P_n^m e^{i m phi} / (n+m)!,  I_n^m = (n-m)! P_n^m e^{i m phi} / r^{n+1},
-//   X_n^{-m} = (-1)^m conj(X_n^m); only m >= 0 is stored (index n(n+1)/2 + m).
+//   X_n^{-m} = (-1)^m conj(X_n^m); expansions store m >= 0 only, coefficient n(n+1)/2 + m,
+//   the four densities of a coefficient adjacent.
 // Multipole about c: M_n^m = sum q conj(R_n^m(y - c)); local about c: phi = sum L conj(R(x - c)).
 //   M2M (child c1 -> parent c2): M'_n^m = sum_{k,l} M_k^l conj(R_{n-k}^{m-l}(c1 - c2))
 //   M2L (a = c_t - c_s):          L_k^l  = (-1)^k sum_{n,m} M_n^m I_{n+k}^{m+l}(a)
 //   L2L (parent c -> child c'):   L'_j^i = sum_{k,l} L_k^l conj(R_{k-j}^{l-i}(c' - c))
 //   d/dz of a local expansion shifts L_{k+1}^l, (d/dx + i d/dy) shifts L_{k+1}^{l+1}.
 // Moving the psi expansion from centre c to c' adds (c - c') . (phi_1, phi_2, phi_3)
-// expansions before the translation.
+// expansions: before the translation in M2M and L2L, after it (by linearity) in M2L.
 //
 // Tree: uniform octree over the bounding cube of the points (side D, corner lo), leaf
 // level L with leaf width >= the largest body diameter, so the nodes of one body lie in
