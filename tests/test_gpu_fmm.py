@@ -43,7 +43,8 @@ def _ctx(nbodies, p, P, max_level=5):
     return rbm.solver_for(inputs.lattice(nbodies, p), fmm_order=P, fmm_max_level=max_level)
 
 
-@pytest.mark.parametrize("side,npts,P,prec", [(4, 40, 8, 0), (6, 16, 6, 0), (4, 40, 8, 1), (2, 30, 6, 0)])
+@pytest.mark.parametrize("side,npts,P,prec", [(4, 40, 8, 0), (6, 16, 6, 0), (4, 40, 8, 1), (2, 30, 6, 0),
+                                               (8, 12, 12, 0), (6, 16, 13, 1)])
 def test_fmm_matches_the_oracle_fmm(side, npts, P, prec):
     _case(f"fmm vs oracle fmm: side={side} npts={npts} P={P} precision={prec}")
     X, Nn, q, body = _cloud(side, 3.0, npts, 11 + side)
