@@ -1,10 +1,11 @@
 """Full-size solves in the configuration the benchmark times, checked against the oracle:
-the 4000-body suspension at 20 % with a true surface gap of 0.1 (p = 12, 1.25 M points) and
-the 1000-ellipsoid suspension (p = 16, 544 k points).  The GPU solves in the precision form
-(float32 far sums with fast multipole inner iterations of order 12, float32 block
-preconditioner, float64 refinement residuals) with the learned warm start, to a relative
-residual of 1e-8, with near-singular upsampling where bodies are closer than a node
-spacing.  On sampled bodies the oracle then applies its own float64 operator to the
+the 4000-body suspension at 20 % with a true surface gap of 0.1 (p = 12, 1.25 M points), the
+1000-ellipsoid suspension (p = 16, 544 k points) and the 512 sedimenting spheres (p = 12,
+160 k points) after three RK4 steps.  The GPU solves in the precision form (float32 far sums
+with fast multipole inner iterations of order 12 at the two larger sizes, direct float32
+sums at 512 bodies, float32 block preconditioner, float64 refinement residuals) with the
+learned warm start, to a relative residual of 1e-8, with near-singular upsampling where
+bodies are closer than a node spacing.  On sampled bodies the oracle then applies its own float64 operator to the
 GPU density (§2.3, §3.2): the residual rows b - A mu against its own right-hand side, the
 GPU's float64 residual vector at those rows, and the velocities it computes from the GPU
 density (§3.3) against the GPU's.  The oracle's off-body sums at the sampled targets run in
@@ -42,18 +43,27 @@ def _par_rows(prob, fn, idx):
 # Near-singular upsampling (§3) per configuration: the 20 % suspension has surfaces 0.1
 # apart, half a node spacing, where the plain smooth rule leaves the discrete system too
 # ill-conditioned for GMRES; the 10 % ellipsoids do not need it.
-P_UP = {"dense4000": 24, "ellipsoids1000": 0}
+P_UP = {"dense4000": 24, "ellipsoids1000": 0, "sediment512": 0}
+FMM = {"dense4000": 12, "ellipsoids1000": 12, "sediment512": 0}
+# RK4 steps (their stage solves captured for training) before the checked solve
+STEPS = {"dense4000": 0, "ellipsoids1000": 0, "sediment512": 3}
 
 
 def _gpu_solve(name):
     w = inputs.workload(name)
     _case(f"{name}: setup, block-diagonal mixed solve (captured), training, learned mixed solve")
-    s = rbm.solver_for(w, tol=1e-8, precision=rbm.MIXED_FP32, guess=rbm.GUESS_BLOCKDIAG, fmm_order=12,
+    s = rbm.solver_for(w, tol=1e-8, precision=rbm.MIXED_FP32, guess=rbm.GUESS_BLOCKDIAG, fmm_order=FMM[name],
                        p_up=P_UP[name])
-    s.learned_bind(k_nbr=8, hidden=256, n_hidden=3, capacity=s.n, batch_max=1024, seed=7)
+    s.learned_bind(k_nbr=8, hidden=256, n_hidden=3, capacity=s.n * (1 + 4 * STEPS[name]), batch_max=1024, seed=7)
     FT = torch.as_tensor(np.asarray(w["FT"], dtype=np.float64), device="cuda")
     VW = torch.zeros_like(FT)
     s.learned_set_capture(True)
+    for k in range(STEPS[name]):
+        s.step_rk4(0.1, FT)
+        print(f"[case] {name}: RK4 step {k + 1}/{STEPS[name]}", flush=True)
+    if STEPS[name]:
+        c, q = s.bodies()
+        w = dict(w, centres=c, quats=q)
     i_bd = s.solve_dev(FT, VW)
     s.learned_set_capture(False)
     s.learned_train(20, 256, 1e-3)
@@ -70,7 +80,7 @@ def _gpu_solve(name):
     return out
 
 
-@pytest.fixture(scope="module", params=["dense4000", "ellipsoids1000"])
+@pytest.fixture(scope="module", params=["dense4000", "ellipsoids1000", "sediment512"])
 def solved(request):
     out = _gpu_solve(request.param)
     out["name"] = request.param
@@ -88,7 +98,7 @@ def _ops(prob, i):
     return sh
 
 
-SAMPLES = {"dense4000": [7, 2711], "ellipsoids1000": [12, 640]}
+SAMPLES = {"dense4000": [7, 2711], "ellipsoids1000": [12, 640], "sediment512": [3, 300]}
 
 
 def test_learned_mixed_solve_meets_the_tolerance_against_the_oracle(solved):
