@@ -33,6 +33,9 @@
  *    centroid.  Torques are about that centroid.  F_i is the force the body exerts
  *    on the fluid (traction integrates to -F_i), so an isolated sphere of radius a
  *    moves with v = F/(6 pi eta a), omega = T/(8 pi eta a^3).
+ *  - Tracing: with the environment variable RBM_VERBOSE set when a context is created, its
+ *    solves print each refinement's residual kind and size and each GMRES cycle's iterations
+ *    to stderr.
  *  - Errors: every call returns an rbm_status; rbm_last_error() gives a
  *    thread-local message.  No call throws across the ABI.  Calls on one context
  *    are not thread safe; different contexts are independent.
