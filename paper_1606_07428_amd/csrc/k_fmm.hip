@@ -32,7 +32,6 @@ namespace rbm {
 
 constexpr int kFmmPMax = kFmmMaxOrder;
 constexpr int kFmmKc = (kFmmPMax + 1) * (kFmmPMax + 2) / 2;          // coefficients, m >= 0
-constexpr int kFmmKc2 = (2 * kFmmPMax + 1) * (2 * kFmmPMax + 2) / 2;  // degree 2P table
 constexpr int kFmmLeafMax = kFmmLeafCap;                              // points per leaf
 constexpr int kFmmVecs = 343;                                         // displacements in [-3, 3]^3
 

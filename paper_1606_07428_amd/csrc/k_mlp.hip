@@ -95,7 +95,6 @@ __global__ __launch_bounds__(256) void k_gemm_bf16_tile16(int m, int n, int k,
   const int lr = lane & 15, lk = 4 * (lane >> 4);
   const int ia = ti * 16 + lr, jb = tj * 16 + lr;
   f4v acc = (f4v){0.f, 0.f, 0.f, 0.f};
-#pragma unroll 2
   for (int k0 = 16 * w; k0 < k; k0 += 64) {
     s4v av, bv;
 #pragma unroll
