@@ -337,3 +337,20 @@ def test_stalled_refinement_switches_to_float64_cycles():
     assert info2["fp64_cycles"] == 0
     s.close()
     s2.close()
+
+
+@pytest.mark.parametrize("prec", [rbm.FP64, rbm.MIXED_FP32])
+def test_zero_loads_give_zero_velocities(prec):
+    """No load on any body: the incident density and the right-hand side vanish (§2.2), so
+    mu = 0 and every velocity is exactly zero, without a GMRES iteration; a load on one body
+    afterwards is solved normally."""
+    _case(f"zero loads, precision {prec}")
+    w = inputs.tiny(4, 5, seed=3)
+    s = rbm.solver_for(w, tol=1e-10, precision=prec)
+    VW, info = s.solve(np.zeros((4, 6)))
+    assert np.all(VW == 0.0) and info["iters"] == 0 and info["rel_residual"] == 0.0
+    FT = np.zeros((4, 6))
+    FT[2, 1] = 1.0
+    VW, info = s.solve(FT)
+    assert info["rel_residual"] <= 1e-10 and info["iters"] > 0 and VW[2, 1] > 0
+    s.close()
