@@ -21,9 +21,11 @@ body pairs):
      throughout);
   3. ``value`` is the off-body pair interactions the float64 solve evaluates divided by the
      learned precision-form solve's time (the float64 solve's work delivered per second);
-     ``roofline`` is the float64 traction kernel of the timed solves (their exact residual
-     sums; HIP events on the library stream); ``cpu_baseline`` is the FP64 NumPy oracle's
-     traction sum on a sample of targets, threaded over the host's cores.
+     ``roofline`` is the far-sum kernel that takes the most time in the timed solves (at
+     4000 bodies the fused float64 traction + Stokeslet pass that ends each solve; HIP events
+     on the library stream around its launches), ``roofline_others`` the other far-sum
+     kernels of the same solves; ``cpu_baseline`` is the FP64 NumPy oracle's traction sum
+     on a sample of targets, threaded over the host's cores.
 --learned-experiment: paired learned-vs-block-diagonal iteration counts along a
 trajectory (train on the first steps, evaluate on the following ones).
 """
@@ -43,6 +45,18 @@ METRIC = "mobility solve time @1e-8 rel. residual (mixed+learned vs FP64); Gpair
 FP64_PEAK_TFLOPS = 78.6      # MI355X vector FP64
 FP32_PEAK_TFLOPS = 157.3     # MI355X vector FP32
 TRACTION_FLOPS_PER_PAIR = 30
+STOKESLET_FLOPS_PER_PAIR = 28
+# far-sum kernels of a solve: name, info fields (summed ms, launches), flops per pair, peak,
+# the sources their traffic record is tied to
+FAR_KERNELS = [
+    ("k_far_ts (float64 traction + Stokeslet)", "ms_fused", "n_fused",
+     TRACTION_FLOPS_PER_PAIR + STOKESLET_FLOPS_PER_PAIR, FP64_PEAK_TFLOPS,
+     ("k_far_fused.hip", "pair.h", "far_plan.h")),
+    ("k_far<double, traction>", "ms_traction", "n_traction", TRACTION_FLOPS_PER_PAIR, FP64_PEAK_TFLOPS,
+     ("k_far.hip", "pair.h", "far_plan.h")),
+    ("k_far<float, traction>", "ms_traction32", "n_traction32", TRACTION_FLOPS_PER_PAIR, FP32_PEAK_TFLOPS,
+     ("k_far.hip", "pair.h", "far_plan.h")),
+]
 
 # Per workload: near-singular upsampling order (0 = plain smooth rule), fast multipole order
 # of the inner far sums (0 = direct float32 sums) and RK4 steps of the training trajectory.
@@ -107,31 +121,55 @@ def _cpu_baseline(w, budget_s, threads):
                       f"sources ({pairs:.3e} pairs, {dt:.1f} s, NumPy in {threads} threads)"}
 
 
-def _kernel_source_hash():
-    """sha256 of the far-sum kernel's sources (the kernel file, its pair arithmetic and its
+def _kernel_source_hash(files=("k_far.hip", "pair.h", "far_plan.h")):
+    """sha256 of a far-sum kernel's sources (the kernel file, its pair arithmetic and its
     source-chunk plan)."""
     import hashlib
     h = hashlib.sha256()
-    for name in ("k_far.hip", "pair.h", "far_plan.h"):
+    for name in files:
         with open(os.path.join(ROOT, "paper_1606_07428_amd", "csrc", name), "rb") as f:
             h.update(f.read())
     return h.hexdigest()
 
 
-def _traffic(kernel, workload):
-    """HBM bytes per launch of `kernel` at `workload` from the committed counter
-    summary (FETCH_SIZE and WRITE_SIZE passes, scaled by the plain-copy calibration),
-    or None when no summary exists for the current kernel."""
-    path = os.path.join(ROOT, "profiles", f"traffic_{workload}.json")
-    try:
-        with open(path) as f:
-            t = json.load(f)
-    except (OSError, ValueError):
-        return None
-    if t.get("kernel") != kernel or t.get("source_sha256") != _kernel_source_hash():
-        return None
-    return {"bytes_per_launch": t["fetch_bytes"] + t["write_bytes"], "fetch_bytes": t["fetch_bytes"],
-            "write_bytes": t["write_bytes"], "source": os.path.basename(path)}
+def _traffic(kernel, workload, files):
+    """HBM bytes per launch of `kernel` at `workload` from a committed counter summary
+    (profiles/traffic_<workload>*.json: FETCH_SIZE and WRITE_SIZE passes, scaled by the
+    plain-copy calibration), or None when none exists for the kernel's current sources."""
+    import glob
+    want = _kernel_source_hash(files)
+    for path in sorted(glob.glob(os.path.join(ROOT, "profiles", f"traffic_{workload}*.json"))):
+        try:
+            with open(path) as f:
+                t = json.load(f)
+        except (OSError, ValueError):
+            continue
+        if t.get("kernel") == kernel and t.get("source_sha256") == want:
+            return {"bytes_per_launch": t["fetch_bytes"] + t["write_bytes"], "fetch_bytes": t["fetch_bytes"],
+                    "write_bytes": t["write_bytes"], "source": os.path.basename(path)}
+    return None
+
+
+def _rooflines(infl, ppl, workload):
+    """Achieved algorithmic FLOP/s of each far-sum kernel over the timed solves (HIP events
+    around its launches), largest total time first."""
+    out = []
+    for name, ms_key, n_key, fpp, peak, files in FAR_KERNELS:
+        if name.startswith("k_far<float") and infl[-1]["fmm_applies"]:
+            continue  # the inner sums ran as fast multipole evaluations, not this kernel
+        ms = sum(i[ms_key] for i in infl)
+        n = sum(i[n_key] for i in infl)
+        if n == 0:
+            continue
+        avg_s = ms / n / 1e3
+        achieved = fpp * ppl / avg_s / 1e12
+        traffic = _traffic(name, workload, files)
+        out.append({"bound": "alu", "kernel": name, "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
+                    "frac": achieved / peak, "traffic": traffic["bytes_per_launch"] if traffic else None,
+                    "traffic_detail": traffic, "launch_ms": avg_s * 1e3, "launches": n,
+                    "pairs_per_launch": ppl, "flops_per_pair": fpp, "total_ms": ms})
+    out.sort(key=lambda r: -r["total_ms"])
+    return out
 
 
 def _timed(torch, solver, FT, VW, steps, warmup):
@@ -264,13 +302,11 @@ def main_bench(args):
     ms_64 = dt64 / args.fp64_steps * 1e3
     pairs64 = inf64[-1]["far_pairs"]
     ppl = infl[-1]["pairs_per_launch"]
-    # roofline: the float64 traction launches of the timed learned solves
+    # rooflines of the far-sum kernels of the timed learned solves; the largest is the line's
+    rooflines = _rooflines(infl, ppl, args.workload)
     ms_trac = sum(i["ms_traction"] for i in infl)
     n_trac = sum(i["n_traction"] for i in infl)
     trac_avg_s = ms_trac / max(n_trac, 1) / 1e3
-    achieved = TRACTION_FLOPS_PER_PAIR * ppl / trac_avg_s / 1e12
-    kernel = "k_far<double, traction>"
-    traffic = _traffic(kernel, args.workload)
     vscale = np.abs(VW64).max()
     solve = {"fp64_solve_far_pairs": pairs64, "pairs_per_launch": ppl}
     solve.update(_form_record("mixed_learned", dtl, infl, args.steps, args.warmup))
@@ -312,13 +348,8 @@ def main_bench(args):
                    "near_singular_order": p_up,
                    "value": "off-body pairs of the float64 solve / time of the step",
                    "state": f"after {args.train_steps} RK4 steps (trained on their stage solves)"},
-        "roofline": {"bound": "alu", "kernel": kernel,
-                     "achieved": achieved, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / FP64_PEAK_TFLOPS,
-                     "traffic": traffic["bytes_per_launch"] if traffic else None,
-                     "traffic_detail": traffic,
-                     "launch_ms": trac_avg_s * 1e3, "launches": n_trac, "pairs_per_launch": ppl,
-                     "flops_per_pair": TRACTION_FLOPS_PER_PAIR},
+        "roofline": rooflines[0] if rooflines else None,
+        "roofline_others": rooflines[1:],
         "solve": solve,
         "learned": learned,
     }
