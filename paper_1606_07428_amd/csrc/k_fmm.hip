@@ -285,18 +285,49 @@ __device__ __forceinline__ void tri_inv(int c, int& n, int& m) {
   m = c - tri(n, 0);
 }
 
-constexpr int kP2mChunk = 16;
+// Column m (n = m..P) of conj(R_n^m(x, y, z)) into out[tri(n, m)]: the recurrences of
+// regular_table for one m, in the same order, so the entries are the same.
+template <typename T>
+__device__ void regular_column(int P, int m, T x, T y, T z, Cx<T>* out) {
+  const T r2 = x * x + y * y + z * z;
+  T dre = 1, dim = 0;
+  for (int k = 1; k <= m; ++k) {
+    const T inv = T(1) / T(2 * k);
+    const T nre = (dre * x - dim * y) * inv, nim = (dre * y + dim * x) * inv;
+    dre = nre;
+    dim = nim;
+  }
+  out[tri(m, m)] = Cx<T>{dre, -dim};
+  if (m + 1 > P) return;
+  T are = dre, aim = dim;
+  T bre = z * dre, bim = z * dim;
+  out[tri(m + 1, m)] = Cx<T>{bre, -bim};
+  for (int n = m + 2; n <= P; ++n) {
+    const T c1 = T(2 * n - 1), inv = T(1) / T((n - m) * (n + m));
+    const T vre = (c1 * z * bre - r2 * are) * inv, vim = (c1 * z * bim - r2 * aim) * inv;
+    are = bre; aim = bim;
+    bre = vre; bim = vim;
+    out[tri(n, m)] = Cx<T>{vre, -vim};
+  }
+}
+
+// points per P2M chunk (the chunk's tables fill 39 KB of LDS in either precision)
+template <typename T> struct P2mChunk { static constexpr int v = sizeof(T) == 8 ? 16 : 32; };
 
 // Leaf multipoles: M_d[c] = sum_p charge_d(p) conj(R_c(y_p - centre)), charges
 // (q_x, q_y, q_z, (y - centre).q), sources in leaf order.  One workgroup per leaf, 4 Kc
-// threads (one output each, density fastest).
+// threads (one output each, density fastest).  The regular tables of a chunk of points
+// are built one (point, m) column per thread, then every output sums over the chunk in
+// point order.
 template <typename T>
 __global__ void __launch_bounds__(1024) k_fmm_p2m(int P, int nb, double lox, double loy, double loz, double w,
                                                   const int* __restrict__ start, const int* __restrict__ perm,
                                                   const double4* __restrict__ Xs, const Src8<T>* __restrict__ src,
                                                   Cx<T>* __restrict__ Mout) {
-  __shared__ Cx<T> Rt[kP2mChunk][kFmmKc];
-  __shared__ T ch[kP2mChunk][4];
+  constexpr int CH = P2mChunk<T>::v;
+  __shared__ Cx<T> Rt[CH][kFmmKc];
+  __shared__ T ch[CH][4];
+  __shared__ T sp[CH][3];
   const int b = blockIdx.x;
   const int Kc = tri(P + 1, 0);
   const int i = b % nb, j = (b / nb) % nb, k = b / (nb * nb);
@@ -306,8 +337,8 @@ __global__ void __launch_bounds__(1024) k_fmm_p2m(int P, int nb, double lox, dou
   const int d = o & 3, c = min(o >> 2, Kc - 1);
   const bool live = o < 4 * Kc;
   Cx<T> acc{0, 0};
-  for (int base = 0; base < n; base += kP2mChunk) {
-    const int cnt = min(kP2mChunk, n - base);
+  for (int base = 0; base < n; base += CH) {
+    const int cnt = min(CH, n - base);
     if (o < cnt) {
       const int p = s0 + base + o;
       const double4 x = Xs[p];
@@ -317,7 +348,14 @@ __global__ void __launch_bounds__(1024) k_fmm_p2m(int P, int nb, double lox, dou
       ch[o][1] = s.v[4];
       ch[o][2] = s.v[5];
       ch[o][3] = sx * s.v[3] + sy * s.v[4] + sz * s.v[5];
-      regular_table<T, T>(P, sx, sy, sz, Rt[o], true);
+      sp[o][0] = sx;
+      sp[o][1] = sy;
+      sp[o][2] = sz;
+    }
+    __syncthreads();
+    for (int t = o; t < cnt * (P + 1); t += blockDim.x) {
+      const int q = t / (P + 1), m = t - q * (P + 1);
+      regular_column<T>(P, m, sp[q][0], sp[q][1], sp[q][2], Rt[q]);
     }
     __syncthreads();
     if (live)
