@@ -383,20 +383,26 @@ const void* rbm_debug_ptr(rbm_ctx* ctx, const char* name);
  * rbm_debug_ptr) to the host buffer dst (synchronous). */
 rbm_status rbm_debug_read(rbm_ctx* ctx, const char* name, size_t offset, size_t bytes, void* dst);
 
-/* Low-level kernels behind the solve, exposed for parity tests and benchmarks
- * (all device pointers, on the context stream):
+/* Low-level kernels behind the solve, exposed for parity tests and benchmarks.  For the
+ * three context calls below: X, Nrm, q, add, y, u are device pointers to float64 arrays
+ * [3][n_points] (component-major); every point is both a target and a source, and the body
+ * of point k is k / M, so the last body may hold fewer than M points; pairs on one body are
+ * left out.  precision 0 = float64, 1 = float32 arithmetic (inputs and outputs stay float64).
+ * Errors: RBM_E_INVAL for a null pointer (add aside), n_points < 1, M < 1 or a precision
+ * other than 0 and 1; RBM_E_NOMEM before rbm_bind_workspace or for more than n_bodies_max * M
+ * points of the bound workspace.  They use the workspace's scratch, so they must not
+ * overlap a solve on the same context.
  *
- * rbm_far_traction: y[3][n_t] = add[3][n_t] (may be NULL) + sum over sources b
- *   not on the target's body of -(3/4pi) d (d.N_a)(d.q_b)/|d|^5, d = X_a - X_b
- *   (traction of the Stokeslet sum, §2.1, §3.1).  Targets X[3][n_t], N[3][n_t];
- *   sources X[3][n_s] with strengths q[3][n_s]; body of point k is k / M.
- *   precision 0 = float64, 1 = float32 arithmetic (inputs/outputs float64). */
+ * rbm_far_traction: y = add (may be NULL) + sum over sources b not on the target's body of
+ *   -(3/4pi) d (d.N_a)(d.q_b)/|d|^5, d = X_a - X_b (traction of the Stokeslet sum, §2.1,
+ *   §3.1).  Issued on the context stream; returns without waiting. */
 rbm_status rbm_far_traction(rbm_ctx* ctx, int n_points, int M, const double* X,
                             const double* Nrm, const double* q, const double* add,
                             double* y, int precision);
 
-/* rbm_far_stokeslet: u[3][n] = sum over sources b not on the target's body of
- * (1/(8 pi eta)) [q_b/|d| + d (d.q_b)/|d|^3]  (Stokeslet of §2.1). */
+/* rbm_far_stokeslet: u = sum over sources b not on the target's body of
+ *   (1/(8 pi eta)) [q_b/|d| + d (d.q_b)/|d|^3]  (Stokeslet of §2.1).  Issued on the context
+ *   stream; returns without waiting. */
 rbm_status rbm_far_stokeslet(rbm_ctx* ctx, int n_points, int M, const double* X,
                              const double* q, double* u, int precision);
 

@@ -1673,6 +1673,7 @@ extern "C" rbm_status rbm_far_traction(rbm_ctx* c, int n_points, int M, const do
                                        const double* Nrm, const double* q, const double* add,
                                        double* y, int precision) {
   if (!c || !X || !Nrm || !q || !y) return fail(RBM_E_INVAL, "null argument");
+  if (precision != 0 && precision != 1) return fail(RBM_E_INVAL, "precision must be 0 or 1");
   if (!c->ws) return fail(RBM_E_NOMEM, "bind a workspace first");
   if (n_points < 1 || M < 1) return fail(RBM_E_INVAL, "sizes must be >= 1");
   if (n_points > c->nmax * c->M) return fail(RBM_E_NOMEM, "more points than the workspace holds");
@@ -1697,6 +1698,7 @@ extern "C" rbm_status rbm_far_traction_fmm(rbm_ctx* c, int n_points, int M, cons
                                            const double* Nrm, const double* q, double d_max, double* y,
                                            int precision, int* level) {
   if (!c || !X || !Nrm || !q || !y) return fail(RBM_E_INVAL, "null argument");
+  if (precision != 0 && precision != 1) return fail(RBM_E_INVAL, "precision must be 0 or 1");
   if (!c->ws) return fail(RBM_E_NOMEM, "bind a workspace first");
   if (c->opt.fmm_order <= 0) return fail(RBM_E_STATE, "create the context with options.fmm_order > 0");
   if (n_points < 1 || M < 1) return fail(RBM_E_INVAL, "sizes must be >= 1");
@@ -1720,6 +1722,7 @@ extern "C" rbm_status rbm_far_traction_fmm(rbm_ctx* c, int n_points, int M, cons
 extern "C" rbm_status rbm_far_stokeslet(rbm_ctx* c, int n_points, int M, const double* X,
                                         const double* q, double* u, int precision) {
   if (!c || !X || !q || !u) return fail(RBM_E_INVAL, "null argument");
+  if (precision != 0 && precision != 1) return fail(RBM_E_INVAL, "precision must be 0 or 1");
   if (!c->ws) return fail(RBM_E_NOMEM, "bind a workspace first");
   if (n_points < 1 || M < 1) return fail(RBM_E_INVAL, "sizes must be >= 1");
   if (n_points > c->nmax * c->M) return fail(RBM_E_NOMEM, "more points than the workspace holds");

@@ -83,6 +83,15 @@ static void host_checks() {
   unsigned char junk[64];
   std::memset(junk, 0x5a, sizeof junk);
   EXPECT(rbm_set_state(c, junk, sizeof junk) != RBM_OK, "junk state record refused");
+  // low-level sums: argument checks come before the workspace check, and without a
+  // workspace the call stops there (the pointers below are never dereferenced)
+  const double* h = FT;
+  double* o6 = VW;
+  EXPECT(rbm_far_traction(c, 2, 1, h, h, nullptr, nullptr, o6, 0) == RBM_E_INVAL, "null strengths refused");
+  EXPECT(rbm_far_traction(c, 2, 1, h, h, h, nullptr, o6, 2) == RBM_E_INVAL, "sum precision 2 refused");
+  EXPECT(rbm_far_stokeslet(c, 2, 1, h, h, o6, -1) == RBM_E_INVAL, "Stokeslet precision -1 refused");
+  EXPECT(rbm_far_traction(c, 2, 1, h, h, h, nullptr, o6, 0) == RBM_E_NOMEM, "sum before a workspace refused");
+  EXPECT(rbm_far_stokeslet(c, 2, 1, h, h, o6, 1) == RBM_E_NOMEM, "Stokeslet before a workspace refused");
   EXPECT(std::strlen(rbm_last_error()) > 0, "error message set");
   rbm_destroy(c);
 }

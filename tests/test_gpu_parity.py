@@ -67,6 +67,45 @@ def test_far_sums_match_oracle(n_points, M, prec):
     s.close()
 
 
+@pytest.mark.parametrize("prec", [0, 1])
+def test_far_sums_degenerate_cases(prec):
+    """Cases the all-pairs sum must get right beyond the tiles: every point on one body (a full
+    body and a ragged one shorter than M), where no pair survives and the sums are add and
+    zero exactly; two one-point bodies, where each sum is the single pair term of §2.1 written
+    out here; and a precision the calls do not know."""
+    _case(f"far sums, degenerate cases, precision={prec}")
+    rng = np.random.default_rng(11)
+    for n, M in [(84, 84), (37, 84)]:
+        X, Nn, q, add = (rng.standard_normal((3, n)) for _ in range(4))
+        s = _sum_solver(n, M)
+        y = s.far_traction(_dev(X), _dev(Nn), _dev(q), M, add=_dev(add), precision=prec)
+        u = s.far_stokeslet(_dev(X), _dev(q), M, precision=prec)
+        ys = rbm.far_traction_static(_dev(X), _dev(Nn), _dev(q), M, add=_dev(add), precision=prec)
+        torch.cuda.synchronize()
+        assert np.array_equal(y.cpu().numpy(), add) and np.array_equal(ys.cpu().numpy(), add)
+        assert not u.cpu().numpy().any()
+        s.close()
+    # two bodies of one point each
+    X = np.array([[0.3, -0.9], [0.2, 0.4], [-0.5, 0.7]])
+    Nn = np.array([[0.6, 0.0], [0.0, 0.8], [0.8, 0.6]])
+    q = np.array([[1.5, -0.4], [0.3, 0.9], [-0.7, 0.2]])
+    s = _sum_solver(2, 1)
+    y = s.far_traction(_dev(X), _dev(Nn), _dev(q), 1, precision=prec).cpu().numpy()
+    u = s.far_stokeslet(_dev(X), _dev(q), 1, precision=prec).cpu().numpy()
+    for a, b in [(0, 1), (1, 0)]:
+        d = X[:, a] - X[:, b]
+        r = np.sqrt(d @ d)
+        t = -3.0 / (4 * math.pi) * d * (d @ Nn[:, a]) * (d @ q[:, b]) / r ** 5
+        v = (q[:, b] / r + d * (d @ q[:, b]) / r ** 3) / (8 * math.pi)
+        tol = 1e-14 if prec == 0 else 1e-6
+        assert np.abs(y[:, a] - t).max() <= tol * np.abs(t).max()
+        assert np.abs(u[:, a] - v).max() <= tol * np.abs(v).max()
+    with pytest.raises(rbm.RbmError) as e:
+        s.far_traction(_dev(X), _dev(Nn), _dev(q), 1, precision=2)
+    assert e.value.status == rbm.RBM_E_INVAL
+    s.close()
+
+
 def _body_frame_ops(shape):
     ops = shape.ops
     A0 = 0.5 * np.eye(ops["K"].shape[0]) + ops["K"] + sg.L_operator(shape.geom)
