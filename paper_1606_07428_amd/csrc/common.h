@@ -18,6 +18,23 @@ __host__ __device__ inline int band_index(int l, int m, int p) {
   return p * p + (m + p - 1);
 }
 
+// Rotated-node chunk of the singular-quadrature kernels (k_singular, k_singular_laplace):
+// the largest of 64, 48 and 32 nodes whose LDS lets two workgroups share a CU's 160 KB,
+// else 32 (one workgroup per CU).  With two resident workgroups one's node sweep, which
+// runs on a single wave, overlaps the other's contraction.  LDS per workgroup in doubles:
+// coefficients 3 (p+1)^2, staged harmonics nB (NC+1) (odd row stride), nkw kernel weights
+// per node, the Legendre table.
+inline size_t singular_lds_bytes(int p, int nc_nodes, int nkw) {
+  const size_t nc = (size_t)(p + 1) * (p + 1), nB = (size_t)p * p + 2 * p;
+  return (3 * nc + nB * (nc_nodes + 1) + (size_t)nkw * nc_nodes + 2 * nc + 2 * (p + 1)) * sizeof(double);
+}
+inline int singular_chunk(int p, int nkw) {
+  constexpr size_t kLdsPerCu = 160 * 1024;
+  for (int n : {64, 48})
+    if (2 * singular_lds_bytes(p, n, nkw) <= kLdsPerCu) return n;
+  return 32;
+}
+
 // Sweep over the normalized associated Legendre functions N_lm P_l^m(x) (no
 // Condon-Shortley phase), 0 <= m <= l <= L, with x = cos(theta), s = sin(theta) >= 0.
 // For every (l, m) it calls f(l, m, P, Q, D) with Q = P / sin(theta) (pole regular,

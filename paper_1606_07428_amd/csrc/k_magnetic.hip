@@ -28,12 +28,16 @@ __global__ __launch_bounds__(256) void k_singular_laplace(int p, int ps,
                                                           double* __restrict__ SL,
                                                           double* __restrict__ KL) {
   extern __shared__ double lds[];
+  // row stride of the staged harmonics: odd, so that the contraction, whose lanes
+  // read one row each at the same column, hits distinct LDS banks (a stride of 64
+  // doubles put every lane in one bank)
+  constexpr int YS = NC + 1;
   const int M = (p + 1) * 2 * p, nc = (p + 1) * (p + 1), nB = p * p + 2 * p;
   const int Ms = (ps + 1) * 2 * ps;
   const int t = blockIdx.x, s = blockIdx.y, tid = threadIdx.x;
   double* cf = lds;             // [3][nc]
-  double* Ych = cf + 3 * nc;    // [nB][NC]
-  double* Kw = Ych + nB * NC;   // [2][NC]
+  double* Ych = cf + 3 * nc;    // [nB][YS]
+  double* Kw = Ych + nB * YS;   // [2][NC]
   double* ltab = Kw + 2 * NC;   // Legendre recurrence coefficients
   for (int i = tid; i < 3 * nc; i += 256) cf[i] = coef_all[(size_t)s * 3 * nc + i];
   legendre_table(p, ltab, tid, 256);
@@ -67,7 +71,7 @@ __global__ __launch_bounds__(256) void k_singular_laplace(int p, int ps,
               x[c] += cf[c * nc + i0] * P;
               dt[c] += cf[c * nc + i0] * D;
             }
-            Ych[band_index(l, 0, p) * NC + tid] = P;
+            Ych[band_index(l, 0, p) * YS + tid] = P;
             return;
           }
           if (m != cur_m) {
@@ -82,9 +86,9 @@ __global__ __launch_bounds__(256) void k_singular_laplace(int p, int ps,
             dt[c] += r2 * D * (ap * cm + am * sm);
             dp[c] += r2 * m * Qv * (am * cm - ap * sm);
           }
-          Ych[band_index(l, m, p) * NC + tid] = yp;
+          Ych[band_index(l, m, p) * YS + tid] = yp;
           const int bm = band_index(l, -m, p);
-          if (bm >= 0) Ych[bm * NC + tid] = ym;
+          if (bm >= 0) Ych[bm * YS + tid] = ym;
         }, ltab);
         const double c0 = dt[1] * dp[2] - dt[2] * dp[1];
         const double c1 = dt[2] * dp[0] - dt[0] * dp[2];
@@ -96,19 +100,19 @@ __global__ __launch_bounds__(256) void k_singular_laplace(int p, int ps,
         Kw[NC + tid] = -w * c4 * (r0 * nt0 + r1 * nt1 + r2v * nt2) * di * di * di;
       } else {
         Kw[tid] = Kw[NC + tid] = 0.0;
-        for (int b = 0; b < nB; ++b) Ych[b * NC + tid] = 0.0;
+        for (int b = 0; b < nB; ++b) Ych[b * YS + tid] = 0.0;
       }
     }
     __syncthreads();
     if (tid < nB)
       for (int q = 0; q < NC; ++q) {
-        const double y = Ych[tid * NC + q];
+        const double y = Ych[tid * YS + q];
         acc0[0] += Kw[q] * y;
         acc0[1] += Kw[NC + q] * y;
       }
     if (tid + 256 < nB)
       for (int q = 0; q < NC; ++q) {
-        const double y = Ych[(tid + 256) * NC + q];
+        const double y = Ych[(tid + 256) * YS + q];
         acc1[0] += Kw[q] * y;
         acc1[1] += Kw[NC + q] * y;
       }
@@ -276,24 +280,19 @@ hipError_t launch_singular_laplace(int ns, int p, int ps, const double* coef, co
                                    const double* gn, const double* node_th, const double* node_ph,
                                    const double* rnodes, const double* rW, const double* Fttab,
                                    double* SL, double* KL, hipStream_t st) {
-  const int M = (p + 1) * 2 * p, nc = (p + 1) * (p + 1), nB = p * p + 2 * p;
+  const int M = (p + 1) * 2 * p;
   dim3 grid(M, ns);
-  const size_t ltab = (size_t)(2 * nc + 2 * (p + 1));
-  const size_t lds64 = (size_t)(3 * nc + nB * 64 + 2 * 64 + ltab) * sizeof(double);
-  if (lds64 <= 150 * 1024) {
-    hipError_t e = hipFuncSetAttribute((const void*)k_singular_laplace<64>,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds64);
+  const int nodes = singular_chunk(p, 2);
+  const size_t lds = singular_lds_bytes(p, nodes, 2);
+  auto run = [&](auto kern) {
+    hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
-    k_singular_laplace<64><<<grid, 256, lds64, st>>>(p, ps, coef, gx, gn, node_th, node_ph, rnodes,
-                                                     rW, Fttab, SL, KL);
-  } else {
-    const size_t lds32 = (size_t)(3 * nc + nB * 32 + 2 * 32 + ltab) * sizeof(double);
-    hipError_t e = hipFuncSetAttribute((const void*)k_singular_laplace<32>,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds32);
-    if (e != hipSuccess) return e;
-    k_singular_laplace<32><<<grid, 256, lds32, st>>>(p, ps, coef, gx, gn, node_th, node_ph, rnodes,
-                                                     rW, Fttab, SL, KL);
-  }
+    kern<<<grid, 256, lds, st>>>(p, ps, coef, gx, gn, node_th, node_ph, rnodes, rW, Fttab, SL, KL);
+    return hipSuccess;
+  };
+  hipError_t e = nodes == 64 ? run(k_singular_laplace<64>) : nodes == 48 ? run(k_singular_laplace<48>)
+                             : run(k_singular_laplace<32>);
+  if (e != hipSuccess) return e;
   return hipGetLastError();
 }
 

@@ -287,12 +287,16 @@ __global__ __launch_bounds__(256) void k_singular(int p, int ps, double eta,
                                                   double* __restrict__ Sop,
                                                   double* __restrict__ Kop) {
   extern __shared__ double lds[];
+  // row stride of the staged harmonics: odd, so that the contraction, whose lanes
+  // read one row each at the same column, hits distinct LDS banks (a stride of 64
+  // doubles put every lane in one bank)
+  constexpr int YS = NC + 1;
   const int M = (p + 1) * 2 * p, M3 = 3 * M, nc = (p + 1) * (p + 1), nB = p * p + 2 * p;
   const int Ms = (ps + 1) * 2 * ps;
   const int t = blockIdx.x, s = blockIdx.y, tid = threadIdx.x;
   double* cf = lds;             // [3][nc]
-  double* Ych = cf + 3 * nc;    // [nB][NC]
-  double* Kw = Ych + nB * NC;   // [12][NC]
+  double* Ych = cf + 3 * nc;    // [nB][YS]
+  double* Kw = Ych + nB * YS;   // [12][NC]
   double* ltab = Kw + 12 * NC;  // Legendre recurrence coefficients
   for (int i = tid; i < 3 * nc; i += 256) cf[i] = coef_all[(size_t)s * 3 * nc + i];
   legendre_table(p, ltab, tid, 256);
@@ -331,7 +335,7 @@ __global__ __launch_bounds__(256) void k_singular(int p, int ps, double eta,
               x[c] += a * P;
               dt[c] += a * D;
             }
-            Ych[band_index(l, 0, p) * NC + tid] = P;
+            Ych[band_index(l, 0, p) * YS + tid] = P;
             return;
           }
           if (m != cur_m) {
@@ -348,9 +352,9 @@ __global__ __launch_bounds__(256) void k_singular(int p, int ps, double eta,
             dt[c] += ap * tp + am * tm;
             dp[c] += ap * pp + am * pm;
           }
-          Ych[band_index(l, m, p) * NC + tid] = yp;
+          Ych[band_index(l, m, p) * YS + tid] = yp;
           const int bm = band_index(l, -m, p);
-          if (bm >= 0) Ych[bm * NC + tid] = ym;
+          if (bm >= 0) Ych[bm * YS + tid] = ym;
         }, ltab);
         const double c0 = dt[1] * dp[2] - dt[2] * dp[1];
         const double c1 = dt[2] * dp[0] - dt[0] * dp[2];
@@ -378,27 +382,27 @@ __global__ __launch_bounds__(256) void k_singular(int p, int ps, double eta,
         Kw[11 * NC + tid] = wk * r1 * r2v;
       } else {
         for (int k = 0; k < 12; ++k) Kw[k * NC + tid] = 0.0;
-        for (int b = 0; b < nB; ++b) Ych[b * NC + tid] = 0.0;
+        for (int b = 0; b < nB; ++b) Ych[b * YS + tid] = 0.0;
       }
     }
     __syncthreads();
     if (tid < nB) {
       for (int q = 0; q < NC; ++q) {
-        const double y = Ych[tid * NC + q];
+        const double y = Ych[tid * YS + q];
 #pragma unroll
         for (int k = 0; k < 12; ++k) acc0[k] += Kw[k * NC + q] * y;
       }
     }
     if (tid + 256 < nB) {
       for (int q = 0; q < NC; ++q) {
-        const double y = Ych[(tid + 256) * NC + q];
+        const double y = Ych[(tid + 256) * YS + q];
 #pragma unroll
         for (int k = 0; k < 12; ++k) acc1[k] += Kw[k * NC + q] * y;
       }
     }
   }
   __syncthreads();
-  double* Cs = Ych;  // [12][nB], fits since NC >= 12
+  double* Cs = Ych;  // [12][nB], fits since YS >= 12
   if (tid < nB)
     for (int k = 0; k < 12; ++k) Cs[k * nB + tid] = acc0[k];
   if (tid + 256 < nB)
@@ -434,24 +438,18 @@ hipError_t launch_singular_assemble(int ns, int p, int ps, double eta, const dou
                                     const double* gx, const double* gn, const double* node_th,
                                     const double* node_ph, const double* rnodes, const double* rW,
                                     const double* Fttab, double* Sop, double* Kop, hipStream_t st) {
-  const int M = (p + 1) * 2 * p, nc = (p + 1) * (p + 1), nB = p * p + 2 * p;
+  const int M = (p + 1) * 2 * p;
   dim3 grid(M, ns);
-  const size_t ltab = (size_t)(2 * nc + 2 * (p + 1));
-  const size_t lds64 = (size_t)(3 * nc + nB * 64 + 12 * 64 + ltab) * sizeof(double);
-  if (lds64 <= 150 * 1024) {
-    hipError_t e = hipFuncSetAttribute((const void*)k_singular<64>,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds64);
+  const int nodes = singular_chunk(p, 12);
+  const size_t lds = singular_lds_bytes(p, nodes, 12);
+  auto run = [&](auto kern) {
+    hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
-    k_singular<64><<<grid, 256, lds64, st>>>(p, ps, eta, coef, gx, gn, node_th, node_ph, rnodes,
-                                             rW, Fttab, Sop, Kop);
-  } else {
-    const size_t lds32 = (size_t)(3 * nc + nB * 32 + 12 * 32 + ltab) * sizeof(double);
-    hipError_t e = hipFuncSetAttribute((const void*)k_singular<32>,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds32);
-    if (e != hipSuccess) return e;
-    k_singular<32><<<grid, 256, lds32, st>>>(p, ps, eta, coef, gx, gn, node_th, node_ph, rnodes,
-                                             rW, Fttab, Sop, Kop);
-  }
+    kern<<<grid, 256, lds, st>>>(p, ps, eta, coef, gx, gn, node_th, node_ph, rnodes, rW, Fttab, Sop, Kop);
+    return hipSuccess;
+  };
+  hipError_t e = nodes == 64 ? run(k_singular<64>) : nodes == 48 ? run(k_singular<48>) : run(k_singular<32>);
+  if (e != hipSuccess) return e;
   return hipGetLastError();
 }
 
