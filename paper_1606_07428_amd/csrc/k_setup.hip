@@ -267,15 +267,22 @@ hipError_t launch_shape_geometry(int ns, int p, const double* coef, const double
 }
 
 // Singular self operators by grid rotation (§3 and the rule of Gimbutas-Veerapaneni
-// cited there).  One workgroup per (target node t, shape s).  For the rotated nodes
-// s_q = Q_t s'_q, Q_t = R_z(phi_t) R_y(theta_t):
+// cited there).  For the rotated nodes s_q = Q_t s'_q, Q_t = R_z(phi_t) R_y(theta_t):
 //   C[k][b] = sum_q W_q J(s_q) kern_k(x_t, x(s_q)) Y_b(s_q)         (b in B_p)
 //   row(t)  = C F                                                     (F: grid -> B_p)
 // kern = Stokeslet/eta (S) and n_t . T (K); both 3x3 symmetric (6 entries each).
 // Outputs are column-major body-frame (3M x 3M) operators: entry (row=c*M+t,
 // col=c'*M+a) at [col*3M + row].
-template <int NC>
-__global__ __launch_bounds__(256) void k_singular(int p, int ps, double eta,
+//
+// One workgroup per (target node t, group of G consecutive shapes).  The rotated nodes
+// and their harmonics Y_b(s_q) depend on t alone, so the shapes of a group share them.
+// Per chunk of NC rotated nodes, lane group g (NC lanes) runs the Legendre recurrence
+// at each node for shape g's surface there (position, tangents, kernel weights), lane
+// group 0 also stages the harmonics in LDS, and then thread b contracts them with the
+// weights of every shape of the group.  Finally C of each shape goes to LDS and the
+// threads form row(t) of its operators.
+template <int NC, int G>
+__global__ __launch_bounds__(256, 2) void k_singular(int ns, int p, int ps, double eta,
                                                   const double* __restrict__ coef_all,
                                                   const double* __restrict__ gx_all,
                                                   const double* __restrict__ gn_all,
@@ -286,6 +293,7 @@ __global__ __launch_bounds__(256) void k_singular(int p, int ps, double eta,
                                                   const double* __restrict__ Ft,
                                                   double* __restrict__ Sop,
                                                   double* __restrict__ Kop) {
+  static_assert(NC * G <= 256, "one lane per (node, shape)");
   extern __shared__ double lds[];
   // row stride of the staged harmonics: odd, so that the contraction, whose lanes
   // read one row each at the same column, hits distinct LDS banks (a stride of 64
@@ -293,49 +301,65 @@ __global__ __launch_bounds__(256) void k_singular(int p, int ps, double eta,
   constexpr int YS = NC + 1;
   const int M = (p + 1) * 2 * p, M3 = 3 * M, nc = (p + 1) * (p + 1), nB = p * p + 2 * p;
   const int Ms = (ps + 1) * 2 * ps;
-  const int t = blockIdx.x, s = blockIdx.y, tid = threadIdx.x;
-  double* cf = lds;             // [3][nc]
-  double* Ych = cf + 3 * nc;    // [nB][YS]
-  double* Kw = Ych + nB * YS;   // [12][NC]
-  double* ltab = Kw + 12 * NC;  // Legendre recurrence coefficients
-  for (int i = tid; i < 3 * nc; i += 256) cf[i] = coef_all[(size_t)s * 3 * nc + i];
+  const int t = blockIdx.x, s0 = blockIdx.y * G, tid = threadIdx.x;
+  const int ng = min(G, ns - s0);  // shapes in this group
+  double* cf = lds;                  // [G][3][nc]
+  double* Ych = cf + G * 3 * nc;     // [nB][YS]
+  double* Kw = Ych + nB * YS;        // [G][12][NC]
+  double* ltab = Kw + G * 12 * NC;   // Legendre recurrence coefficients
+  for (int i = tid; i < G * 3 * nc; i += 256)
+    cf[i] = i < ng * 3 * nc ? coef_all[(size_t)s0 * 3 * nc + i] : 0.0;
   legendre_table(p, ltab, tid, 256);
   double st, ct, sp, cp;
   sincos(nth[t], &st, &ct);
   sincos(nph[t], &sp, &cp);
   const double Q[9] = {cp * ct, -sp, cp * st, sp * ct, cp, sp * st, -st, 0.0, ct};
-  const double* gx = gx_all + (size_t)s * 3 * M;
-  const double* gn = gn_all + (size_t)s * 3 * M;
-  const double xt0 = gx[t], xt1 = gx[M + t], xt2 = gx[2 * M + t];
-  const double nt0 = gn[t], nt1 = gn[M + t], nt2 = gn[2 * M + t];
+  // lane (node, g) of the sweep: its shape's target point and normal
+  const int node = tid % NC, g = tid / NC;
+  const bool sweeper = tid < NC * G;
+  const bool live = sweeper && g < ng;
+  double xt0 = 0, xt1 = 0, xt2 = 0, nt0 = 0, nt1 = 0, nt2 = 0;
+  if (live) {
+    const double* gx = gx_all + (size_t)(s0 + g) * 3 * M;
+    const double* gn = gn_all + (size_t)(s0 + g) * 3 * M;
+    xt0 = gx[t], xt1 = gx[M + t], xt2 = gx[2 * M + t];
+    nt0 = gn[t], nt1 = gn[M + t], nt2 = gn[2 * M + t];
+  }
+  const double* cfg = cf + (sweeper ? g : 0) * 3 * nc;
+  double* Kwg = Kw + (sweeper ? g : 0) * 12 * NC;
   const double cS = 1.0 / (8.0 * RBM_PI * eta);
   const double cK = -3.0 / (4.0 * RBM_PI);
-  double acc0[12], acc1[12];
-  for (int k = 0; k < 12; ++k) acc0[k] = acc1[k] = 0.0;
+  double acc0[G][12], acc1[12];
+#pragma unroll
+  for (int gg = 0; gg < G; ++gg)
+#pragma unroll
+    for (int k = 0; k < 12; ++k) acc0[gg][k] = 0.0;
+  for (int k = 0; k < 12; ++k) acc1[k] = 0.0;
   for (int chunk = 0; chunk < Ms; chunk += NC) {
     __syncthreads();
-    if (tid < NC) {
-      const int q = chunk + tid;
+    if (sweeper) {
+      const int q = chunk + node;
       if (q < Ms) {
-        const double s0 = rnodes[q], s1 = rnodes[Ms + q], s2 = rnodes[2 * Ms + q];
-        const double v0 = Q[0] * s0 + Q[1] * s1 + Q[2] * s2;
-        const double v1 = Q[3] * s0 + Q[4] * s1 + Q[5] * s2;
-        const double v2 = Q[6] * s0 + Q[7] * s1 + Q[8] * s2;
+        const double s0n = rnodes[q], s1n = rnodes[Ms + q], s2n = rnodes[2 * Ms + q];
+        const double v0 = Q[0] * s0n + Q[1] * s1n + Q[2] * s2n;
+        const double v1 = Q[3] * s0n + Q[4] * s1n + Q[5] * s2n;
+        const double v2 = Q[6] * s0n + Q[7] * s1n + Q[8] * s2n;
         const double sx = sqrt(v0 * v0 + v1 * v1);   // sin(theta) of the rotated node
         const double cx = v2;                        // cos(theta)
         const double ph = atan2(v1, v0);
         double x[3] = {0, 0, 0}, dt[3] = {0, 0, 0}, dp[3] = {0, 0, 0};
         int cur_m = -1;
         double cm = 1.0, sm = 0.0;
+        const bool stage = g == 0;
         legendre_sweep(p, cx, sx, [&](int l, int m, double P, double Qv, double D) {
           const int i0 = l * l + l;
           if (m == 0) {
             for (int c = 0; c < 3; ++c) {
-              const double a = cf[c * nc + i0];
+              const double a = cfg[c * nc + i0];
               x[c] += a * P;
               dt[c] += a * D;
             }
-            Ych[band_index(l, 0, p) * YS + tid] = P;
+            if (stage) Ych[band_index(l, 0, p) * YS + node] = P;
             return;
           }
           if (m != cur_m) {
@@ -347,42 +371,49 @@ __global__ __launch_bounds__(256) void k_singular(int p, int ps, double eta,
           const double tp = r2 * D * cm, tm = r2 * D * sm;
           const double pp = -r2 * m * Qv * sm, pm = r2 * m * Qv * cm;
           for (int c = 0; c < 3; ++c) {
-            const double ap = cf[c * nc + i0 + m], am = cf[c * nc + i0 - m];
+            const double ap = cfg[c * nc + i0 + m], am = cfg[c * nc + i0 - m];
             x[c] += ap * yp + am * ym;
             dt[c] += ap * tp + am * tm;
             dp[c] += ap * pp + am * pm;
           }
-          Ych[band_index(l, m, p) * YS + tid] = yp;
-          const int bm = band_index(l, -m, p);
-          if (bm >= 0) Ych[bm * YS + tid] = ym;
+          if (stage) {
+            Ych[band_index(l, m, p) * YS + node] = yp;
+            const int bm = band_index(l, -m, p);
+            if (bm >= 0) Ych[bm * YS + node] = ym;
+          }
         }, ltab);
-        const double c0 = dt[1] * dp[2] - dt[2] * dp[1];
-        const double c1 = dt[2] * dp[0] - dt[0] * dp[2];
-        const double c2 = dt[0] * dp[1] - dt[1] * dp[0];
-        const double J = sqrt(c0 * c0 + c1 * c1 + c2 * c2);
-        const double w = rW[q] * J;
-        const double r0 = xt0 - x[0], r1 = xt1 - x[1], r2v = xt2 - x[2];
-        const double d2 = r0 * r0 + r1 * r1 + r2v * r2v;
-        const double di = 1.0 / sqrt(d2);
-        const double di3 = di * di * di;
-        const double ws = w * cS;
-        Kw[0 * NC + tid] = ws * (di + r0 * r0 * di3);
-        Kw[1 * NC + tid] = ws * (di + r1 * r1 * di3);
-        Kw[2 * NC + tid] = ws * (di + r2v * r2v * di3);
-        Kw[3 * NC + tid] = ws * r0 * r1 * di3;
-        Kw[4 * NC + tid] = ws * r0 * r2v * di3;
-        Kw[5 * NC + tid] = ws * r1 * r2v * di3;
-        const double rn = r0 * nt0 + r1 * nt1 + r2v * nt2;
-        const double wk = w * cK * rn * di3 * di * di;
-        Kw[6 * NC + tid] = wk * r0 * r0;
-        Kw[7 * NC + tid] = wk * r1 * r1;
-        Kw[8 * NC + tid] = wk * r2v * r2v;
-        Kw[9 * NC + tid] = wk * r0 * r1;
-        Kw[10 * NC + tid] = wk * r0 * r2v;
-        Kw[11 * NC + tid] = wk * r1 * r2v;
+        if (live) {
+          const double c0 = dt[1] * dp[2] - dt[2] * dp[1];
+          const double c1 = dt[2] * dp[0] - dt[0] * dp[2];
+          const double c2 = dt[0] * dp[1] - dt[1] * dp[0];
+          const double J = sqrt(c0 * c0 + c1 * c1 + c2 * c2);
+          const double w = rW[q] * J;
+          const double r0 = xt0 - x[0], r1 = xt1 - x[1], r2v = xt2 - x[2];
+          const double d2 = r0 * r0 + r1 * r1 + r2v * r2v;
+          const double di = 1.0 / sqrt(d2);
+          const double di3 = di * di * di;
+          const double ws = w * cS;
+          Kwg[0 * NC + node] = ws * (di + r0 * r0 * di3);
+          Kwg[1 * NC + node] = ws * (di + r1 * r1 * di3);
+          Kwg[2 * NC + node] = ws * (di + r2v * r2v * di3);
+          Kwg[3 * NC + node] = ws * r0 * r1 * di3;
+          Kwg[4 * NC + node] = ws * r0 * r2v * di3;
+          Kwg[5 * NC + node] = ws * r1 * r2v * di3;
+          const double rn = r0 * nt0 + r1 * nt1 + r2v * nt2;
+          const double wk = w * cK * rn * di3 * di * di;
+          Kwg[6 * NC + node] = wk * r0 * r0;
+          Kwg[7 * NC + node] = wk * r1 * r1;
+          Kwg[8 * NC + node] = wk * r2v * r2v;
+          Kwg[9 * NC + node] = wk * r0 * r1;
+          Kwg[10 * NC + node] = wk * r0 * r2v;
+          Kwg[11 * NC + node] = wk * r1 * r2v;
+        } else {
+          for (int k = 0; k < 12; ++k) Kwg[k * NC + node] = 0.0;
+        }
       } else {
-        for (int k = 0; k < 12; ++k) Kw[k * NC + tid] = 0.0;
-        for (int b = 0; b < nB; ++b) Ych[b * YS + tid] = 0.0;
+        for (int k = 0; k < 12; ++k) Kwg[k * NC + node] = 0.0;
+        if (g == 0)
+          for (int b = 0; b < nB; ++b) Ych[b * YS + node] = 0.0;
       }
     }
     __syncthreads();
@@ -390,10 +421,12 @@ __global__ __launch_bounds__(256) void k_singular(int p, int ps, double eta,
       for (int q = 0; q < NC; ++q) {
         const double y = Ych[tid * YS + q];
 #pragma unroll
-        for (int k = 0; k < 12; ++k) acc0[k] += Kw[k * NC + q] * y;
+        for (int gg = 0; gg < G; ++gg)
+#pragma unroll
+          for (int k = 0; k < 12; ++k) acc0[gg][k] += Kw[(gg * 12 + k) * NC + q] * y;
       }
     }
-    if (tid + 256 < nB) {
+    if (G == 1 && tid + 256 < nB) {
       for (int q = 0; q < NC; ++q) {
         const double y = Ych[(tid + 256) * YS + q];
 #pragma unroll
@@ -402,53 +435,90 @@ __global__ __launch_bounds__(256) void k_singular(int p, int ps, double eta,
     }
   }
   __syncthreads();
-  double* Cs = Ych;  // [12][nB], fits since YS >= 12
+  // C of every shape of the group, [G][12][nB], over the coefficient, harmonic and weight
+  // buffers (the launcher checks that it fits there)
+  double* Cs = lds;
   if (tid < nB)
-    for (int k = 0; k < 12; ++k) Cs[k * nB + tid] = acc0[k];
-  if (tid + 256 < nB)
+#pragma unroll
+    for (int gg = 0; gg < G; ++gg)
+#pragma unroll
+      for (int k = 0; k < 12; ++k) Cs[(gg * 12 + k) * nB + tid] = acc0[gg][k];
+  if (G == 1 && tid + 256 < nB)
     for (int k = 0; k < 12; ++k) Cs[k * nB + tid + 256] = acc1[k];
   __syncthreads();
-  double* S = Sop + (size_t)s * M3 * M3;
-  double* K = Kop + (size_t)s * M3 * M3;
   const int ci[6] = {0, 1, 2, 0, 0, 1}, cj[6] = {0, 1, 2, 1, 2, 2};
-  for (int a = tid; a < M; a += 256) {
-    double v[12];
-    for (int k = 0; k < 12; ++k) v[k] = 0.0;
-    const double* f = Ft + (size_t)a * nB;
-    for (int b = 0; b < nB; ++b) {
-      const double fb = f[b];
+  for (int gg = 0; gg < ng; ++gg) {
+    const double* C = Cs + gg * 12 * nB;
+    double* S = Sop + (size_t)(s0 + gg) * M3 * M3;
+    double* K = Kop + (size_t)(s0 + gg) * M3 * M3;
+    for (int a = tid; a < M; a += 256) {
+      double v[12];
+      for (int k = 0; k < 12; ++k) v[k] = 0.0;
+      const double* f = Ft + (size_t)a * nB;
+      for (int b = 0; b < nB; ++b) {
+        const double fb = f[b];
 #pragma unroll
-      for (int k = 0; k < 12; ++k) v[k] += Cs[k * nB + b] * fb;
-    }
-    for (int k = 0; k < 6; ++k) {
-      const int c = ci[k], cc = cj[k];
-      const size_t rowA = (size_t)c * M + t, colA = (size_t)cc * M + a;
-      S[colA * M3 + rowA] = v[k];
-      K[colA * M3 + rowA] = v[6 + k];
-      if (c != cc) {
-        const size_t rowB = (size_t)cc * M + t, colB = (size_t)c * M + a;
-        S[colB * M3 + rowB] = v[k];
-        K[colB * M3 + rowB] = v[6 + k];
+        for (int k = 0; k < 12; ++k) v[k] += C[k * nB + b] * fb;
+      }
+      for (int k = 0; k < 6; ++k) {
+        const int c = ci[k], cc = cj[k];
+        const size_t rowA = (size_t)c * M + t, colA = (size_t)cc * M + a;
+        S[colA * M3 + rowA] = v[k];
+        K[colA * M3 + rowA] = v[6 + k];
+        if (c != cc) {
+          const size_t rowB = (size_t)cc * M + t, colB = (size_t)c * M + a;
+          S[colB * M3 + rowB] = v[k];
+          K[colB * M3 + rowB] = v[6 + k];
+        }
       }
     }
   }
+}
+
+// LDS of k_singular<NC, G> in bytes; 0 if the per-shape results C ([G][12][nB]) would not
+// fit over its coefficient, harmonic and weight buffers.
+static size_t singular_group_lds(int p, int nc_nodes, int g) {
+  const size_t nc = (size_t)(p + 1) * (p + 1), nB = (size_t)p * p + 2 * p;
+  const size_t front = g * 3 * nc + nB * (nc_nodes + 1) + (size_t)g * 12 * nc_nodes;
+  if ((size_t)g * 12 * nB > front) return 0;
+  return (front + 2 * nc + 2 * (p + 1)) * sizeof(double);
 }
 
 hipError_t launch_singular_assemble(int ns, int p, int ps, double eta, const double* coef,
                                     const double* gx, const double* gn, const double* node_th,
                                     const double* node_ph, const double* rnodes, const double* rW,
                                     const double* Fttab, double* Sop, double* Kop, hipStream_t st) {
-  const int M = (p + 1) * 2 * p;
-  dim3 grid(M, ns);
-  const int nodes = singular_chunk(p, 12);
-  const size_t lds = singular_lds_bytes(p, nodes, 12);
+  // Two shapes per workgroup when their accumulators fit one pass over B_p (nB <= 256)
+  // and two workgroups fit a CU's LDS; else one shape with the largest node chunk that
+  // lets two workgroups share a CU (singular_chunk).  (Four shapes need 48 accumulators
+  // per thread and spill at two waves per SIMD.)
+  constexpr size_t kLdsPerCu = 160 * 1024;
+  const int M = (p + 1) * 2 * p, nB = p * p + 2 * p;
+  int nodes = 0, group = 1;
+  if (nB <= 256)
+    for (int n : {64, 48, 32}) {
+      const size_t b = singular_group_lds(p, n, 2);
+      if (b && 2 * b <= kLdsPerCu) {
+        nodes = n;
+        group = 2;
+        break;
+      }
+    }
+  if (!nodes) nodes = singular_chunk(p, 12);
+  const size_t lds = singular_group_lds(p, nodes, group);
+  if (!lds) return hipErrorInvalidValue;
+  dim3 grid(M, (ns + group - 1) / group);
   auto run = [&](auto kern) {
     hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
-    kern<<<grid, 256, lds, st>>>(p, ps, eta, coef, gx, gn, node_th, node_ph, rnodes, rW, Fttab, Sop, Kop);
+    kern<<<grid, 256, lds, st>>>(ns, p, ps, eta, coef, gx, gn, node_th, node_ph, rnodes, rW, Fttab, Sop, Kop);
     return hipSuccess;
   };
-  hipError_t e = nodes == 64 ? run(k_singular<64>) : nodes == 48 ? run(k_singular<48>) : run(k_singular<32>);
+  hipError_t e;
+  if (group == 2)
+    e = nodes == 64 ? run(k_singular<64, 2>) : nodes == 48 ? run(k_singular<48, 2>) : run(k_singular<32, 2>);
+  else
+    e = nodes == 64 ? run(k_singular<64, 1>) : nodes == 48 ? run(k_singular<48, 1>) : run(k_singular<32, 1>);
   if (e != hipSuccess) return e;
   return hipGetLastError();
 }
