@@ -105,6 +105,44 @@ __device__ __forceinline__ void legendre_sweep(int L, double x, double s, F&& f,
   }
 }
 
+// The columns m = r, 7 - r, 8 + r, 15 - r, ... (r in 0..3) of legendre_sweep, for four
+// lanes sharing one point: every lane gets about a quarter of the (l, m) terms, and each
+// value is formed by the same operations in the same order as in legendre_sweep (the
+// diagonal P_mm, Q_mm are carried through the columns a lane skips).  Needs the table.
+template <class F>
+__device__ __forceinline__ void legendre_columns4(int L, int r, double x, double s, F&& f,
+                                                  const double* tab) {
+  double pmm = 0.28209479177387814347;  // 1/sqrt(4 pi)
+  double qmm = 0.0;
+  const int n2 = (L + 1) * (L + 1);
+  int mm = 0;  // pmm, qmm belong to column mm
+  for (int k = 0;; ++k) {
+    const int m = (k & 1) ? 4 * k + 3 - r : 4 * k + r;
+    if (m > L) break;
+    for (; mm < m; ++mm) {
+      const double c = tab[2 * n2 + 2 * (mm + 1)];
+      qmm = c * pmm;
+      pmm = c * s * pmm;
+    }
+    double p0 = pmm, q0 = qmm, d0 = m * x * qmm;
+    f(m, m, p0, q0, d0);
+    if (m < L) {
+      const double c = tab[2 * n2 + 2 * m + 1];
+      double p1 = c * x * p0, q1 = c * x * q0, d1 = c * (x * d0 - s * p0);
+      f(m + 1, m, p1, q1, d1);
+      for (int l = m + 2; l <= L; ++l) {
+        const double a = tab[2 * (l * (L + 1) + m)];
+        const double b = tab[2 * (l * (L + 1) + m) + 1];
+        const double p2 = a * (x * p1 - b * p0);
+        const double q2 = a * (x * q1 - b * q0);
+        const double d2 = a * (x * d1 - s * p1 - b * d0);
+        f(l, m, p2, q2, d2);
+        p0 = p1; p1 = p2; q0 = q1; q1 = q2; d0 = d1; d1 = d2;
+      }
+    }
+  }
+}
+
 // Rotation matrix (row-major) of a unit quaternion (w, x, y, z), body -> lab.
 __host__ __device__ inline void quat_to_rot(const double* q, double* R) {
   double w = q[0], x = q[1], y = q[2], z = q[3];

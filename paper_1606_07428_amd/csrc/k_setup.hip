@@ -281,7 +281,7 @@ hipError_t launch_shape_geometry(int ns, int p, const double* coef, const double
 // group 0 also stages the harmonics in LDS, and then thread b contracts them with the
 // weights of every shape of the group.  Finally C of each shape goes to LDS and the
 // threads form row(t) of its operators.
-template <int NC, int G>
+template <int NC, int G, int LPN>
 __global__ __launch_bounds__(256, 2) void k_singular(int ns, int p, int ps, double eta,
                                                   const double* __restrict__ coef_all,
                                                   const double* __restrict__ gx_all,
@@ -293,7 +293,8 @@ __global__ __launch_bounds__(256, 2) void k_singular(int ns, int p, int ps, doub
                                                   const double* __restrict__ Ft,
                                                   double* __restrict__ Sop,
                                                   double* __restrict__ Kop) {
-  static_assert(NC * G <= 256, "one lane per (node, shape)");
+  static_assert(LPN == 1 || LPN == 4, "one or four lanes per (node, shape)");
+  static_assert(NC * G * LPN <= 256, "LPN lanes per (node, shape)");
   extern __shared__ double lds[];
   // row stride of the staged harmonics: odd, so that the contraction, whose lanes
   // read one row each at the same column, hits distinct LDS banks (a stride of 64
@@ -314,9 +315,11 @@ __global__ __launch_bounds__(256, 2) void k_singular(int ns, int p, int ps, doub
   sincos(nth[t], &st, &ct);
   sincos(nph[t], &sp, &cp);
   const double Q[9] = {cp * ct, -sp, cp * st, sp * ct, cp, sp * st, -st, 0.0, ct};
-  // lane (node, g) of the sweep: its shape's target point and normal
-  const int node = tid % NC, g = tid / NC;
-  const bool sweeper = tid < NC * G;
+  // lanes (node, g, r) of the sweep, r < LPN splitting the Legendre columns: the shape's
+  // target point and normal
+  const int pair = tid / LPN, r = tid % LPN;
+  const int node = pair % NC, g = pair / NC;
+  const bool sweeper = pair < NC * G;
   const bool live = sweeper && g < ng;
   double xt0 = 0, xt1 = 0, xt2 = 0, nt0 = 0, nt1 = 0, nt2 = 0;
   if (live) {
@@ -351,7 +354,7 @@ __global__ __launch_bounds__(256, 2) void k_singular(int ns, int p, int ps, doub
         int cur_m = -1;
         double cm = 1.0, sm = 0.0;
         const bool stage = g == 0;
-        legendre_sweep(p, cx, sx, [&](int l, int m, double P, double Qv, double D) {
+        auto term = [&](int l, int m, double P, double Qv, double D) {
           const int i0 = l * l + l;
           if (m == 0) {
             for (int c = 0; c < 3; ++c) {
@@ -381,8 +384,22 @@ __global__ __launch_bounds__(256, 2) void k_singular(int ns, int p, int ps, doub
             const int bm = band_index(l, -m, p);
             if (bm >= 0) Ych[bm * YS + node] = ym;
           }
-        }, ltab);
-        if (live) {
+        };
+        if (LPN == 1) {
+          legendre_sweep(p, cx, sx, term, ltab);
+        } else {
+          legendre_columns4(p, r, cx, sx, term, ltab);
+          // the four lanes of the point are adjacent: sum their columns' contributions
+#pragma unroll
+          for (int o = 1; o < LPN; o <<= 1)
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+              x[c] += __shfl_xor(x[c], o, 64);
+              dt[c] += __shfl_xor(dt[c], o, 64);
+              dp[c] += __shfl_xor(dp[c], o, 64);
+            }
+        }
+        if (live && r == 0) {
           const double c0 = dt[1] * dp[2] - dt[2] * dp[1];
           const double c1 = dt[2] * dp[0] - dt[0] * dp[2];
           const double c2 = dt[0] * dp[1] - dt[1] * dp[0];
@@ -407,13 +424,14 @@ __global__ __launch_bounds__(256, 2) void k_singular(int ns, int p, int ps, doub
           Kwg[9 * NC + node] = wk * r0 * r1;
           Kwg[10 * NC + node] = wk * r0 * r2v;
           Kwg[11 * NC + node] = wk * r1 * r2v;
-        } else {
+        } else if (r == 0) {
           for (int k = 0; k < 12; ++k) Kwg[k * NC + node] = 0.0;
         }
       } else {
-        for (int k = 0; k < 12; ++k) Kwg[k * NC + node] = 0.0;
+        if (r == 0)
+          for (int k = 0; k < 12; ++k) Kwg[k * NC + node] = 0.0;
         if (g == 0)
-          for (int b = 0; b < nB; ++b) Ych[b * YS + node] = 0.0;
+          for (int b = r; b < nB; b += LPN) Ych[b * YS + node] = 0.0;
       }
     }
     __syncthreads();
@@ -488,22 +506,22 @@ hipError_t launch_singular_assemble(int ns, int p, int ps, double eta, const dou
                                     const double* gx, const double* gn, const double* node_th,
                                     const double* node_ph, const double* rnodes, const double* rW,
                                     const double* Fttab, double* Sop, double* Kop, hipStream_t st) {
-  // Two shapes per workgroup when their accumulators fit one pass over B_p (nB <= 256)
-  // and two workgroups fit a CU's LDS; else one shape with the largest node chunk that
-  // lets two workgroups share a CU (singular_chunk).  (Four shapes need 48 accumulators
-  // per thread and spill at two waves per SIMD.)
+  // Two shapes per workgroup, 32 rotated nodes per chunk and four lanes per (node, shape),
+  // each sweeping a quarter of the Legendre columns, when the two shapes' accumulators fit
+  // one pass over B_p (nB <= 256) and two workgroups fit a CU's LDS; else one shape and
+  // one lane per node with the largest chunk that lets two workgroups share a CU
+  // (singular_chunk).  (Four shapes per workgroup need 48 accumulators per thread and
+  // spill at two waves per SIMD.)
   constexpr size_t kLdsPerCu = 160 * 1024;
   const int M = (p + 1) * 2 * p, nB = p * p + 2 * p;
   int nodes = 0, group = 1;
-  if (nB <= 256)
-    for (int n : {64, 48, 32}) {
-      const size_t b = singular_group_lds(p, n, 2);
-      if (b && 2 * b <= kLdsPerCu) {
-        nodes = n;
-        group = 2;
-        break;
-      }
+  if (nB <= 256) {
+    const size_t b = singular_group_lds(p, 32, 2);
+    if (b && 2 * b <= kLdsPerCu) {
+      nodes = 32;
+      group = 2;
     }
+  }
   if (!nodes) nodes = singular_chunk(p, 12);
   const size_t lds = singular_group_lds(p, nodes, group);
   if (!lds) return hipErrorInvalidValue;
@@ -516,9 +534,9 @@ hipError_t launch_singular_assemble(int ns, int p, int ps, double eta, const dou
   };
   hipError_t e;
   if (group == 2)
-    e = nodes == 64 ? run(k_singular<64, 2>) : nodes == 48 ? run(k_singular<48, 2>) : run(k_singular<32, 2>);
+    e = run(k_singular<32, 2, 4>);
   else
-    e = nodes == 64 ? run(k_singular<64, 1>) : nodes == 48 ? run(k_singular<48, 1>) : run(k_singular<32, 1>);
+    e = nodes == 64 ? run(k_singular<64, 1, 1>) : nodes == 48 ? run(k_singular<48, 1, 1>) : run(k_singular<32, 1, 1>);
   if (e != hipSuccess) return e;
   return hipGetLastError();
 }
