@@ -702,13 +702,35 @@ __global__ __launch_bounds__(1024) void k_gauss_jordan(int n, double* A_all, int
         const double a = A[(size_t)col * n + i] - (i == col ? 1.0 : 0.0);
         w[q] = q < kb ? a : 0.0;
       }
-      for (int j = 0; j < n; ++j) {
-        if (j >= k0 && j < k0 + kb) continue;
-        double v = A[(size_t)j * n + i];
+      // the columns before and after the panel, four at a time: four independent loads
+      // in flight per wave, and the staged rows read as pairs of doubles (aligned: n = 3M
+      // is even and both ranges start at a multiple of 4)
+      auto update = [&](int j, int j1) {
+        for (; j + 4 <= j1; j += 4) {
+          double v[4];
 #pragma unroll
-        for (int q = 0; q < nb; ++q) v = fma(w[q], rows[(size_t)q * n + j], v);
-        A[(size_t)j * n + i] = v;
-      }
+          for (int u = 0; u < 4; ++u) v[u] = A[(size_t)(j + u) * n + i];
+#pragma unroll
+          for (int q = 0; q < nb; ++q) {
+            const double2 r01 = *reinterpret_cast<const double2*>(rows + (size_t)q * n + j);
+            const double2 r23 = *reinterpret_cast<const double2*>(rows + (size_t)q * n + j + 2);
+            v[0] = fma(w[q], r01.x, v[0]);
+            v[1] = fma(w[q], r01.y, v[1]);
+            v[2] = fma(w[q], r23.x, v[2]);
+            v[3] = fma(w[q], r23.y, v[3]);
+          }
+#pragma unroll
+          for (int u = 0; u < 4; ++u) A[(size_t)(j + u) * n + i] = v[u];
+        }
+        for (; j < j1; ++j) {
+          double v = A[(size_t)j * n + i];
+#pragma unroll
+          for (int q = 0; q < nb; ++q) v = fma(w[q], rows[(size_t)q * n + j], v);
+          A[(size_t)j * n + i] = v;
+        }
+      };
+      update(0, k0);
+      update(k0 + kb, n);
     }
     __syncthreads();
   }
