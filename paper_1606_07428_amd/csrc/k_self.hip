@@ -212,59 +212,75 @@ template <> struct MfmaAcc<float> {
   __device__ static int row(int lk, int e) { return 4 * lk + e; }
 };
 
-// y_body[(row/M)*N + i*M + row%M] = Z[row][i]
+// y_body[(row/M)*N + i*M + row%M] = Z[row][i], Z = A B (A: 3M x 3M column-major, B: one body
+// per column).  Tiles of 64 rows x 32 bodies, 832 workgroups at 1000 bodies and p = 16 (64 x 64
+// tiles left 416 for 256 CUs); four waves of 32 x 16; K staged by 32 through LDS, the next
+// slice loaded into registers while the MFMAs use the current one.
 template <typename T>
 __global__ __launch_bounds__(256) void k_self_gemm(int M3, int n, int M, const T* __restrict__ A,
                                                    const T* __restrict__ B,
                                                    double* __restrict__ y_body) {
-  __shared__ T As[64][17];
-  __shared__ T Bs[16][65];
+  constexpr int BM = 64, BN = 32, BK = 32;
+  __shared__ T As[BM][BK + 1];
+  __shared__ T Bs[BK][BN + 1];
   using V = typename MfmaAcc<T>::V;
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
-  const int bm = blockIdx.y * 64, bn = blockIdx.x * 64;
-  const int wr = (wid >> 1) * 32, wc = (wid & 1) * 32;
-  V acc[2][2];
+  const int bm = blockIdx.y * BM, bn = blockIdx.x * BN;
+  const int wr = (wid >> 1) * 32, wc = (wid & 1) * 16;
+  V acc[2];
   for (int a = 0; a < 2; ++a)
-    for (int b = 0; b < 2; ++b)
-      for (int e = 0; e < 4; ++e) acc[a][b][e] = 0;
+    for (int e = 0; e < 4; ++e) acc[a][e] = 0;
   const int lr = lane & 15, lk = lane >> 4;
-  for (int k0 = 0; k0 < M3; k0 += 16) {
-    for (int e = tid; e < 1024; e += 256) {
-      const int r = e & 63, kk = e >> 6;  // A column-major: consecutive rows are contiguous
+  // slice elements of this thread: A (BM x BK) e = tid + 256 u, row e % BM (consecutive rows
+  // contiguous in the column-major A); B (BK x BN) e = tid + 256 u, k e % BK (one body's k
+  // contiguous)
+  constexpr int UA = BM * BK / 256, UB = BK * BN / 256;
+  T ra[UA], rb[UB];
+  auto load = [&](int k0) {
+#pragma unroll
+    for (int u = 0; u < UA; ++u) {
+      const int e = tid + 256 * u, r = e % BM, kk = e / BM;
       const int gi = bm + r, gk = k0 + kk;
-      As[r][kk] = (gi < M3 && gk < M3) ? A[(size_t)gk * M3 + gi] : (T)0;
+      ra[u] = (gi < M3 && gk < M3) ? A[(size_t)gk * M3 + gi] : (T)0;
     }
-    for (int e = tid; e < 1024; e += 256) {
-      const int kk = e & 15, c = e >> 4;  // B column-major (one body per column)
+#pragma unroll
+    for (int u = 0; u < UB; ++u) {
+      const int e = tid + 256 * u, kk = e % BK, c = e / BK;
       const int gk = k0 + kk, gj = bn + c;
-      Bs[kk][c] = (gk < M3 && gj < n) ? B[(size_t)gj * M3 + gk] : (T)0;
+      rb[u] = (gk < M3 && gj < n) ? B[(size_t)gj * M3 + gk] : (T)0;
     }
+  };
+  load(0);
+  for (int k0 = 0; k0 < M3; k0 += BK) {
     __syncthreads();
 #pragma unroll
-    for (int ks = 0; ks < 16; ks += 4) {
+    for (int u = 0; u < UA; ++u) {
+      const int e = tid + 256 * u;
+      As[e % BM][e / BM] = ra[u];
+    }
 #pragma unroll
-      for (int ti = 0; ti < 2; ++ti) {
-        const T av = As[wr + ti * 16 + lr][ks + lk];
-#pragma unroll
-        for (int tj = 0; tj < 2; ++tj) {
-          const T bv = Bs[ks + lk][wc + tj * 16 + lr];
-          acc[ti][tj] = MfmaAcc<T>::mfma(av, bv, acc[ti][tj]);
-        }
-      }
+    for (int u = 0; u < UB; ++u) {
+      const int e = tid + 256 * u;
+      Bs[e % BK][e / BK] = rb[u];
     }
     __syncthreads();
+    if (k0 + BK < M3) load(k0 + BK);
+#pragma unroll
+    for (int ks = 0; ks < BK; ks += 4) {
+      const T bv = Bs[ks + lk][wc + lr];
+#pragma unroll
+      for (int ti = 0; ti < 2; ++ti) acc[ti] = MfmaAcc<T>::mfma(As[wr + ti * 16 + lr][ks + lk], bv, acc[ti]);
+    }
   }
   const size_t N = (size_t)n * M;
 #pragma unroll
   for (int ti = 0; ti < 2; ++ti)
 #pragma unroll
-    for (int tj = 0; tj < 2; ++tj)
-#pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        const int row = bm + wr + ti * 16 + MfmaAcc<T>::row(lk, e), i = bn + wc + tj * 16 + lr;
-        if (row < M3 && i < n)
-          y_body[(size_t)(row / M) * N + (size_t)i * M + row % M] = (double)acc[ti][tj][e];
-      }
+    for (int e = 0; e < 4; ++e) {
+      const int row = bm + wr + ti * 16 + MfmaAcc<T>::row(lk, e), i = bn + wc + lr;
+      if (row < M3 && i < n)
+        y_body[(size_t)(row / M) * N + (size_t)i * M + row % M] = (double)acc[ti][e];
+    }
 }
 
 // scatter of a float32 (3M x n, row-major [row][i]) product into y_body
@@ -296,7 +312,7 @@ hipError_t launch_self_apply_shared(int n, int M, const TM* A, const double* Rm,
   } else {
     TM* B = reinterpret_cast<TM*>(scratchB);
     k_rotate_in<TM><<<gblocks, 256, 0, st>>>(n, M, Rm, x_lab, B);
-    dim3 grid((n + 63) / 64, (M3 + 63) / 64);
+    dim3 grid((n + 31) / 32, (M3 + 63) / 64);
     k_self_gemm<TM><<<grid, 256, 0, st>>>(M3, n, M, A, B, y_body);
   }
   return hipGetLastError();
