@@ -276,11 +276,12 @@ hipError_t launch_shape_geometry(int ns, int p, const double* coef, const double
 //
 // One workgroup per (target node t, group of G consecutive shapes).  The rotated nodes
 // and their harmonics Y_b(s_q) depend on t alone, so the shapes of a group share them.
-// Per chunk of NC rotated nodes, lane group g (NC lanes) runs the Legendre recurrence
-// at each node for shape g's surface there (position, tangents, kernel weights), lane
-// group 0 also stages the harmonics in LDS, and then thread b contracts them with the
-// weights of every shape of the group.  Finally C of each shape goes to LDS and the
-// threads form row(t) of its operators.
+// Per chunk of NC rotated nodes, LPN adjacent lanes per (node, shape g) run the Legendre
+// recurrence at the node for shape g's surface there (with LPN = 4 each lane takes a
+// quarter of the columns m and the lanes add their partial position and tangents by
+// shuffles), then form the kernel weights; the lanes of shape 0 also stage the harmonics
+// in LDS, and thread b contracts them with the weights of every shape of the group.
+// Finally C of each shape goes to LDS and the threads form row(t) of its operators.
 template <int NC, int G, int LPN>
 __global__ __launch_bounds__(256, 2) void k_singular(int ns, int p, int ps, double eta,
                                                   const double* __restrict__ coef_all,
