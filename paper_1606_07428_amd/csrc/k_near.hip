@@ -170,10 +170,11 @@ hipError_t launch_near_list(int n, int M, int kmax, double kappa, const double* 
 // Fine sources of the bodies listed in `need` (the bodies that are near some body):
 // density zt_c(b) = sum_a U[a][b] z_c(a) (band-limited interpolant; z in body frames when
 // z_is_body, then rotated), X' = c_j + R_j r'_b, q' = w'_b zt, packed like the plain
-// sources.  A 256-thread block covers 32 fine nodes x 8 chunks of the a-sum for kJB
-// listed bodies: short independent load chains, U[a][b] read once per block (coalesced
-// over b) for kJB bodies, partial sums reduced in LDS in a fixed order.
-constexpr int kJB = 4;
+// sources.  One lane per fine node b (64 per wave) and kIB listed bodies per wave: U[a][b]
+// is read coalesced over the lanes and the bodies' densities z_c(a) are wave-uniform
+// (scalar loads), so each U value feeds 3 kIB multiply-adds; every sum runs over a in
+// order, in one lane.
+constexpr int kIB = 8;
 template <typename T>
 __global__ __launch_bounds__(256) void k_interp_pack(int n, int M, int Mu, int nneed,
                                                      const int* __restrict__ need,
@@ -185,66 +186,56 @@ __global__ __launch_bounds__(256) void k_interp_pack(int n, int M, int Mu, int n
                                                      const double* __restrict__ fr_all,
                                                      const double* __restrict__ fw_all,
                                                      Src8<T>* __restrict__ srcf) {
-  __shared__ double part[8][kJB * 3][33];
-  const int bl = threadIdx.x & 31, kc = threadIdx.x >> 5;
-  const int b = blockIdx.x * 32 + bl;
-  const int q0 = blockIdx.y * kJB, jn = min(kJB, nneed - q0);
+  const int lane = threadIdx.x & 63;
+  const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+  const int b = blockIdx.x * 64 + lane, bc = min(b, Mu - 1);
+  const int q0 = (blockIdx.y * 4 + wv) * kIB;
+  if (q0 >= nneed) return;  // whole waves; the kernel has no barrier
+  const int jn = min(kIB, nneed - q0);
   const size_t N = (size_t)n * M;
-  double acc[kJB][3];
+  size_t zo[kIB];
 #pragma unroll
-  for (int jj = 0; jj < kJB; ++jj) acc[jj][0] = acc[jj][1] = acc[jj][2] = 0.0;
-  size_t zo[kJB];
+  for (int jj = 0; jj < kIB; ++jj) zo[jj] = (size_t)need[q0 + min(jj, jn - 1)] * M;
+  double acc[kIB][3];
 #pragma unroll
-  for (int jj = 0; jj < kJB; ++jj) zo[jj] = (size_t)need[q0 + min(jj, jn - 1)] * M;
-  if (b < Mu) {
-    const int a0 = (M * kc) / 8, a1 = (M * (kc + 1)) / 8;
-#pragma unroll 4
-    for (int a = a0; a < a1; ++a) {
-      const double u = U[(size_t)a * Mu + b];
+  for (int jj = 0; jj < kIB; ++jj) acc[jj][0] = acc[jj][1] = acc[jj][2] = 0.0;
+  for (int a = 0; a < M; ++a) {
+    const double u = U[(size_t)a * Mu + bc];
 #pragma unroll
-      for (int jj = 0; jj < kJB; ++jj) {
-        const size_t g = zo[jj] + a;
-        acc[jj][0] += u * z[g];
-        acc[jj][1] += u * z[N + g];
-        acc[jj][2] += u * z[2 * N + g];
-      }
+    for (int jj = 0; jj < kIB; ++jj) {
+      const size_t g = zo[jj] + a;
+      acc[jj][0] += u * z[g];
+      acc[jj][1] += u * z[N + g];
+      acc[jj][2] += u * z[2 * N + g];
     }
   }
+  if (b >= Mu) return;
 #pragma unroll
-  for (int jj = 0; jj < kJB; ++jj)
-#pragma unroll
-    for (int c = 0; c < 3; ++c) part[kc][jj * 3 + c][bl] = acc[jj][c];
-  __syncthreads();
-  // 32 nodes x kJB bodies epilogues, one per thread of the first kJB*32 threads
-  const int jj = threadIdx.x >> 5;
-  if (jj >= jn || b >= Mu) return;
-  double v[3];
-  for (int c = 0; c < 3; ++c) {
-    double t = 0.0;
-    for (int k = 0; k < 8; ++k) t += part[k][jj * 3 + c][bl];
-    v[c] = t;
+  for (int jj = 0; jj < kIB; ++jj) {
+    if (jj >= jn) break;
+    double v[3] = {acc[jj][0], acc[jj][1], acc[jj][2]};
+    const int j = need[q0 + jj], s = sid[j];
+    const double* R = Rm + 9 * j;
+    if (z_is_body) {
+      const double b0 = R[0] * v[0] + R[1] * v[1] + R[2] * v[2];
+      const double b1 = R[3] * v[0] + R[4] * v[1] + R[5] * v[2];
+      const double b2 = R[6] * v[0] + R[7] * v[1] + R[8] * v[2];
+      v[0] = b0; v[1] = b1; v[2] = b2;
+    }
+    const double* fr = fr_all + (size_t)s * 3 * Mu;
+    const double r0 = fr[b], r1 = fr[Mu + b], r2 = fr[2 * (size_t)Mu + b];
+    const double w = fw_all[(size_t)s * Mu + b];
+    Src8<T> o;
+    o.v[0] = (T)(cen[3 * j] + R[0] * r0 + R[1] * r1 + R[2] * r2);
+    o.v[1] = (T)(cen[3 * j + 1] + R[3] * r0 + R[4] * r1 + R[5] * r2);
+    o.v[2] = (T)(cen[3 * j + 2] + R[6] * r0 + R[7] * r1 + R[8] * r2);
+    o.v[3] = (T)(w * v[0]);
+    o.v[4] = (T)(w * v[1]);
+    o.v[5] = (T)(w * v[2]);
+    o.v[6] = 0;
+    o.v[7] = 0;
+    srcf[(size_t)j * Mu + b] = o;
   }
-  const int j = need[q0 + jj], s = sid[j];
-  const double* R = Rm + 9 * j;
-  if (z_is_body) {
-    const double b0 = R[0] * v[0] + R[1] * v[1] + R[2] * v[2];
-    const double b1 = R[3] * v[0] + R[4] * v[1] + R[5] * v[2];
-    const double b2 = R[6] * v[0] + R[7] * v[1] + R[8] * v[2];
-    v[0] = b0; v[1] = b1; v[2] = b2;
-  }
-  const double* fr = fr_all + (size_t)s * 3 * Mu;
-  const double r0 = fr[b], r1 = fr[Mu + b], r2 = fr[2 * (size_t)Mu + b];
-  const double w = fw_all[(size_t)s * Mu + b];
-  Src8<T> o;
-  o.v[0] = (T)(cen[3 * j] + R[0] * r0 + R[1] * r1 + R[2] * r2);
-  o.v[1] = (T)(cen[3 * j + 1] + R[3] * r0 + R[4] * r1 + R[5] * r2);
-  o.v[2] = (T)(cen[3 * j + 2] + R[6] * r0 + R[7] * r1 + R[8] * r2);
-  o.v[3] = (T)(w * v[0]);
-  o.v[4] = (T)(w * v[1]);
-  o.v[5] = (T)(w * v[2]);
-  o.v[6] = 0;
-  o.v[7] = 0;
-  srcf[(size_t)j * Mu + b] = o;
 }
 
 // Correction of the all-pairs sum for near pairs.  The concatenated source list of body
@@ -347,7 +338,7 @@ hipError_t launch_near_corr(int kind, int n, int M, int Mu, int kmax, int nneed,
                             hipStream_t st) {
   const int N = n * M;
   if (nitems > 0 && nneed > 0) {
-    dim3 gi((Mu + 31) / 32, (nneed + kJB - 1) / kJB);
+    dim3 gi((Mu + 63) / 64, (nneed + 4 * kIB - 1) / (4 * kIB));
     k_interp_pack<T><<<gi, 256, 0, st>>>(n, M, Mu, nneed, need, U, z, z_is_body, sid, cen, Rm, fr, fw,
                                          reinterpret_cast<Src8<T>*>(srcf));
     hipError_t e = hipGetLastError();
