@@ -170,11 +170,11 @@ hipError_t launch_near_list(int n, int M, int kmax, double kappa, const double* 
 // Fine sources of the bodies listed in `need` (the bodies that are near some body):
 // density zt_c(b) = sum_a U[a][b] z_c(a) (band-limited interpolant; z in body frames when
 // z_is_body, then rotated), X' = c_j + R_j r'_b, q' = w'_b zt, packed like the plain
-// sources.  One lane per fine node b (64 per wave) and kIB listed bodies per wave: U[a][b]
-// is read coalesced over the lanes and the bodies' densities z_c(a) are wave-uniform
-// (scalar loads), so each U value feeds 3 kIB multiply-adds; every sum runs over a in
-// order, in one lane.
-constexpr int kIB = 8;
+// sources.  kNB fine nodes per lane (b = 256 x + lane + 64 k) and kIB listed bodies per
+// wave: U[a][b] is read coalesced over the lanes and the bodies' densities z_c(a) are
+// wave-uniform (scalar loads), so each density value feeds kNB multiply-adds and each U
+// value 3 kIB; every sum runs over a in order, in one lane.
+constexpr int kIB = 4, kNB = 4;
 template <typename T>
 __global__ __launch_bounds__(256) void k_interp_pack(int n, int M, int Mu, int nneed,
                                                      const int* __restrict__ need,
@@ -188,53 +188,69 @@ __global__ __launch_bounds__(256) void k_interp_pack(int n, int M, int Mu, int n
                                                      Src8<T>* __restrict__ srcf) {
   const int lane = threadIdx.x & 63;
   const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
-  const int b = blockIdx.x * 64 + lane, bc = min(b, Mu - 1);
   const int q0 = (blockIdx.y * 4 + wv) * kIB;
   if (q0 >= nneed) return;  // whole waves; the kernel has no barrier
   const int jn = min(kIB, nneed - q0);
   const size_t N = (size_t)n * M;
+  int bs[kNB];
+#pragma unroll
+  for (int k = 0; k < kNB; ++k) bs[k] = min(blockIdx.x * 64 * kNB + lane + 64 * k, Mu - 1);
   size_t zo[kIB];
 #pragma unroll
   for (int jj = 0; jj < kIB; ++jj) zo[jj] = (size_t)need[q0 + min(jj, jn - 1)] * M;
-  double acc[kIB][3];
+  double acc[kIB][3][kNB];
 #pragma unroll
-  for (int jj = 0; jj < kIB; ++jj) acc[jj][0] = acc[jj][1] = acc[jj][2] = 0.0;
+  for (int jj = 0; jj < kIB; ++jj)
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+#pragma unroll
+      for (int k = 0; k < kNB; ++k) acc[jj][c][k] = 0.0;
   for (int a = 0; a < M; ++a) {
-    const double u = U[(size_t)a * Mu + bc];
+    double u[kNB];
+#pragma unroll
+    for (int k = 0; k < kNB; ++k) u[k] = U[(size_t)a * Mu + bs[k]];
 #pragma unroll
     for (int jj = 0; jj < kIB; ++jj) {
       const size_t g = zo[jj] + a;
-      acc[jj][0] += u * z[g];
-      acc[jj][1] += u * z[N + g];
-      acc[jj][2] += u * z[2 * N + g];
+      const double z0 = z[g], z1 = z[N + g], z2 = z[2 * N + g];
+#pragma unroll
+      for (int k = 0; k < kNB; ++k) {
+        acc[jj][0][k] += u[k] * z0;
+        acc[jj][1][k] += u[k] * z1;
+        acc[jj][2][k] += u[k] * z2;
+      }
     }
   }
-  if (b >= Mu) return;
 #pragma unroll
-  for (int jj = 0; jj < kIB; ++jj) {
-    if (jj >= jn) break;
-    double v[3] = {acc[jj][0], acc[jj][1], acc[jj][2]};
-    const int j = need[q0 + jj], s = sid[j];
-    const double* R = Rm + 9 * j;
-    if (z_is_body) {
-      const double b0 = R[0] * v[0] + R[1] * v[1] + R[2] * v[2];
-      const double b1 = R[3] * v[0] + R[4] * v[1] + R[5] * v[2];
-      const double b2 = R[6] * v[0] + R[7] * v[1] + R[8] * v[2];
-      v[0] = b0; v[1] = b1; v[2] = b2;
+  for (int k = 0; k < kNB; ++k) {
+    const int b = blockIdx.x * 64 * kNB + lane + 64 * k;
+    if (b >= Mu) break;
+#pragma unroll
+    for (int jj = 0; jj < kIB; ++jj) {
+      if (jj >= jn) break;
+      double v[3] = {acc[jj][0][k], acc[jj][1][k], acc[jj][2][k]};
+      const int j = need[q0 + jj], s = sid[j];
+      const double* R = Rm + 9 * j;
+      if (z_is_body) {
+        const double b0 = R[0] * v[0] + R[1] * v[1] + R[2] * v[2];
+        const double b1 = R[3] * v[0] + R[4] * v[1] + R[5] * v[2];
+        const double b2 = R[6] * v[0] + R[7] * v[1] + R[8] * v[2];
+        v[0] = b0; v[1] = b1; v[2] = b2;
+      }
+      const double* fr = fr_all + (size_t)s * 3 * Mu;
+      const double r0 = fr[b], r1 = fr[Mu + b], r2 = fr[2 * (size_t)Mu + b];
+      const double w = fw_all[(size_t)s * Mu + b];
+      Src8<T> o;
+      o.v[0] = (T)(cen[3 * j] + R[0] * r0 + R[1] * r1 + R[2] * r2);
+      o.v[1] = (T)(cen[3 * j + 1] + R[3] * r0 + R[4] * r1 + R[5] * r2);
+      o.v[2] = (T)(cen[3 * j + 2] + R[6] * r0 + R[7] * r1 + R[8] * r2);
+      o.v[3] = (T)(w * v[0]);
+      o.v[4] = (T)(w * v[1]);
+      o.v[5] = (T)(w * v[2]);
+      o.v[6] = 0;
+      o.v[7] = 0;
+      srcf[(size_t)j * Mu + b] = o;
     }
-    const double* fr = fr_all + (size_t)s * 3 * Mu;
-    const double r0 = fr[b], r1 = fr[Mu + b], r2 = fr[2 * (size_t)Mu + b];
-    const double w = fw_all[(size_t)s * Mu + b];
-    Src8<T> o;
-    o.v[0] = (T)(cen[3 * j] + R[0] * r0 + R[1] * r1 + R[2] * r2);
-    o.v[1] = (T)(cen[3 * j + 1] + R[3] * r0 + R[4] * r1 + R[5] * r2);
-    o.v[2] = (T)(cen[3 * j + 2] + R[6] * r0 + R[7] * r1 + R[8] * r2);
-    o.v[3] = (T)(w * v[0]);
-    o.v[4] = (T)(w * v[1]);
-    o.v[5] = (T)(w * v[2]);
-    o.v[6] = 0;
-    o.v[7] = 0;
-    srcf[(size_t)j * Mu + b] = o;
   }
 }
 
@@ -338,7 +354,7 @@ hipError_t launch_near_corr(int kind, int n, int M, int Mu, int kmax, int nneed,
                             hipStream_t st) {
   const int N = n * M;
   if (nitems > 0 && nneed > 0) {
-    dim3 gi((Mu + 63) / 64, (nneed + 4 * kIB - 1) / (4 * kIB));
+    dim3 gi((Mu + 64 * kNB - 1) / (64 * kNB), (nneed + 4 * kIB - 1) / (4 * kIB));
     k_interp_pack<T><<<gi, 256, 0, st>>>(n, M, Mu, nneed, need, U, z, z_is_body, sid, cen, Rm, fr, fw,
                                          reinterpret_cast<Src8<T>*>(srcf));
     hipError_t e = hipGetLastError();
